@@ -1,0 +1,493 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the property it checks and where it comes from (paper
+section/equation/table, closed form, invariant, textbook special case, or
+brute force).  None of them compares the oracle with itself.
+"""
+import json
+import math
+import os
+from math import factorial
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_07387_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def poly_cell_averages(om, f):
+    """Exact cell averages of a polynomial field using the oracle's volume
+    quadrature, whose exactness is pinned separately (test_volume_quadrature_*)."""
+    U = np.zeros((5, om.n_cell))
+    for c in range(om.n_cell):
+        x, w = om.cell_quadrature(c)
+        U[:, c] = (w[:, None] * f(x)).sum(0) / w.sum()
+    return U
+
+
+def monomials(x, order):
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    out = [np.ones_like(X)]
+    for d in range(1, order + 1):
+        for a in range(d, -1, -1):
+            for b in range(d - a, -1, -1):
+                out.append(X ** a * Y ** b * Z ** (d - a - b))
+    return np.stack(out, axis=1)
+
+
+def random_poly(order, seed, offset=(10.0, 0.0, 0.0, 0.0, 100.0)):
+    rng = np.random.default_rng(seed)
+    K = (order + 1) * (order + 2) * (order + 3) // 6
+    co = rng.normal(size=(K, 5))
+
+    def f(x):
+        return monomials(x, order) @ co + np.asarray(offset)[None, :]
+
+    return f
+
+
+def max_face_error(om, fs, f, skip_boundary=True):
+    fd = om.face_data()
+    err = 0.0
+    for fi in range(om.n_face):
+        q = fd["nq"][fi]
+        ex = f(fd["qp"][fi, :q])
+        for s in range(2):
+            if fd["cells"][fi, s] < 0 or np.isnan(fs[fi, s, 0, 0]):
+                continue
+            pts = fd["qp"][fi, :q] - (fd["shift"][fi] if s == 1 else 0.0)
+            ex = f(pts) if s == 1 else ex
+            err = max(err, float(np.abs(fs[fi, s, :q] - ex).max()))
+    return err
+
+
+# ------------------------------------------------------------------ Pi 1
+
+
+def test_benchmark_table_counts():
+    """Table 'benchmark matrix' (Sec. 4.2): reconstructed DoF per variable =
+    cells x (K(r,3)-1 + n_d x K'_dir) and face QPs = faces x QPs per face.
+    The oracle's own counts (unknowns, directional stencils per cell, QPs per
+    quadrilateral face) must reproduce the printed rows."""
+    rows = json.load(open(os.path.join(GOLDEN, "benchmark_counts.json")))["rows"]
+    # K(r, d) of eq. lsq_poly
+    assert [(r + 1) * (r + 2) * (r + 3) // 6 for r in (2, 3, 4)] == [10, 20, 35]
+    hexm = inputs.periodic_hex_mesh(6)
+    tetm = inputs.kuhn_tet_mesh((3, 3, 3), (1.0,) * 3, (True,) * 3, 0.15, seed=0)
+    got = {}
+    for r in (2, 3):
+        om = oracle.OracleMesh(hexm, order=r)
+        cen, dirs, _ = om.stencil(0)
+        got[("hex", r)] = (om.K, len(dirs), om.nq_max)
+        om = oracle.OracleMesh(tetm, order=r)
+        cen, dirs, _ = om.stencil(5)
+        got[("tet", r)] = (om.K, len(dirs), om.nq_max)
+    for row in rows:
+        r, ctype = row["order"], row["cell_type"]
+        if r == 4:
+            # P4 (next step): 34 central unknowns, quadratic directional (9), 4x4 face points
+            K, nd, kd, nq = 34, 6, 9, 16
+        else:
+            K, nd, nq = got[(ctype, r)]
+            kd = 3  # linear directional polynomials at 3rd/4th order (Sec. 2.2)
+        assert row["cells"] * (K + nd * kd) == pytest.approx(row["dof_per_var"], rel=1e-12)
+        if ctype == "hex":
+            assert row["faces"] * nq == pytest.approx(row["face_qps"], rel=1e-12)
+        else:
+            # The paper's triangle faces carry 6 points at P3; this build's
+            # tetrahedral workloads use the 3-point rule instead.
+            assert row["face_qps"] / row["faces"] == 6 and nq == 3
+
+
+# ------------------------------------------------------------------ Pi 2
+
+
+def _single_tet_mesh(P):
+    m = inputs.Mesh(xyz=np.asarray(P, np.float64), ctype=np.array([4], np.uint8),
+                    cell_ptr=np.array([0, 4], np.int64), cell_vtx=np.arange(4, dtype=np.int64),
+                    period=np.zeros(3))
+    faces = [[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]]
+    m.bface_ptr = np.array([0, 3, 6, 9, 12], np.int64)
+    m.bface_vtx = np.array(sum(faces, []), np.int64)
+    m.bface_tag = np.ones(4, np.int32)
+    return m
+
+
+def test_volume_quadrature_tet_closed_form():
+    """integral_T l1^a l2^b l3^c l4^d dV = 6|T| a!b!c!d!/(a+b+c+d+3)! (exact)."""
+    P = np.array([[0.1, 0.0, 0.2], [1.3, 0.1, 0.0], [0.2, 0.9, 0.1], [0.3, 0.2, 1.1]])
+    m = _single_tet_mesh(P)
+    om = oracle.OracleMesh(m, order=3, need=np.zeros(1, np.uint8))
+    x, w = om.cell_quadrature(0)
+    T = np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1)
+    vol = abs(np.linalg.det(T)) / 6
+    lam = np.linalg.solve(T, (x - P[0]).T).T
+    bary = np.concatenate([1 - lam.sum(1, keepdims=True), lam], axis=1)
+    for a in range(4):
+        for b in range(4 - a):
+            for c in range(4 - a - b):
+                for d in range(5 - a - b - c):  # total degree <= 4 = 2r-2 at r = 3
+                    ex = 6 * vol * factorial(a) * factorial(b) * factorial(c) * factorial(d) / factorial(a + b + c + d + 3)
+                    got = np.sum(w * bary[:, 0] ** a * bary[:, 1] ** b * bary[:, 2] ** c * bary[:, 3] ** d)
+                    assert got == pytest.approx(ex, rel=1e-13, abs=1e-16)
+
+
+def test_volume_quadrature_hex_closed_form():
+    """Unit cube: integral x^a y^b z^c = 1/((a+1)(b+1)(c+1))."""
+    m = inputs.hex_box_mesh((1, 1, 1), (1.0, 1.0, 1.0), (False, False, False))
+    om = oracle.OracleMesh(m, order=3, need=np.zeros(1, np.uint8))
+    x, w = om.cell_quadrature(0)
+    for a in range(5):
+        for b in range(5 - a):
+            for c in range(5 - a - b):
+                got = np.sum(w * x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c)
+                assert got == pytest.approx(1.0 / ((a + 1) * (b + 1) * (c + 1)), rel=1e-13)
+
+
+def test_face_quadrature_exactness():
+    """Triangle 3-point rule: exact for degree 2 (integral l1^a l2^b l3^c dA =
+    2|T| a!b!c!/(a+b+c+2)!).  Quadrilateral r x r Gauss: exact for degree
+    2r-1 per direction on the unit square.  Weights sum to one (eq. fv_update)."""
+    P = np.array([[0.1, 0.0, 0.2], [1.3, 0.1, 0.0], [0.2, 0.9, 0.1], [0.3, 0.2, 1.1]])
+    om = oracle.OracleMesh(_single_tet_mesh(P), order=2, need=np.zeros(1, np.uint8))
+    fd = om.face_data()
+    for f in range(om.n_face):
+        q = fd["nq"][f]
+        assert q == 3 and fd["qw"][f, :q].sum() == pytest.approx(1.0, rel=1e-15)
+        # recover the face's vertices: the 3 tet vertices nearest its plane
+        n = fd["nrm"][f]
+        d = np.abs((P - fd["qp"][f, :q].mean(0)) @ n)
+        V = P[np.argsort(d)[:3]]
+        A = np.stack([V[1] - V[0], V[2] - V[0]], axis=1)
+        lam = np.linalg.lstsq(A, (fd["qp"][f, :q] - V[0]).T, rcond=None)[0].T
+        bary = np.concatenate([1 - lam.sum(1, keepdims=True), lam], axis=1)
+        area = fd["area"][f]
+        assert area == pytest.approx(0.5 * np.linalg.norm(np.cross(V[1] - V[0], V[2] - V[0])), rel=1e-14)
+        for a in range(3):
+            for b in range(3 - a):
+                c = 2 - a - b
+                for cc in range(c + 1):
+                    ex = 2 * area * factorial(a) * factorial(b) * factorial(cc) / factorial(a + b + cc + 2)
+                    got = area * np.sum(fd["qw"][f, :q] * bary[:, 0] ** a * bary[:, 1] ** b * bary[:, 2] ** cc)
+                    assert got == pytest.approx(ex, rel=1e-14)
+    for r in (2, 3):
+        m = inputs.hex_box_mesh((1, 1, 1), (1.0, 1.0, 1.0), (False, False, False))
+        om = oracle.OracleMesh(m, order=r, need=np.zeros(1, np.uint8))
+        fd = om.face_data()
+        for f in range(om.n_face):
+            q = fd["nq"][f]
+            assert q == r * r
+            n = fd["nrm"][f]
+            ax = int(np.argmax(np.abs(n)))
+            u, v = [a for a in range(3) if a != ax]
+            x = fd["qp"][f, :q]
+            for a in range(2 * r):
+                for b in range(2 * r):
+                    got = np.sum(fd["qw"][f, :q] * x[:, u] ** a * x[:, v] ** b)
+                    assert got == pytest.approx(1.0 / ((a + 1) * (b + 1)), rel=1e-13)
+
+
+# ------------------------------------------------------------------ Pi 3
+
+
+def test_pseudo_inverse_matches_library_pinv():
+    """B = A^+ diag(|V_m|) (eq. lsq_system solved by QR) against numpy's SVD
+    pseudo-inverse, with A assembled here from the oracle's cell quadrature."""
+    m = inputs.kuhn_tet_mesh((4, 4, 4), (1.0,) * 3, (False,) * 3, 0.15, seed=11)
+    om = oracle.OracleMesh(m, order=3)
+    vol, cen, hb = om.cell_data()
+    for cell in (100, 200, 300):
+        ops = om.operators(cell)
+        cen_ids, dirs, _ = om.stencil(cell)
+
+        def phi(x, K):
+            xi = (x - cen[cell]) / hb[cell]
+            return monomials(xi, 3)[:, 1:K + 1] - ops["mean"][None, :K]
+
+        for ids, B, K in [(cen_ids, ops["Bc"], om.K)] + [(d, ops["Bd"][s], 3) for s, d in enumerate(dirs)]:
+            A = np.zeros((len(ids), K))
+            for j, mcell in enumerate(ids):
+                x, w = om.cell_quadrature(mcell)
+                A[j] = w @ phi(x, K)
+            Bref = np.linalg.pinv(A) @ np.diag(vol[ids])
+            cond = np.linalg.cond(A)
+            assert np.abs(B - Bref).max() <= 1e-13 * cond * np.abs(Bref).max()
+            # left inverse: B diag(1/V) A = I
+            assert np.abs(B @ np.diag(1.0 / vol[ids]) @ A - np.eye(K)).max() < 1e-12 * cond
+
+
+# ------------------------------------------------------------------ Pi 4
+
+
+@pytest.mark.parametrize("ctype,order", [("hex", 2), ("tet", 2), ("tet", 3), ("hex", 3)])
+def test_polynomial_reproduction(ctype, order):
+    """Linear (central) path reproduces polynomials of degree <= r exactly at
+    every face QP (eq. lsq_system is exact for them); full CWENOZ reproduces
+    degree <= 1 exactly (all candidates equal -> tau = 0 -> omega = lambda ->
+    the LPR blend returns p_opt, Sec. 2.2 smooth-region recovery)."""
+    need = None
+    if ctype == "hex" and order == 3:
+        # a nearest-centroid stencil of a cell on a flat wall never reaches the
+        # third layer normal to it at P3: check cells three layers inside
+        n = 8
+        m = inputs.hex_box_mesh((n, n, n), (1.0,) * 3, (False,) * 3)
+        ijk = np.stack(np.unravel_index(np.arange(n ** 3), (n, n, n)), axis=1)
+        need = np.all((ijk >= 3) & (ijk <= n - 4), axis=1).astype(np.uint8)
+    elif ctype == "hex":
+        m = inputs.hex_box_mesh((5, 5, 5), (1.0,) * 3, (False,) * 3)
+    else:
+        m = inputs.kuhn_tet_mesh((4, 4, 4), (1.0,) * 3, (False,) * 3, 0.15, seed=3)
+    om = oracle.OracleMesh(m, order=order, need=need)
+    ph = oracle.phys()
+    f = random_poly(order, seed=order)
+    U = poly_cell_averages(om, f)
+    assert need is None or om.mc_max >= 40
+    fs = om.reconstruct(U, ph, gate_mask=np.ones(om.n_cell, np.uint8))
+    scale = np.abs(U).max()
+    assert max_face_error(om, fs, f) < 1e-13 * scale * 10
+    f1 = random_poly(1, seed=7)
+    U1 = poly_cell_averages(om, f1)
+    fs1, flags, label = om.reconstruct(U1, ph, with_flags=True)
+    assert max_face_error(om, fs1, f1) < 1e-13 * np.abs(U1).max() * 10
+    assert label.max() < 1e-12  # omega == lambda for linear data
+
+
+def test_cwenoz_shifts_weight_at_discontinuity():
+    """Near a jump the nonlinear weights leave the linear weights (Sec. 2.2:
+    the indicators penalise oscillatory stencils); on smooth data they stay."""
+    m = inputs.hex_box_mesh((8, 4, 4), (1.0,) * 3, (False,) * 3)
+    om = oracle.OracleMesh(m, order=2)
+    vol, cen, _ = om.cell_data()
+    U = inputs.uniform_state(m, 1.0, [0, 0, 0], 1.0)
+    U[0] = np.where(cen[:, 0] < 0.5, 1.0, 4.0)
+    fs, flags, label = om.reconstruct(U, oracle.phys(), with_flags=True)
+    near = np.abs(cen[:, 0] - 0.5) < 0.2
+    assert label[near].min() > 0.1
+    f = random_poly(2, seed=1)
+    fs2, _, label2 = om.reconstruct(poly_cell_averages(om, f), oracle.phys(), with_flags=True)
+    assert label[near].min() > label2.max()
+
+
+# ------------------------------------------------------------------ Pi 5, Pi 6
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet"])
+def test_free_stream_preservation(kind):
+    if kind == "hex":
+        m = inputs.periodic_hex_mesh(6)
+    else:
+        m = inputs.kuhn_tet_mesh((4, 4, 4), (2 * math.pi,) * 3, (True,) * 3, 0.15, seed=5)
+    om = oracle.OracleMesh(m, order=2)
+    U = inputs.uniform_state(m, 1.3, [0.4, -0.3, 0.2], 2.0)
+    for flux in ("hllc", "rusanov"):
+        for visc in (False, True):
+            ph = oracle.phys(flux=flux, viscous=visc)
+            R = om.rhs(U, ph)
+            assert np.abs(R).max() <= 1e-13 * np.abs(U).max()
+
+
+def test_discrete_conservation_periodic():
+    """Single-valued face fluxes: sum |V_i| U_i is constant on a periodic mesh."""
+    m = inputs.kuhn_tet_mesh((3, 3, 3), (2 * math.pi,) * 3, (True,) * 3, 0.15, seed=2)
+    om = oracle.OracleMesh(m, order=2)
+    vol, _, _ = om.cell_data()
+    U0 = inputs.tgv_initial(m, noise_seed=4)
+    ph = oracle.phys(flux="hllc", viscous=True)
+    U, ke, dts = om.run(U0, ph, 0.5, 20)
+    tot0 = U0 @ vol
+    tot = U @ vol
+    assert np.all(np.abs(tot - tot0) <= 1e-13 * (np.abs(U0) @ vol))
+
+
+# ------------------------------------------------------------------ Pi 7, Pi 8
+
+
+def _rand_state(rng, gamma=1.4):
+    rho = rng.uniform(0.5, 2.0)
+    vel = rng.normal(size=3)
+    p = rng.uniform(0.5, 3.0)
+    return np.array([rho, *(rho * vel), p / (gamma - 1) + 0.5 * rho * vel @ vel])
+
+
+def _euler_flux(u, n, gamma=1.4):
+    rho, m, E = u[0], u[1:4], u[4]
+    vel = m / rho
+    p = (gamma - 1) * (E - 0.5 * rho * vel @ vel)
+    un = vel @ n
+    return np.array([rho * un, *(m * un + p * n), (E + p) * un])
+
+
+@pytest.mark.parametrize("flux", ["hllc", "rusanov"])
+def test_flux_consistency_symmetry_rotation(flux):
+    rng = np.random.default_rng(0)
+    ph = oracle.phys(flux=flux)
+    for _ in range(50):
+        u, v = _rand_state(rng), _rand_state(rng)
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        F = oracle.point_flux(ph, u, u, n)
+        assert np.allclose(F, _euler_flux(u, n), rtol=1e-14, atol=1e-14 * np.abs(F).max())
+        F1 = oracle.point_flux(ph, u, v, n)
+        F2 = oracle.point_flux(ph, v, u, -n)
+        assert np.allclose(F1, -F2, rtol=1e-13, atol=1e-13 * np.abs(F1).max())
+        # rotational invariance: F(Q u, Q v; Q n) = Q F(u, v; n)
+        Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        rot = lambda s: np.array([s[0], *(Q @ s[1:4]), s[4]])
+        F3 = oracle.point_flux(ph, rot(u), rot(v), Q @ n)
+        assert np.allclose(F3, rot(F1), rtol=1e-12, atol=1e-12 * np.abs(F1).max())
+
+
+def test_hllc_stationary_contact_flux():
+    """Toro's HLLC resolves a stationary contact exactly: mass and energy flux
+    vanish, momentum flux is p n."""
+    ph = oracle.phys(flux="hllc")
+    n = np.array([0.6, 0.0, 0.8])
+    p = 1.7
+    uL = np.array([1.0, 0, 0, 0, p / 0.4])
+    uR = np.array([3.5, 0, 0, 0, p / 0.4])
+    F = oracle.point_flux(ph, uL, uR, n)
+    assert F[0] == 0.0 and F[4] == 0.0
+    assert np.allclose(F[1:4], p * n, rtol=1e-15)
+
+
+def test_steady_contact_hllc_vs_rusanov():
+    """A density contact at rest stays steady with HLLC for 100 steps;
+    Rusanov smears it (contrast)."""
+    m = inputs.hex_box_mesh((16, 3, 3), (1.0, 0.2, 0.2), (True, True, True))
+    om = oracle.OracleMesh(m, order=2)
+    _, cen, _ = om.cell_data()
+    U0 = inputs.uniform_state(m, 1.0, [0, 0, 0], 1.0)
+    U0[0] = np.where(np.abs(cen[:, 0] - 0.5) < 0.25, 3.0, 1.0)
+    Uh, _, _ = om.run(U0, oracle.phys(flux="hllc"), 0.5, 100)
+    Ur, _, _ = om.run(U0, oracle.phys(flux="rusanov"), 0.5, 100)
+    assert np.abs(Uh - U0).max() <= 1e-12
+    assert np.abs(Ur[0] - U0[0]).max() > 1e-2
+
+
+# ------------------------------------------------------------------ Pi 9
+
+
+def _vortex_error(kind, n, order=2, t_end=0.5):
+    L = 10.0
+    if kind == "hex":
+        m = inputs.hex_box_mesh((n, n, 4), (L, L, 4 * L / n), (True, True, True))
+    else:
+        m = inputs.kuhn_tet_mesh((n, n, 3), (L, L, 3 * L / n), (True, True, True), 0.15, seed=9)
+    om = oracle.OracleMesh(m, order=order)
+    vol, _, _ = om.cell_data()
+    U0 = inputs.cell_averages(m, lambda x: inputs.isentropic_vortex(x), npt=5).T.copy()
+    ph = oracle.phys(flux="hllc", mach=1.0)
+    dt0 = om.dt(U0, ph, 0.4)
+    nsteps = int(math.ceil(t_end / dt0))
+    # fixed dt so that the final time is exactly t_end
+    U = U0.copy()
+    dt = t_end / nsteps
+    for _ in range(nsteps):
+        Un = U.copy()
+        for s in range(3):
+            R = om.rhs(U, ph)
+            om.rk_stage(s, dt, Un, R, U)
+    Uex = inputs.cell_averages(m, lambda x: inputs.isentropic_vortex(x, t=t_end), npt=5).T
+    return np.sum(vol * np.abs(U[0] - Uex[0])) / vol.sum()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind,ns,slope", [("hex", (16, 32, 64), 2.7), ("tet", (12, 24, 48), 2.5)])
+def test_isentropic_vortex_design_order(kind, ns, slope):
+    """Shu's isentropic vortex (textbook closed form): L1 density error falls at
+    the design rate of P2 (third order) under refinement."""
+    errs = [_vortex_error(kind, n) for n in ns]
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert rates[-1] >= slope, (errs, rates)
+
+
+# ------------------------------------------------------------------ Pi 11, Pi 12
+
+
+def test_green_gauss_and_viscous_flux_linear_shear():
+    """u = a y on a uniform hex box: Green-Gauss gradient exact in interior
+    cells; penalty term zero; viscous x-momentum flux mu a |S| on y-faces."""
+    a = 0.3
+    m = inputs.hex_box_mesh((6, 6, 6), (1.0,) * 3, (False,) * 3)
+    om = oracle.OracleMesh(m, order=2)
+    vol, cen, _ = om.cell_data()
+    f = lambda x: np.stack([np.ones(len(x)), a * x[:, 1], 0 * x[:, 0], 0 * x[:, 0],
+                            1.0 / 0.4 + 0.5 * (a * x[:, 1]) ** 2], axis=1)
+    U = poly_cell_averages(om, f)
+    # the cell-average kinetic energy differs from the pointwise one by a*a*h^2/24:
+    # set E from the averaged velocity so that p is uniform cell by cell
+    U[4] = 1.0 / 0.4 + 0.5 * U[1] ** 2 / U[0]
+    bcs = oracle.bc({t: (2, None) for t in range(1, 7)})
+    ph = oracle.phys(viscous=True, flux="hllc", reynolds=50.0)
+    g = om.gradients(U, ph, bcs)
+    interior = np.all((cen > 1.0 / 6) & (cen < 5.0 / 6), axis=1)
+    assert np.allclose(g[1, interior], a, rtol=1e-13)
+    assert np.abs(np.delete(g[:, interior], 1, axis=0)).max() < 1e-12
+    fs = om.reconstruct(U, ph, gate_mask=np.ones(om.n_cell, np.uint8))
+    fv = om.face_flux(fs, ph, g, bcs)
+    fi = om.face_flux(fs, oracle.phys(viscous=False, flux="hllc"), None, bcs)
+    fd = om.face_data()
+    mu = 1.0 / 50.0
+    cnt = 0
+    for k in range(om.n_face):
+        cL, cR = fd["cells"][k]
+        if cR < 0 or not (interior[cL] and interior[cR]):
+            continue
+        n = fd["nrm"][k]
+        if abs(n[1]) > 0.5:
+            visc = -(fv[k] - fi[k])  # |S| F_v . n
+            assert visc[1] == pytest.approx(mu * a * n[1] * fd["area"][k], rel=1e-6)
+            assert visc[0] == 0.0
+            cnt += 1
+    assert cnt > 10
+
+
+def test_tgv_initial_diagnostics_converge():
+    """TGV initial field (Sec. 4.2): <|u|^2/2> = 1/8, <|curl u|^2> = 3/4, so
+    eps_s(0) = 3 mu / 4 = 4.6875e-4 at Re 1600; div u = 0 (eps_d -> 0)."""
+    errs_ke, errs_es = [], []
+    for n in (8, 16, 32):
+        m = inputs.periodic_hex_mesh(n)
+        om = oracle.OracleMesh(m, order=2, need=np.zeros(m.n_cell, np.uint8))
+        U = inputs.tgv_initial(m)
+        ph = oracle.phys(viscous=True)
+        errs_ke.append(abs(om.kinetic_energy(U) - 0.125))
+        es, ed = om.dissipation(U, ph)
+        errs_es.append(abs(es - 0.75 / 1600.0))
+        assert ed < 1e-3 * es
+    assert errs_ke[-1] < 2e-3 and errs_es[-1] < 0.05 * 0.75 / 1600
+    assert errs_ke[0] / errs_ke[-1] > 12 and errs_es[0] / errs_es[-1] > 12
+
+
+# ------------------------------------------------------------------ Pi 13, Pi 14
+
+
+def test_ssp_rk3_stability_polynomial():
+    """Shu-Osher SSP-RK3 on y' = lambda y gives 1 + z + z^2/2 + z^3/6 exactly."""
+    m = inputs.periodic_hex_mesh(3)
+    om = oracle.OracleMesh(m, order=2, need=np.zeros(m.n_cell, np.uint8))
+    lam = np.linspace(-2.5, 0.5, 27 * 5).reshape(5, 27)
+    dt = 0.7
+    U0 = np.ones((5, 27))
+    U = U0.copy()
+    for s in range(3):
+        om.rk_stage(s, dt, U0, lam * U, U)
+    z = lam * dt
+    assert np.allclose(U, 1 + z + z ** 2 / 2 + z ** 3 / 6, rtol=1e-14, atol=1e-15)
+
+
+def test_normal_shock_rankine_hugoniot():
+    """Post-shock state of the shocked box satisfies the Rankine-Hugoniot jump
+    conditions in the shock frame."""
+    g = 1.4
+    rho2, u2, p2 = inputs.normal_shock_states(3.0, g)
+    S = 3.0 * math.sqrt(g)
+    E1, E2 = 1.0 / (g - 1), p2 / (g - 1) + 0.5 * rho2 * u2 * u2
+    mass = rho2 * (u2 - S) - 1.0 * (0 - S)
+    mom = (rho2 * u2 * (u2 - S) + p2) - (0 + 1.0)
+    ene = ((E2 + p2) * u2 - S * E2) - (0 - S * E1)
+    assert abs(mass) < 1e-13 and abs(mom) < 1e-13 * p2 and abs(ene) < 1e-12 * p2
+    assert rho2 == pytest.approx(27.0 / 7.0, rel=1e-15) and p2 == pytest.approx(31.0 / 3.0, rel=1e-15)
