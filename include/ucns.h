@@ -1,0 +1,248 @@
+/* libucns -- MI355X (gfx950) explicit residual evaluation of a high-order
+ * unstructured finite-volume solver for the compressible Navier-Stokes
+ * equations: least-squares CWENOZ reconstruction, Green-Gauss gradients,
+ * HLLC/Rusanov + viscous face fluxes, per-cell residual and SSP-RK3 update.
+ *
+ * The method is the one stated in Sec. 2.2 of "Towards Heterogeneous
+ * Exascale CFD with a Single Fortran Code Base" (UCNS3D v4): governing
+ * equations (eq. ns), finite-volume update (eq. fv_update), least-squares
+ * polynomial (eqs. lsq_poly, lsq_system), CWENOZ blend and weights (eqs.
+ * cwenoz_poly, cwenoz_weights), viscous interface gradient (eq.
+ * viscous_gradient_penalty), semi-discrete system (eq. semi_discrete), and the
+ * per-stage sequence of the paper's time-step algorithm (Algorithm 1).
+ *
+ * Conventions
+ *  - Every call returns an int status; UCNS_OK = 0.  Argument, shape and mesh
+ *    errors are reported synchronously; a message is kept per thread and read
+ *    with ucns_last_error().  No C++ exception crosses this interface.
+ *  - The library owns only the host-side mesh handle.  Every device buffer
+ *    (mesh arena, state, workspaces, dt, flags) is allocated by the caller and
+ *    passed as a device pointer of the current device; device pointers must be
+ *    256-byte aligned (UCNS_EINVAL otherwise).  The library never allocates
+ *    device memory.
+ *  - Compute calls are asynchronous on the caller's HIP stream; launch errors
+ *    are returned as UCNS_EHIP, faults surface at the caller's next sync.
+ *  - State U is structure-of-arrays [5][n_cell] float64, conserved variables
+ *    (rho, rho u, rho v, rho w, rho E).
+ *  - precision: UCNS_F64 (all arithmetic in FP64) or UCNS_F32 (operators,
+ *    reconstruction, gradients and fluxes in FP32 with FP32 accumulation;
+ *    state, residual and RK update stay FP64).
+ *  - Face states: [n_face][2][QMAX][5] in the precision's type, side 0 the
+ *    owner (lower cell id), side 1 the neighbour; face fluxes [n_face][5];
+ *    gradients [12][n_cell] (row 3*var + dir, var in u, v, w, T).
+ *  - A handle may be used by several threads for compute calls at once;
+ *    ucns_mesh_upload and ucns_mesh_free must not race with other calls on it.
+ */
+#ifndef UCNS_H
+#define UCNS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ucns_mesh ucns_mesh;
+typedef struct ihipStream_t* ucns_stream; /* a hipStream_t; NULL = default stream */
+
+enum {
+    UCNS_OK = 0,
+    UCNS_EINVAL = -1,  /* bad argument, size or alignment */
+    UCNS_EMESH = -2,   /* invalid mesh: non-positive volume, non-manifold or unmatched face */
+    UCNS_ERANK = -3,   /* a central stencil stays rank deficient */
+    UCNS_EHIP = -4,    /* HIP runtime error */
+    UCNS_ENOMEM = -5,  /* caller buffer too small */
+    UCNS_ESTATE = -6,  /* call out of order (e.g. compute before upload) */
+    UCNS_ENUM = -7     /* NaN/Inf or non-positive dt detected */
+};
+
+enum { UCNS_TET = 4, UCNS_PYR = 5, UCNS_PRISM = 6, UCNS_HEX = 8 };
+enum { UCNS_F64 = 0, UCNS_F32 = 1 };
+enum { UCNS_RUSANOV = 0, UCNS_HLLC = 1 };
+enum { UCNS_BC_NONE = 0, UCNS_BC_DIRICHLET = 1, UCNS_BC_TRANSMISSIVE = 2, UCNS_BC_WALL = 3 };
+
+/* Mesh description (host arrays, read during ucns_mesh_build only).
+ * Cell vertex order: VTK for tet and hex; prism: bottom triangle (0,1,2)
+ * counter-clockwise seen from the top, then (3,4,5) above it; pyramid: base
+ * (0..3) as a hex bottom, apex 4.  Periodic axes (period > 0) list one copy
+ * of each periodic vertex; a cell's coordinates are the images nearest its
+ * first vertex.  Boundary faces list their vertices in any order; tags 1..7. */
+typedef struct {
+    int64_t n_vert;
+    const double* xyz;        /* [n_vert][3] */
+    int64_t n_cell;
+    const uint8_t* type;      /* [n_cell] UCNS_TET .. UCNS_HEX */
+    const int64_t* cell_ptr;  /* [n_cell+1] */
+    const int64_t* cell_vtx;
+    double period[3];
+    int64_t n_bface;
+    const int64_t* bface_ptr; /* [n_bface+1] */
+    const int64_t* bface_vtx;
+    const int32_t* bface_tag;
+} ucns_mesh_desc;
+
+/* Reconstruction options.  order r = 2 or 3 (P2, P3); central stencil
+ * 2 K(r,3) cells; 8 cells per directional (linear) stencil; triangle faces
+ * use the 3-point rule, quadrilateral faces r x r Gauss points. */
+typedef struct {
+    int order;          /* 2 or 3 */
+    double lambda_c;    /* central linear weight before normalisation, 1000 */
+    double eps;         /* epsilon of the nonlinear weights, 1e-12 */
+    int max_layers;     /* vertex-neighbour layers searched, 3 */
+} ucns_recon_opts;
+
+/* Physics: nondimensional with rho_ref = u_ref = L = 1, p_ref = 1/(gamma M^2),
+ * T = gamma M^2 p / rho, mu = 1/Re, kappa = mu / ((gamma-1) M^2 Pr). */
+typedef struct {
+    double gamma, mach, reynolds, prandtl;
+    int viscous;        /* 0 Euler, 1 Navier-Stokes */
+    int flux;           /* UCNS_RUSANOV or UCNS_HLLC */
+} ucns_phys;
+
+/* Boundary condition per face tag 1..7 (index 0 unused). */
+typedef struct {
+    int kind[8];
+    double state[8][5]; /* conserved state for UCNS_BC_DIRICHLET */
+} ucns_bc;
+
+/* Troubled-cell gate: per-cell mask (1 = smooth: take the linear central
+ * polynomial and skip the directional stencils, smoothness indicators and
+ * nonlinear weights).  NULL gate = full CWENOZ everywhere. */
+typedef struct {
+    const uint8_t* mask;  /* device [n_cell] */
+} ucns_gate;
+
+const char* ucns_last_error(void);
+
+/* ---------------------------------------------------------------- mesh */
+
+/* Builds, on the host in FP64 and with n_threads threads (0 = hardware), the
+ * faces (periodic matching, owner = lower cell id), cell and face geometry,
+ * face quadrature, the zero-mean scaled monomial basis, the central and
+ * directional stencils and their least-squares operators B = A^+ diag(|V_m|)
+ * (eq. lsq_system solved by QR), the smoothness-indicator matrices and the
+ * basis values at each cell's face quadrature points.  Errors: UCNS_EINVAL,
+ * UCNS_EMESH, UCNS_ERANK.  *out is owned by the caller; free with
+ * ucns_mesh_free. */
+int ucns_mesh_build(const ucns_mesh_desc* desc, const ucns_recon_opts* opts, int n_threads, ucns_mesh** out);
+void ucns_mesh_free(ucns_mesh* mesh);
+
+/* info[0..15]: n_cell, n_face, K (unknowns), QMAX (points per face slot),
+ * max faces per cell, padded central stencil, max directional stencils per
+ * cell, padded directional stencil, n_boundary_faces, dropped directional
+ * stencils, min central stencil size, max central stencil size, order,
+ * 0, 0, 0. */
+int ucns_mesh_info(const ucns_mesh* mesh, int64_t* info);
+
+/* Bytes of the device arena holding all mesh arrays for one precision. */
+int ucns_mesh_arena_bytes(const ucns_mesh* mesh, int precision, size_t* bytes);
+
+/* Copies the packed mesh arrays of one precision into the caller's device
+ * arena (256-byte aligned, at least ucns_mesh_arena_bytes) on stream; the
+ * handle keeps the pointer.  The arena must outlive every later compute call
+ * with that precision. */
+int ucns_mesh_upload(ucns_mesh* mesh, int precision, void* arena, size_t bytes, ucns_stream stream);
+
+/* Host-side inspection (for verification): cell-to-face table
+ * c2f[c*6+lf] = 2*face + side (-1 unused); face cells [n_face][2] (-1 - tag
+ * on a boundary side); face quadrature points [n_face][QMAX][3] in the
+ * owner's frame; face shift [n_face][3] (neighbour frame = owner frame -
+ * shift); stencils and FP64 operators of one cell in the same row-major
+ * layout as the returned counts. */
+int ucns_mesh_faces(const ucns_mesh* mesh, int32_t* c2f, int64_t* fcell, double* qp, double* shift);
+int ucns_mesh_cell_geometry(const ucns_mesh* mesh, double* vol, double* cen, double* hbasis);
+int ucns_mesh_stencil(const ucns_mesh* mesh, int64_t cell, int64_t* central, int32_t* ncen, int64_t* dir,
+                      int32_t* ndir, int32_t* dface);
+int ucns_mesh_operators(const ucns_mesh* mesh, int64_t cell, double* Bc, double* Bd, double* O, double* Phi);
+
+/* --------------------------------------------------------- workspaces */
+
+/* Element counts of the caller-owned workspaces: face_state, face_flux,
+ * gradW (in the precision's type) and the reduction scratch (float64). */
+int ucns_workspace_elems(const ucns_mesh* mesh, int64_t* face_state, int64_t* face_flux, int64_t* gradW,
+                         int64_t* reduce_scratch);
+
+/* ------------------------------------------------------------- compute */
+
+/* Time step (reading of the paper's compute_time_step, Listing 1):
+ * dt = cfl * min_i h_i / (|u_i| + c_i), h_i = 6|V_i| / sum_f |S_f|; with
+ * viscosity also dt <= cfl * min_i rho_i h_i^2 / (2 mu max(4/3, gamma/Pr)).
+ * Deterministic two-pass minimum; writes *dt_dev (device scalar). */
+int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, double cfl, double* reduce_scratch,
+            double* dt_dev, ucns_stream stream);
+
+/* Reconstruction (Sec. 2.2, eqs. lsq_system, cwenoz_poly, cwenoz_weights):
+ * per cell and conserved variable, central and directional least-squares
+ * coefficients from stencil jumps, smoothness indicators, WENO-Z nonlinear
+ * weights, blend, and the polynomial values at the cell's face quadrature
+ * points written to face_state.  Positivity of density and pressure at every
+ * point is enforced with the fallback gated-linear -> full CWENOZ -> first
+ * order; flags[c] (device, may be NULL) records bit0 linear taken, bit1
+ * CWENOZ fallback, bit2 first-order fallback.  label (device float [n_cell],
+ * may be NULL) receives max over variables and stencils of |omega - lambda|. */
+int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
+                     const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream);
+
+/* Green-Gauss gradients of W = (u, v, w, T) from cell averages (face value
+ * the mean of the two cells; ghost states on boundaries).  gradW [12][n_cell]. */
+int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const double* U,
+                   int precision, void* gradW, ucns_stream stream);
+
+/* Face fluxes (Sec. 2.2, eq. fv_update and eq. viscous_gradient_penalty with
+ * alpha = 4/3): F_f = |S_f| sum_q w_q (F_c(U_L, U_R; n) - F_v), HLLC or
+ * Rusanov convective flux; the Gauss-point sum is a cross-lane reduction.
+ * gradW may be NULL for Euler.  face_flux [n_face][5]. */
+int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const void* face_state,
+                   const void* gradW, int precision, void* face_flux, ucns_stream stream);
+
+/* Residual R_i = -(1/|V_i|) sum_f s_if F_f (eq. fv_update), a per-cell gather
+ * over the cell's faces in fixed local order (no atomics).  R [5][n_cell]. */
+int ucns_residual(const ucns_mesh* mesh, const void* face_flux, int precision, double* R, ucns_stream stream);
+
+/* SSP-RK3 stage s (Shu-Osher): U <- a_s U0 + b_s (U + dt R) with
+ * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3); dt read from the device scalar.
+ * Stage 0 also stores the incoming U (the step's U^n) into U0, which stages 1
+ * and 2 then read. */
+int ucns_rk_stage(const ucns_mesh* mesh, int stage, const double* dt_dev, double* U0, const double* R,
+                  double* U, ucns_stream stream);
+
+/* ucns_residual followed by ucns_rk_stage in one pass (R is not stored);
+ * same U0 convention as ucns_rk_stage. */
+int ucns_residual_rk_stage(const ucns_mesh* mesh, const void* face_flux, int precision, int stage,
+                           const double* dt_dev, double* U0, double* U, ucns_stream stream);
+
+/* Kinetic energy sum |V| |m|^2 / (2 rho) / sum |V| (deterministic two-pass
+ * sum in a fixed order); writes *ke_dev. */
+int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* reduce_scratch, double* ke_dev,
+                 ucns_stream stream);
+
+/* ---------------------------------------------------------------- gate */
+
+/* Twelve gate features per cell from cell averages (row-major [n_cell][12],
+ * float32): for v in (rho, rho E): log(1e-12 + x) of the max and mean
+ * normalised central-stencil jump, the normalised central-polynomial
+ * gradient, and the max/mean/min face-neighbour deviation from the linear
+ * prediction. */
+int ucns_gate_features(const ucns_mesh* mesh, const double* U, float* features, ucns_stream stream);
+
+/* MLP 12 -> 64 -> 64 -> 1 (ReLU, sigmoid output) on BF16 matrix cores with
+ * FP32 accumulation.  params (device float32, packed): mu[12], sigma[12],
+ * W1[64][16] (input padded to 16), b1[64], W2[64][64], b2[64], w3[64], b3[1],
+ * theta[1].  ucns_gate_mask writes mask[c] = (sigmoid(z) < theta) for the
+ * standardised features. */
+int ucns_mlp_forward(const float* params, const float* features, int64_t n, float* prob, ucns_stream stream);
+int ucns_gate_mask(const float* params, const float* features, int64_t n, uint8_t* mask, ucns_stream stream);
+
+/* One training step of the MLP on a batch: forward, class-weighted binary
+ * cross-entropy, backward (BF16 matrix-core products, FP32 accumulation) and
+ * Adam (FP32 master weights).  grads (device float32, same packing as the
+ * weights) receives the batch gradient; loss_dev the mean loss.  adam_state:
+ * m and v (2 x n_params floats) and step counter handled by the caller via t. */
+int ucns_mlp_train_step(float* params, float* grads, float* adam_state, const float* features,
+                        const float* labels, int64_t n, float pos_weight, float lr, int t, float* loss_dev,
+                        ucns_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

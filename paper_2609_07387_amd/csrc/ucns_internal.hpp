@@ -1,0 +1,82 @@
+// Internal host-side structures of libucns (not part of the C ABI).
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ucns.h"
+
+namespace ucns {
+
+constexpr int kMaxFaces = 6;     // faces per cell
+constexpr int kMaxQ = 9;         // quadrature points per face (3x3 at P3)
+constexpr int kMaxK = 19;        // unknowns at P3
+constexpr int kMaxCentral = 64;  // central stencil cap
+constexpr int kMaxDir = 16;      // directional stencil cap
+constexpr int kDirTarget = 8;    // directional stencil size before closure
+constexpr int kDirMin = 4;       // fewer candidates drop the sector
+constexpr int kNumVar = 5;
+
+void set_error(const std::string& msg);
+
+// Offsets (bytes) of every array inside one precision's device arena.
+struct Arena {
+    size_t bytes = 0;
+    size_t sten_c = 0, Bc = 0, ndir = 0, sten_d = 0, Bd = 0, O = 0, Phi = 0, c2f = 0;
+    size_t vol = 0, hdt = 0, fcell = 0, fnrm = 0, farea = 0, fw = 0, fdc = 0, fnq = 0, nbr = 0;
+    void* dev = nullptr;  // caller-owned device pointer after upload
+};
+
+struct Mesh {
+    // ---- input
+    int64_t nv = 0, nc = 0;
+    std::vector<double> xyz;
+    std::vector<uint8_t> type;
+    std::vector<int64_t> cptr, cvtx;
+    double period[3] = {0, 0, 0};
+    // ---- options
+    int order = 2, K = 9, qmax = 4, nfmax = 6, max_layers = 3;
+    double lambda_c = 1000.0, eps = 1e-12;
+    // ---- faces (numbered by owner cell, then owner-local face)
+    int64_t nf = 0, nbnd = 0;
+    std::vector<int64_t> fcell;   // [nf][2]; side 1 = -1 - tag on the boundary
+    std::vector<int> flf;         // [nf][2] local face indices
+    std::vector<int> fnq;         // points per face
+    std::vector<double> farea, fnrm, fqp, fqw, fshift, fcen, fdc;  // fdc: owner->neighbour centroid offset
+    std::vector<int32_t> c2f;     // [nc][kMaxFaces] = 2 f + side, -1 unused
+    // ---- cells
+    std::vector<double> vol, cen, hb, hdt;
+    std::vector<double> moments;  // [nc][nmom] central moments
+    int mom_deg = 0, nmom = 0;
+    // ---- stencils
+    std::vector<int> ncen, navail;
+    std::vector<int64_t> cand;    // [nc][kMaxCentral] sorted candidates
+    std::vector<double> cdist;    // [nc][kMaxCentral]
+    std::vector<int> ndir, ndropped;
+    std::vector<int> nds, dface;  // [nc][kMaxFaces]
+    std::vector<int64_t> dir;     // [nc][kMaxFaces][kMaxDir]
+    int mc_pad = 0, md_pad = 0, nd_max = 0, mc_min = 0;
+    // ---- operators (FP64, cell-major, for packing and inspection)
+    std::vector<double> Bc;       // [nc][K][mc_pad]
+    std::vector<double> Bd;       // [nc][nd_max][3][md_pad]
+    std::vector<double> O;        // [nc][K][K]
+    std::vector<double> Phi;      // [nc][nfmax][qmax][K]
+    std::vector<double> mean;     // [nc][K]
+    // ---- device arenas
+    Arena arena[2];
+    int64_t n_dropped_total = 0;
+};
+
+int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads, Mesh** out);
+// Packs the arrays of one precision into a host image of the device arena.
+int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char>* image);
+
+int cell_nfaces(int type);
+const int* face_verts(int type, int lf, int* nv);
+
+}  // namespace ucns
+
+struct ucns_mesh {
+    ucns::Mesh* m;
+};

@@ -1,0 +1,1006 @@
+// libucns device path for gfx950 (CDNA4): reconstruction, gradients, face
+// fluxes, residual gather, SSP-RK3 stage, time step and diagnostics, plus the
+// C-ABI entry points (declared in include/ucns.h).
+//
+// Method: Sec. 2.2 of the UCNS3D v4 paper (eqs. lsq_system, cwenoz_poly,
+// cwenoz_weights, viscous_gradient_penalty, fv_update) with the per-stage
+// order of its time-step algorithm (Algorithm 1).
+//
+// Layout: per-cell operators are cell-fastest ([entry][n_cell]) so that one
+// thread per cell streams them coalesced; face arrays are face-major.  The
+// residual is a per-cell gather of single-valued face fluxes (no atomics),
+// and the two reductions (dt, kinetic energy) use a fixed block count and a
+// fixed tree, so every result is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ucns_internal.hpp"
+
+namespace ucns {
+const char* last_error_cstr();
+}
+
+using namespace ucns;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
+
+template <class T>
+struct PhysT {
+    T gamma, gm1, gM2, mu, kappa, pr;  // gM2 = gamma M^2
+    int viscous, flux;
+};
+
+template <class T>
+struct BcT {
+    int kind[8];
+    T state[8][5];
+};
+
+template <class T>
+PhysT<T> make_phys(const ucns_phys* p) {
+    PhysT<T> o;
+    o.gamma = T(p->gamma);
+    o.gm1 = T(p->gamma - 1.0);
+    o.gM2 = T(p->gamma * p->mach * p->mach);
+    double mu = p->reynolds > 0 ? 1.0 / p->reynolds : 0.0;
+    o.mu = T(mu);
+    o.kappa = T(p->viscous ? mu / ((p->gamma - 1.0) * p->mach * p->mach * p->prandtl) : 0.0);
+    o.pr = T(p->prandtl);
+    o.viscous = p->viscous;
+    o.flux = p->flux;
+    return o;
+}
+
+template <class T>
+BcT<T> make_bc(const ucns_bc* b) {
+    BcT<T> o;
+    for (int t = 0; t < 8; ++t) {
+        o.kind[t] = b ? b->kind[t] : UCNS_BC_TRANSMISSIVE;
+        for (int v = 0; v < 5; ++v) o.state[t][v] = b ? T(b->state[t][v]) : T(0);
+    }
+    return o;
+}
+
+// ------------------------------------------------------------ reconstruction
+
+template <class T>
+struct ReconArgs {
+    const double* U;
+    int64_t nc;
+    const int32_t* sten_c;
+    const T* Bc;
+    int MC;
+    const uint8_t* ndir;
+    const int32_t* sten_d;
+    const T* Bd;
+    int MD;
+    const T* O;
+    const T* Phi;
+    const int32_t* c2f;
+    const uint8_t* fnq;
+    int Q, NF;
+    const uint8_t* gate;
+    T* fs;
+    uint8_t* flags;
+    float* label;
+    T lam_c, eps, gm1;
+};
+
+__device__ __forceinline__ int tri_index(int K, int k, int l) { return k * K - (k * (k - 1)) / 2 + (l - k); }
+
+// One thread per cell, all five conserved variables.
+//  (i)   stencil jumps b_m = U_m - U_i in FP64, then rounded to T
+//  (ii)  a_opt = B_c b (central, eq. lsq_system)
+//  (iii) a_s = B_s b_s per directional stencil (linear)
+//  (iv)  SI_1 = a_opt^T O a_opt, SI_s = a_s^T O_lin a_s
+//  (v)   tau = mean |SI_1 - SI_s|, w~ = lambda (1 + tau/(eps + SI)) (eq. cwenoz_weights)
+//  (vi)  Levy-Puppo-Russo blend (eq. cwenoz_poly), accumulated in one pass:
+//        abar = s1 a_opt + (tau/W) G on the linear modes, with
+//        s1 = (1 + tau/(eps+SI_1))/W, W = 1 + tau sum_s lambda_s/(eps+SI_s),
+//        G = sum_{s>=2} lambda_s (1/(eps+SI_s) - 1/(eps+SI_1)) a_s
+//  (vii) point values U_i + Phi_q . abar at the cell's face points, with the
+//        positivity fallback linear -> CWENOZ -> first order.
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= A.nc) return;
+    const int64_t nc = A.nc;
+    double ui[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ui[v] = A.U[v * nc + c];
+
+    T a[K][5];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) a[k][v] = T(0);
+    for (int m = 0; m < A.MC; ++m) {
+        const int64_t j = A.sten_c[m * nc + c];
+        T b[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b[v] = T(A.U[v * nc + j] - ui[v]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T w = A.Bc[(int64_t(k) * A.MC + m) * nc + c];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) a[k][v] += w * b[v];
+        }
+    }
+
+    int mode = (A.gate && A.gate[c]) ? 0 : 1;  // 0 linear, 1 CWENOZ, 2 first order
+    uint8_t fl = mode == 0 ? 1 : 0;
+    float lab = 0.f;
+    while (true) {
+        T s1[5], g[3][5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            s1[v] = mode == 2 ? T(0) : T(1);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) g[k][v] = T(0);
+        }
+        const int nd = A.ndir[c];
+        if (mode == 1 && nd > 0) {
+            const T lam_s = T(1) / (A.lam_c + T(nd));
+            const T lam_1 = A.lam_c * lam_s;
+            T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                T s = T(0);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    T t = T(0);
+#pragma unroll
+                    for (int l = k + 1; l < K; ++l) t += A.O[int64_t(tri_index(K, k, l)) * nc + c] * a[l][v];
+                    s += a[k][v] * (A.O[int64_t(tri_index(K, k, k)) * nc + c] * a[k][v] + T(2) * t);
+                }
+                SI1[v] = s;
+                inv1[v] = T(1) / (A.eps + s);
+                tsum[v] = T(0);
+                Lam[v] = lam_1 * inv1[v];
+                rmin[v] = inv1[v];
+                rmax[v] = inv1[v];
+            }
+            const T o00 = A.O[0 * nc + c], o01 = A.O[1 * nc + c], o02 = A.O[2 * nc + c];
+            const T o11 = A.O[int64_t(K) * nc + c], o12 = A.O[int64_t(K + 1) * nc + c];
+            const T o22 = A.O[int64_t(2 * K - 1) * nc + c];
+            for (int s = 0; s < nd; ++s) {
+                T as[3][5];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+                for (int m = 0; m < A.MD; ++m) {
+                    const int64_t j = A.sten_d[(int64_t(s) * A.MD + m) * nc + c];
+                    T b[5];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) b[v] = T(A.U[v * nc + j] - ui[v]);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const T w = A.Bd[((int64_t(s) * 3 + k) * A.MD + m) * nc + c];
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) as[k][v] += w * b[v];
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    const T x = as[0][v], y = as[1][v], z = as[2][v];
+                    const T SIs = x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z;
+                    tsum[v] += fabs(SI1[v] - SIs);
+                    const T r = T(1) / (A.eps + SIs);
+                    Lam[v] += lam_s * r;
+                    rmin[v] = fmin(rmin[v], r);
+                    rmax[v] = fmax(rmax[v], r);
+                    const T coef = lam_s * (r - inv1[v]);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) g[k][v] += coef * as[k][v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T tau = tsum[v] / T(nd);
+                const T W = T(1) + tau * Lam[v];
+                s1[v] = (T(1) + tau * inv1[v]) / W;
+                const T tw = tau / W;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) g[k][v] *= tw;
+                if (A.label) {
+                    // |omega_s - lambda_s| = lambda_s |(1 + tau r_s)/W - 1|: extreme at rmin or rmax
+                    float d1 = float(fabs(lam_1 * (s1[v] - T(1))));
+                    float d2 = float(fabs(lam_s * ((T(1) + tau * rmin[v]) / W - T(1))));
+                    float d3 = float(fabs(lam_s * ((T(1) + tau * rmax[v]) / W - T(1))));
+                    lab = fmaxf(lab, fmaxf(d1, fmaxf(d2, d3)));
+                }
+            }
+        }
+        // point values at the cell's face quadrature points
+        bool ok = true;
+        for (int lf = 0; lf < A.NF; ++lf) {
+            const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
+            if (f2 < 0) continue;
+            const int64_t f = f2 >> 1;
+            const int side = f2 & 1;
+            const int nq = A.fnq[f];
+            for (int q = 0; q < nq; ++q) {
+                T d[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) d[v] = T(0);
+                if (mode != 2) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const T phi = A.Phi[((int64_t(lf) * A.Q + q) * K + k) * nc + c];
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) {
+                            const T coef = k < 3 ? s1[v] * a[k][v] + g[k < 3 ? k : 0][v] : s1[v] * a[k][v];
+                            d[v] += phi * coef;
+                        }
+                    }
+                }
+                T val[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
+                const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+                ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
+                T* out = A.fs + ((f * 2 + side) * A.Q + q) * 5;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) out[v] = val[v];
+            }
+        }
+        if (ok || mode == 2) break;
+        fl |= mode == 0 ? 2 : 4;
+        ++mode;
+    }
+    if (A.flags) A.flags[c] = fl;
+    if (A.label) A.label[c] = lab;
+}
+
+// ------------------------------------------------------------------ physics
+
+template <class T>
+__device__ __forceinline__ T pressure(const PhysT<T>& P, const T* u) {
+    return P.gm1 * (u[4] - T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0]);
+}
+
+template <class T>
+__device__ __forceinline__ void euler_flux(const PhysT<T>& P, const T* u, const T* n, T p, T* F) {
+    const T un = (u[1] * n[0] + u[2] * n[1] + u[3] * n[2]) / u[0];
+    F[0] = u[0] * un;
+    F[1] = u[1] * un + p * n[0];
+    F[2] = u[2] * un + p * n[1];
+    F[3] = u[3] * un + p * n[2];
+    F[4] = (u[4] + p) * un;
+}
+
+// Rusanov: s = max(|u_nL| + c_L, |u_nR| + c_R).
+template <class T>
+__device__ void rusanov_flux(const PhysT<T>& P, const T* L, const T* R, const T* n, T* F) {
+    const T pL = pressure(P, L), pR = pressure(P, R);
+    T FL[5], FR[5];
+    euler_flux(P, L, n, pL, FL);
+    euler_flux(P, R, n, pR, FR);
+    const T unL = (L[1] * n[0] + L[2] * n[1] + L[3] * n[2]) / L[0];
+    const T unR = (R[1] * n[0] + R[2] * n[1] + R[3] * n[2]) / R[0];
+    const T s = fmax(fabs(unL) + sqrt(P.gamma * pL / L[0]), fabs(unR) + sqrt(P.gamma * pR / R[0]));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (R[v] - L[v]);
+}
+
+// HLLC (Toro, Spruce & Speares) with Davis wave speeds; S* >= 0 takes the
+// left star state.
+template <class T>
+__device__ void hllc_flux(const PhysT<T>& P, const T* L, const T* R, const T* n, T* F) {
+    const T rL = L[0], rR = R[0];
+    const T unL = (L[1] * n[0] + L[2] * n[1] + L[3] * n[2]) / rL;
+    const T unR = (R[1] * n[0] + R[2] * n[1] + R[3] * n[2]) / rR;
+    const T pL = pressure(P, L), pR = pressure(P, R);
+    const T cL = sqrt(P.gamma * pL / rL), cR = sqrt(P.gamma * pR / rR);
+    const T SL = fmin(unL - cL, unR - cR), SR = fmax(unL + cL, unR + cR);
+    if (SL >= T(0)) {
+        euler_flux(P, L, n, pL, F);
+        return;
+    }
+    if (SR <= T(0)) {
+        euler_flux(P, R, n, pR, F);
+        return;
+    }
+    const T Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR));
+    const bool left = Ss >= T(0);
+    const T* Kst = left ? L : R;
+    const T SK = left ? SL : SR, unK = left ? unL : unR, pK = left ? pL : pR;
+    euler_flux(P, Kst, n, pK, F);
+    const T chi = (SK - unK) / (SK - Ss);
+    const T rho = Kst[0];
+    T Us[5];
+    Us[0] = rho * chi;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Us[1 + a] = rho * chi * (Kst[1 + a] / rho + (Ss - unK) * n[a]);
+    Us[4] = rho * chi * (Kst[4] / rho + (Ss - unK) * (Ss + pK / (rho * (SK - unK))));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] += SK * (Us[v] - Kst[v]);
+}
+
+template <class T>
+__device__ __forceinline__ void prim_W(const PhysT<T>& P, const T* u, T* W) {
+    const T ir = T(1) / u[0];
+    W[0] = u[1] * ir;
+    W[1] = u[2] * ir;
+    W[2] = u[3] * ir;
+    W[3] = P.gM2 * pressure(P, u) * ir;
+}
+
+template <class T>
+__device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, T* out) {
+    const int kind = B.kind[tag];
+    if (kind == UCNS_BC_DIRICHLET) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v] = B.state[tag][v];
+    } else if (kind == UCNS_BC_WALL) {
+        out[0] = in[0];
+        out[1] = -in[1];
+        out[2] = -in[2];
+        out[3] = -in[3];
+        out[4] = in[4];
+    } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v] = in[v];
+    }
+}
+
+// ---------------------------------------------------------------- gradients
+
+template <class T>
+struct GradArgs {
+    const double* U;
+    int64_t nc;
+    const int32_t* c2f;
+    int NF;
+    const int32_t* fcell;
+    const T* fnrm;
+    const T* farea;
+    const double* vol;
+    T* gradW;
+};
+
+// Green-Gauss: grad W_i = (1/|V_i|) sum_f (W_i + W_j)/2 n_f |S_f| (outward).
+template <class T>
+__global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<T> P, BcT<T> B) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= A.nc) return;
+    const int64_t nc = A.nc;
+    T ui[5], Wi[4], g[12];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ui[v] = T(A.U[v * nc + c]);
+    prim_W(P, ui, Wi);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) g[k] = T(0);
+    for (int lf = 0; lf < A.NF; ++lf) {
+        const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
+        if (f2 < 0) continue;
+        const int64_t f = f2 >> 1;
+        const int side = f2 & 1;
+        const int32_t other = A.fcell[2 * f + (1 - side)];
+        T uo[5], Wo[4];
+        if (other >= 0) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) uo[v] = T(A.U[v * nc + other]);
+        } else {
+            ghost(B, -1 - other, ui, uo);
+        }
+        prim_W(P, uo, Wo);
+        const T s = (side ? T(-0.5) : T(0.5)) * A.farea[f];
+#pragma unroll
+        for (int var = 0; var < 4; ++var) {
+            const T wf = (Wi[var] + Wo[var]) * s;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g[3 * var + a] += wf * A.fnrm[3 * f + a];
+        }
+    }
+    const T iv = T(1.0 / A.vol[c]);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) A.gradW[k * nc + c] = g[k] * iv;
+}
+
+// ---------------------------------------------------------------- face flux
+
+template <class T>
+struct FluxArgs {
+    const T* fs;
+    int64_t nf, nc;
+    int Q;
+    const int32_t* fcell;
+    const T* fnrm;
+    const T* farea;
+    const T* fw;
+    const T* fdc;
+    const uint8_t* fnq;
+    const T* gradW;
+    T* ff;
+};
+
+// Viscous flux F_v . n with the penalised interface gradient
+// grad W_f = (grad W_L + grad W_R)/2 + (4/3)/L_int (W_R - W_L) (x) n.
+template <class T>
+__device__ void viscous_flux(const PhysT<T>& P, const T* uL, const T* uR, const T* gL, const T* gR, const T* n,
+                             T Lint, T* Fv) {
+    T WL[4], WR[4], G[4][3];
+    prim_W(P, uL, WL);
+    prim_W(P, uR, WR);
+    const T pen = T(4.0 / 3.0) / Lint;
+#pragma unroll
+    for (int var = 0; var < 4; ++var)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            G[var][a] = T(0.5) * (gL[3 * var + a] + gR[3 * var + a]) + pen * (WR[var] - WL[var]) * n[a];
+    const T div = G[0][0] + G[1][1] + G[2][2];
+    T e = T(0);
+    Fv[0] = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T t = T(0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) t += (G[i][j] + G[j][i] - (i == j ? T(2.0 / 3.0) * div : T(0))) * n[j];
+        t *= P.mu;
+        Fv[1 + i] = t;
+        e += T(0.5) * (WL[i] + WR[i]) * t;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) e += P.kappa * G[3][j] * n[j];
+    Fv[4] = e;
+}
+
+// QG lanes per face (QG >= points per face, power of two); the Gauss-point
+// sum is a butterfly over the group's lanes.
+template <class T, int QG>
+__global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<T> P, BcT<T> B) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t f = tid / QG;
+    const int q = int(tid % QG);
+    if (f >= A.nf) return;  // whole groups leave together
+    T F[5] = {T(0), T(0), T(0), T(0), T(0)};
+    const int nq = A.fnq[f];
+    if (q < nq) {
+        const T n[3] = {A.fnrm[3 * f], A.fnrm[3 * f + 1], A.fnrm[3 * f + 2]};
+        const int32_t cR = A.fcell[2 * f + 1];
+        T uL[5], uR[5];
+        const T* pL = A.fs + ((f * 2) * A.Q + q) * 5;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) uL[v] = pL[v];
+        if (cR >= 0) {
+            const T* pR = A.fs + ((f * 2 + 1) * A.Q + q) * 5;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) uR[v] = pR[v];
+        } else {
+            ghost(B, -1 - cR, uL, uR);
+        }
+        if (P.flux == UCNS_HLLC)
+            hllc_flux(P, uL, uR, n, F);
+        else
+            rusanov_flux(P, uL, uR, n, F);
+        if (P.viscous) {
+            const int32_t cL = A.fcell[2 * f];
+            T gL[12], gR[12], Fv[5];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                gL[k] = A.gradW[k * A.nc + cL];
+                gR[k] = cR >= 0 ? A.gradW[k * A.nc + cR] : gL[k];
+            }
+            const T dx = A.fdc[3 * f], dy = A.fdc[3 * f + 1], dz = A.fdc[3 * f + 2];
+            viscous_flux(P, uL, uR, gL, gR, n, sqrt(dx * dx + dy * dy + dz * dz), Fv);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) F[v] -= Fv[v];
+        }
+        const T w = A.fw[f * A.Q + q];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] *= w;
+    }
+#pragma unroll
+    for (int off = QG / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] += __shfl_xor(F[v], off, QG);
+    if (q == 0) {
+        const T ar = A.farea[f];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.ff[f * 5 + v] = ar * F[v];
+    }
+}
+
+// ----------------------------------------------------- residual + RK stage
+
+template <class T>
+struct ResArgs {
+    const T* ff;
+    int64_t nc;
+    const int32_t* c2f;
+    int NF;
+    const double* vol;
+    double* R;   // residual output (residual only)
+    double* U0;  // RK: written at stage 0, read at stages 1 and 2
+    double* U;
+    const double* dt;
+    double a, b;
+    int stage;
+};
+
+// R_i = -(1/|V_i|) sum_f s_if F_f over the cell's faces in local order.
+template <class T, bool RK>
+__global__ __launch_bounds__(kBlock) void residual_kernel(ResArgs<T> A) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= A.nc) return;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int lf = 0; lf < A.NF; ++lf) {
+        const int32_t f2 = A.c2f[int64_t(lf) * A.nc + c];
+        if (f2 < 0) continue;
+        const int64_t f = f2 >> 1;
+        const double s = (f2 & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] += s * double(A.ff[f * 5 + v]);
+    }
+    const double iv = -1.0 / A.vol[c];
+    if (RK) {
+        const double dt = *A.dt;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const int64_t i = v * A.nc + c;
+            const double u = A.U[i];
+            if (A.stage == 0) {
+                A.U0[i] = u;
+                A.U[i] = u + dt * (acc[v] * iv);
+            } else {
+                A.U[i] = A.a * A.U0[i] + A.b * (u + dt * (acc[v] * iv));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) A.R[v * A.nc + c] = acc[v] * iv;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void rk_stage_kernel(int64_t n, double* U0, const double* R, double* U,
+                                                          const double* dt, double a, double b, int stage) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double u = U[i];
+    if (stage == 0) {
+        U0[i] = u;
+        U[i] = u + *dt * R[i];
+    } else {
+        U[i] = a * U0[i] + b * (u + *dt * R[i]);
+    }
+}
+
+// ----------------------------------------------------------------- reductions
+
+// Fixed-shape block reduction (deterministic for a fixed launch shape).
+template <bool MIN>
+__device__ double block_reduce(double x) {
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = MIN ? fmin(sh[threadIdx.x], sh[threadIdx.x + s]) : sh[threadIdx.x] + sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void dt_partial_kernel(int64_t nc, const double* U, const double* hdt,
+                                                            PhysT<double> P, double* part) {
+    double best = INFINITY;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < nc; c += int64_t(gridDim.x) * blockDim.x) {
+        double u[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u[v] = U[v * nc + c];
+        const double sp = sqrt(u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+        const double cs = sqrt(P.gamma * pressure(P, u) / u[0]);
+        const double h = hdt[c];
+        double t = h / (sp + cs);
+        if (P.viscous) t = fmin(t, u[0] * h * h / (2.0 * P.mu * fmax(4.0 / 3.0, P.gamma / P.pr)));
+        if (!(t > 0.0)) t = -INFINITY;  // NaN or non-positive: poisons the minimum
+        best = fmin(best, t);
+    }
+    const double r = block_reduce<true>(best);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void dt_final_kernel(int nb, const double* part, double cfl, double* dt) {
+    double best = INFINITY;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) best = fmin(best, part[i]);
+    const double r = block_reduce<true>(best);
+    if (threadIdx.x == 0) *dt = (r > 0.0 && r < INFINITY) ? cfl * r : NAN;
+}
+
+__global__ __launch_bounds__(kBlock) void ke_partial_kernel(int64_t nc, const double* U, const double* vol, double* part) {
+    double s = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < nc; c += int64_t(gridDim.x) * blockDim.x) {
+        const double r = U[c], mx = U[nc + c], my = U[2 * nc + c], mz = U[3 * nc + c];
+        s += vol[c] * 0.5 * (mx * mx + my * my + mz * mz) / r;
+    }
+    const double t = block_reduce<false>(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void ke_final_kernel(int nb, const double* part, double inv_vol, double* out) {
+    // fixed order: each thread sums a strided slice, then a fixed tree
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+    const double t = block_reduce<false>(s);
+    if (threadIdx.x == 0) *out = t * inv_vol;
+}
+
+// ----------------------------------------------------------------- helpers
+
+inline unsigned grid_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+int hip_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return UCNS_EHIP;
+    }
+    return UCNS_OK;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
+
+#define UCNS_REQUIRE(cond, code, msg) \
+    do {                              \
+        if (!(cond)) {                \
+            set_error(msg);           \
+            return code;              \
+        }                             \
+    } while (0)
+
+template <class T>
+const T* arena_ptr(const Arena& a, size_t off) {
+    return reinterpret_cast<const T*>(static_cast<const unsigned char*>(a.dev) + off);
+}
+
+template <class T, int K>
+int launch_recon_k(const Mesh& m, const Arena& ar, double gm1, const double* U, const uint8_t* gate, void* fs,
+                   uint8_t* flags, float* label, hipStream_t st) {
+    ReconArgs<T> A;
+    A.U = U;
+    A.nc = m.nc;
+    A.sten_c = arena_ptr<int32_t>(ar, ar.sten_c);
+    A.Bc = arena_ptr<T>(ar, ar.Bc);
+    A.MC = m.mc_pad;
+    A.ndir = arena_ptr<uint8_t>(ar, ar.ndir);
+    A.sten_d = arena_ptr<int32_t>(ar, ar.sten_d);
+    A.Bd = arena_ptr<T>(ar, ar.Bd);
+    A.MD = std::max(1, m.md_pad);
+    A.O = arena_ptr<T>(ar, ar.O);
+    A.Phi = arena_ptr<T>(ar, ar.Phi);
+    A.c2f = arena_ptr<int32_t>(ar, ar.c2f);
+    A.fnq = arena_ptr<uint8_t>(ar, ar.fnq);
+    A.Q = m.qmax;
+    A.NF = m.nfmax;
+    A.gate = gate;
+    A.fs = static_cast<T*>(fs);
+    A.flags = flags;
+    A.label = label;
+    A.lam_c = T(m.lambda_c);
+    A.eps = T(m.eps);
+    A.gm1 = T(gm1);
+    hipLaunchKernelGGL((reconstruct_kernel<T, K>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
+    return UCNS_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+struct ucns_mesh_impl_guard {};
+
+extern "C" {
+
+const char* ucns_last_error(void) { return ucns::last_error_cstr(); }
+
+int ucns_mesh_build(const ucns_mesh_desc* desc, const ucns_recon_opts* opts, int n_threads, ucns_mesh** out) {
+    UCNS_REQUIRE(out != nullptr, UCNS_EINVAL, "null output handle");
+    *out = nullptr;
+    Mesh* m = nullptr;
+    int rc = build_mesh(desc, opts, n_threads, &m);
+    if (rc != UCNS_OK) return rc;
+    *out = new ucns_mesh{m};
+    return UCNS_OK;
+}
+
+void ucns_mesh_free(ucns_mesh* mesh) {
+    if (!mesh) return;
+    delete mesh->m;
+    delete mesh;
+}
+
+int ucns_mesh_info(const ucns_mesh* mesh, int64_t* info) {
+    UCNS_REQUIRE(mesh && info, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    int64_t v[16] = {m.nc, m.nf, m.K, m.qmax, m.nfmax, m.mc_pad, m.nd_max, m.md_pad, m.nbnd, m.n_dropped_total,
+                     m.mc_min, m.mc_pad, m.order, 0, 0, 0};
+    std::memcpy(info, v, sizeof v);
+    return UCNS_OK;
+}
+
+int ucns_mesh_arena_bytes(const ucns_mesh* mesh, int precision, size_t* bytes) {
+    UCNS_REQUIRE(mesh && bytes, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    Arena a;
+    pack_arena(*mesh->m, precision, a, nullptr);
+    *bytes = a.bytes;
+    return UCNS_OK;
+}
+
+int ucns_mesh_upload(ucns_mesh* mesh, int precision, void* arena, size_t bytes, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && arena, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(aligned(arena), UCNS_EINVAL, "arena must be 256-byte aligned");
+    Mesh& m = *mesh->m;
+    Arena a;
+    std::vector<unsigned char> image;
+    pack_arena(m, precision, a, &image);
+    UCNS_REQUIRE(bytes >= a.bytes, UCNS_ENOMEM, "arena smaller than ucns_mesh_arena_bytes");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(arena, image.data(), a.bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_error(std::string("upload: ") + hipGetErrorString(e));
+        return UCNS_EHIP;
+    }
+    a.dev = arena;
+    m.arena[precision] = a;
+    return UCNS_OK;
+}
+
+int ucns_mesh_faces(const ucns_mesh* mesh, int32_t* c2f, int64_t* fcell, double* qp, double* shift) {
+    UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    if (c2f) std::memcpy(c2f, m.c2f.data(), sizeof(int32_t) * m.c2f.size());
+    if (fcell) std::memcpy(fcell, m.fcell.data(), sizeof(int64_t) * m.fcell.size());
+    if (qp) std::memcpy(qp, m.fqp.data(), sizeof(double) * m.fqp.size());
+    if (shift) std::memcpy(shift, m.fshift.data(), sizeof(double) * m.fshift.size());
+    return UCNS_OK;
+}
+
+int ucns_mesh_cell_geometry(const ucns_mesh* mesh, double* vol, double* cen, double* hbasis) {
+    UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    if (vol) std::memcpy(vol, m.vol.data(), sizeof(double) * m.nc);
+    if (cen) std::memcpy(cen, m.cen.data(), sizeof(double) * 3 * m.nc);
+    if (hbasis) std::memcpy(hbasis, m.hb.data(), sizeof(double) * m.nc);
+    return UCNS_OK;
+}
+
+int ucns_mesh_stencil(const ucns_mesh* mesh, int64_t cell, int64_t* central, int32_t* ncen, int64_t* dir,
+                      int32_t* ndir, int32_t* dface) {
+    UCNS_REQUIRE(mesh && central && ncen && dir && ndir && dface, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    UCNS_REQUIRE(cell >= 0 && cell < m.nc, UCNS_EINVAL, "cell out of range");
+    *ncen = m.ncen[cell];
+    for (int k = 0; k < m.ncen[cell]; ++k) central[k] = m.cand[size_t(cell) * kMaxCentral + k];
+    for (int s = 0; s < m.ndir[cell]; ++s) {
+        ndir[s] = m.nds[cell * kMaxFaces + s];
+        dface[s] = m.dface[cell * kMaxFaces + s];
+        for (int k = 0; k < ndir[s]; ++k) dir[s * kMaxDir + k] = m.dir[(size_t(cell) * kMaxFaces + s) * kMaxDir + k];
+    }
+    return m.ndir[cell];
+}
+
+int ucns_mesh_operators(const ucns_mesh* mesh, int64_t cell, double* Bc, double* Bd, double* O, double* Phi) {
+    UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    UCNS_REQUIRE(cell >= 0 && cell < m.nc, UCNS_EINVAL, "cell out of range");
+    const int K = m.K;
+    if (Bc)
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < m.ncen[cell]; ++j) Bc[k * m.ncen[cell] + j] = m.Bc[(size_t(cell) * K + k) * m.mc_pad + j];
+    if (Bd)
+        for (int s = 0; s < m.ndir[cell]; ++s)
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < m.nds[cell * kMaxFaces + s]; ++j)
+                    Bd[(s * 3 + k) * kMaxDir + j] = m.Bd[((size_t(cell) * m.nd_max + s) * 3 + k) * m.md_pad + j];
+    if (O) std::memcpy(O, &m.O[size_t(cell) * K * K], sizeof(double) * K * K);
+    if (Phi) std::memcpy(Phi, &m.Phi[size_t(cell) * m.nfmax * m.qmax * K], sizeof(double) * m.nfmax * m.qmax * K);
+    return UCNS_OK;
+}
+
+int ucns_workspace_elems(const ucns_mesh* mesh, int64_t* face_state, int64_t* face_flux, int64_t* gradW,
+                         int64_t* reduce_scratch) {
+    UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    if (face_state) *face_state = m.nf * 2 * m.qmax * 5;
+    if (face_flux) *face_flux = m.nf * 5;
+    if (gradW) *gradW = 12 * m.nc;
+    if (reduce_scratch) *reduce_scratch = kRedBlocks;
+    return UCNS_OK;
+}
+
+int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, double cfl, double* scratch,
+            double* dt_dev, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && U && scratch && dt_dev, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    const Arena& a = m.arena[UCNS_F64].dev ? m.arena[UCNS_F64] : m.arena[UCNS_F32];
+    UCNS_REQUIRE(a.dev, UCNS_ESTATE, "mesh not uploaded");
+    UCNS_REQUIRE(cfl > 0, UCNS_EINVAL, "cfl must be positive");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    PhysT<double> P = make_phys<double>(phys);
+    unsigned nb = std::min<unsigned>(kRedBlocks, grid_for(m.nc));
+    hipLaunchKernelGGL(dt_partial_kernel, dim3(nb), dim3(kBlock), 0, st, m.nc, U, arena_ptr<double>(a, a.hdt), P, scratch);
+    hipLaunchKernelGGL(dt_final_kernel, dim3(1), dim3(kBlock), 0, st, int(nb), scratch, cfl, dt_dev);
+    return hip_check("ucns_dt");
+}
+
+int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
+                     const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && U && face_state, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(aligned(U) && aligned(face_state), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    const Mesh& m = *mesh->m;
+    const Arena& ar = m.arena[precision];
+    UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const uint8_t* gm = gate ? gate->mask : nullptr;
+    const double gm1 = phys->gamma - 1.0;
+    int rc = UCNS_EINVAL;
+    if (precision == UCNS_F64) {
+        if (m.K == 9) rc = launch_recon_k<double, 9>(m, ar, gm1, U, gm, face_state, flags, label, st);
+        if (m.K == 19) rc = launch_recon_k<double, 19>(m, ar, gm1, U, gm, face_state, flags, label, st);
+    } else {
+        if (m.K == 9) rc = launch_recon_k<float, 9>(m, ar, gm1, U, gm, face_state, flags, label, st);
+        if (m.K == 19) rc = launch_recon_k<float, 19>(m, ar, gm1, U, gm, face_state, flags, label, st);
+    }
+    if (rc != UCNS_OK) {
+        set_error("unsupported reconstruction order");
+        return rc;
+    }
+    return hip_check("ucns_reconstruct");
+}
+
+int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const double* U, int precision,
+                   void* gradW, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && U && gradW, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(aligned(U) && aligned(gradW), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    const Mesh& m = *mesh->m;
+    const Arena& ar = m.arena[precision];
+    UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    auto go = [&](auto zero) {
+        using T = decltype(zero);
+        GradArgs<T> A{U, m.nc, arena_ptr<int32_t>(ar, ar.c2f), m.nfmax, arena_ptr<int32_t>(ar, ar.fcell),
+                      arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<double>(ar, ar.vol),
+                      static_cast<T*>(gradW)};
+        hipLaunchKernelGGL(gradients_kernel<T>, dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A, make_phys<T>(phys),
+                           make_bc<T>(bc));
+    };
+    if (precision == UCNS_F64)
+        go(double(0));
+    else
+        go(float(0));
+    return hip_check("ucns_gradients");
+}
+
+int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const void* face_state,
+                   const void* gradW, int precision, void* face_flux, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && face_state && face_flux, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(!phys->viscous || gradW, UCNS_EINVAL, "viscous flux needs gradients");
+    UCNS_REQUIRE(aligned(face_state) && aligned(face_flux), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    UCNS_REQUIRE(phys->flux == UCNS_HLLC || phys->flux == UCNS_RUSANOV, UCNS_EINVAL, "unknown flux");
+    const Mesh& m = *mesh->m;
+    const Arena& ar = m.arena[precision];
+    UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int QG = m.qmax <= 4 ? 4 : 16;
+    const int64_t nthreads = m.nf * QG;
+    auto go = [&](auto zero) {
+        using T = decltype(zero);
+        FluxArgs<T> A{static_cast<const T*>(face_state), m.nf, m.nc, m.qmax, arena_ptr<int32_t>(ar, ar.fcell),
+                      arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<T>(ar, ar.fw),
+                      arena_ptr<T>(ar, ar.fdc), arena_ptr<uint8_t>(ar, ar.fnq), static_cast<const T*>(gradW),
+                      static_cast<T*>(face_flux)};
+        if (QG == 4)
+            hipLaunchKernelGGL((face_flux_kernel<T, 4>), dim3(grid_for(nthreads)), dim3(kBlock), 0, st, A,
+                               make_phys<T>(phys), make_bc<T>(bc));
+        else
+            hipLaunchKernelGGL((face_flux_kernel<T, 16>), dim3(grid_for(nthreads)), dim3(kBlock), 0, st, A,
+                               make_phys<T>(phys), make_bc<T>(bc));
+    };
+    if (precision == UCNS_F64)
+        go(double(0));
+    else
+        go(float(0));
+    return hip_check("ucns_face_flux");
+}
+
+namespace {
+int launch_residual(const ucns_mesh* mesh, const void* face_flux, int precision, double* R, int stage,
+                    const double* dt_dev, double* U0, double* U, ucns_stream stream) {
+    static const double Ac[3] = {0.0, 0.75, 1.0 / 3.0}, Bc_[3] = {1.0, 0.25, 2.0 / 3.0};
+    const Mesh& m = *mesh->m;
+    const Arena& ar = m.arena[precision];
+    UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    auto go = [&](auto zero) {
+        using T = decltype(zero);
+        ResArgs<T> A{static_cast<const T*>(face_flux), m.nc, arena_ptr<int32_t>(ar, ar.c2f), m.nfmax,
+                     arena_ptr<double>(ar, ar.vol), R, U0, U, dt_dev, stage >= 0 ? Ac[stage] : 0.0,
+                     stage >= 0 ? Bc_[stage] : 0.0, stage};
+        if (stage >= 0)
+            hipLaunchKernelGGL((residual_kernel<T, true>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
+        else
+            hipLaunchKernelGGL((residual_kernel<T, false>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
+    };
+    if (precision == UCNS_F64)
+        go(double(0));
+    else
+        go(float(0));
+    return hip_check("ucns_residual");
+}
+}  // namespace
+
+int ucns_residual(const ucns_mesh* mesh, const void* face_flux, int precision, double* R, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && face_flux && R, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(aligned(face_flux) && aligned(R), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    return launch_residual(mesh, face_flux, precision, R, -1, nullptr, nullptr, nullptr, stream);
+}
+
+int ucns_residual_rk_stage(const ucns_mesh* mesh, const void* face_flux, int precision, int stage,
+                           const double* dt_dev, double* U0, double* U, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && face_flux && dt_dev && U0 && U, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(stage >= 0 && stage <= 2, UCNS_EINVAL, "stage must be 0, 1 or 2");
+    UCNS_REQUIRE(aligned(face_flux) && aligned(U0) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    return launch_residual(mesh, face_flux, precision, nullptr, stage, dt_dev, U0, U, stream);
+}
+
+int ucns_rk_stage(const ucns_mesh* mesh, int stage, const double* dt_dev, double* U0, const double* R,
+                  double* U, ucns_stream stream) {
+    static const double Ac[3] = {0.0, 0.75, 1.0 / 3.0}, Bc_[3] = {1.0, 0.25, 2.0 / 3.0};
+    UCNS_REQUIRE(mesh && dt_dev && U0 && R && U, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(stage >= 0 && stage <= 2, UCNS_EINVAL, "stage must be 0, 1 or 2");
+    UCNS_REQUIRE(aligned(U0) && aligned(R) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    const int64_t n = 5 * mesh->m->nc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(rk_stage_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, n, U0, R, U, dt_dev, Ac[stage],
+                       Bc_[stage], stage);
+    return hip_check("ucns_rk_stage");
+}
+
+int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* scratch, double* ke_dev, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && U && scratch && ke_dev, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    const Arena& a = m.arena[UCNS_F64].dev ? m.arena[UCNS_F64] : m.arena[UCNS_F32];
+    UCNS_REQUIRE(a.dev, UCNS_ESTATE, "mesh not uploaded");
+    double tv = 0;
+    for (int64_t c = 0; c < m.nc; ++c) tv += m.vol[c];
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    unsigned nb = std::min<unsigned>(kRedBlocks, grid_for(m.nc));
+    hipLaunchKernelGGL(ke_partial_kernel, dim3(nb), dim3(kBlock), 0, st, m.nc, U, arena_ptr<double>(a, a.vol), scratch);
+    hipLaunchKernelGGL(ke_final_kernel, dim3(1), dim3(kBlock), 0, st, int(nb), scratch, 1.0 / tv, ke_dev);
+    return hip_check("ucns_diag_ke");
+}
+
+int ucns_gate_features(const ucns_mesh*, const double*, float*, ucns_stream) {
+    set_error("gate features not available in this build");
+    return UCNS_ESTATE;
+}
+int ucns_mlp_forward(const float*, const float*, int64_t, float*, ucns_stream) {
+    set_error("mlp not available in this build");
+    return UCNS_ESTATE;
+}
+int ucns_gate_mask(const float*, const float*, int64_t, uint8_t*, ucns_stream) {
+    set_error("mlp not available in this build");
+    return UCNS_ESTATE;
+}
+int ucns_mlp_train_step(float*, float*, float*, const float*, const float*, int64_t, float, float, int, float*,
+                        ucns_stream) {
+    set_error("mlp not available in this build");
+    return UCNS_ESTATE;
+}
+
+}  // extern "C"

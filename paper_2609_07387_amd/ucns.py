@@ -1,0 +1,327 @@
+"""Thin Python binding of libucns (argument marshalling only).
+
+Every step of the residual evaluation runs in the library's HIP kernels;
+PyTorch only provides device memory and the stream.  The names follow the C
+ABI in ``include/ucns.h``.  Importing this module does not need a GPU; the
+compute calls do, and they fail loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libucns.so")
+
+F64, F32 = 0, 1
+RUSANOV, HLLC = 0, 1
+BC_NONE, BC_DIRICHLET, BC_TRANSMISSIVE, BC_WALL = 0, 1, 2, 3
+MAX_FACES, MAX_DIR = 6, 16
+
+# Names declared in include/ucns.h (checked by the test-suite against the
+# library's exports).
+EXPORTS = [
+    "ucns_last_error", "ucns_mesh_build", "ucns_mesh_free", "ucns_mesh_info", "ucns_mesh_arena_bytes",
+    "ucns_mesh_upload", "ucns_mesh_faces", "ucns_mesh_cell_geometry", "ucns_mesh_stencil", "ucns_mesh_operators",
+    "ucns_workspace_elems", "ucns_dt", "ucns_reconstruct", "ucns_gradients", "ucns_face_flux", "ucns_residual",
+    "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
+    "ucns_gate_mask", "ucns_mlp_train_step",
+]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [
+        ("n_vert", C.c_int64), ("xyz", C.c_void_p), ("n_cell", C.c_int64), ("type", C.c_void_p),
+        ("cell_ptr", C.c_void_p), ("cell_vtx", C.c_void_p), ("period", C.c_double * 3),
+        ("n_bface", C.c_int64), ("bface_ptr", C.c_void_p), ("bface_vtx", C.c_void_p), ("bface_tag", C.c_void_p),
+    ]
+
+
+class ReconOpts(C.Structure):
+    _fields_ = [("order", C.c_int), ("lambda_c", C.c_double), ("eps", C.c_double), ("max_layers", C.c_int)]
+
+
+class Phys(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("reynolds", C.c_double), ("prandtl", C.c_double),
+                ("viscous", C.c_int), ("flux", C.c_int)]
+
+
+class BC(C.Structure):
+    _fields_ = [("kind", C.c_int * 8), ("state", (C.c_double * 5) * 8)]
+
+
+class Gate(C.Structure):
+    _fields_ = [("mask", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libucns (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libucns.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dbl, flt = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_float
+        L.ucns_last_error.restype = C.c_char_p
+        L.ucns_mesh_build.argtypes = [C.POINTER(MeshDesc), C.POINTER(ReconOpts), i32, C.POINTER(vp)]
+        L.ucns_mesh_free.argtypes = [vp]
+        L.ucns_mesh_free.restype = None
+        L.ucns_mesh_info.argtypes = [vp, vp]
+        L.ucns_mesh_arena_bytes.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
+        L.ucns_mesh_upload.argtypes = [vp, i32, vp, C.c_size_t, vp]
+        L.ucns_mesh_faces.argtypes = [vp, vp, vp, vp, vp]
+        L.ucns_mesh_cell_geometry.argtypes = [vp, vp, vp, vp]
+        L.ucns_mesh_stencil.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.ucns_mesh_operators.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ucns_workspace_elems.argtypes = [vp, vp, vp, vp, vp]
+        L.ucns_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp, vp, vp]
+        L.ucns_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, vp, vp]
+        L.ucns_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, i32, vp, vp]
+        L.ucns_face_flux.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, i32, vp, vp]
+        L.ucns_residual.argtypes = [vp, vp, i32, vp, vp]
+        L.ucns_rk_stage.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.ucns_residual_rk_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
+        L.ucns_diag_ke.argtypes = [vp, vp, vp, vp, vp]
+        L.ucns_gate_features.argtypes = [vp, vp, vp, vp]
+        L.ucns_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.ucns_gate_mask.argtypes = [vp, vp, i64, vp, vp]
+        L.ucns_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i64, flt, flt, i32, vp, vp]
+        _lib = L
+    return _lib
+
+
+class UcnsError(RuntimeError):
+    pass
+
+
+def check(rc):
+    if rc != 0:
+        raise UcnsError(f"libucns error {rc}: {lib().ucns_last_error().decode()}")
+
+
+def _np(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dp(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def phys(gamma=1.4, mach=0.1, reynolds=1600.0, prandtl=0.72, viscous=False, flux="hllc") -> Phys:
+    return Phys(gamma, mach, reynolds, prandtl, int(bool(viscous)), HLLC if flux == "hllc" else RUSANOV)
+
+
+def bc(entries=None) -> BC:
+    """entries: {tag: (kind, state5 or None)}."""
+    b = BC()
+    for t in range(8):
+        b.kind[t] = BC_TRANSMISSIVE
+    for t, (kind, state) in (entries or {}).items():
+        b.kind[t] = kind
+        if state is not None:
+            for v in range(5):
+                b.state[t][v] = float(state[v])
+    return b
+
+
+class Mesh:
+    """Library mesh handle (host build) plus its device arenas."""
+
+    def __init__(self, mesh, order=2, lambda_c=1000.0, eps=1e-12, max_layers=3, n_threads=0):
+        L = lib()
+        self._keep = [np.ascontiguousarray(mesh.xyz, np.float64), np.ascontiguousarray(mesh.ctype, np.uint8),
+                      np.ascontiguousarray(mesh.cell_ptr, np.int64), np.ascontiguousarray(mesh.cell_vtx, np.int64),
+                      np.ascontiguousarray(mesh.bface_ptr, np.int64), np.ascontiguousarray(mesh.bface_vtx, np.int64),
+                      np.ascontiguousarray(mesh.bface_tag, np.int32)]
+        xyz, ty, cp, cv, bp, bv, bt = self._keep
+        d = MeshDesc(xyz.shape[0], _np(xyz), ty.shape[0], _np(ty), _np(cp), _np(cv),
+                     (C.c_double * 3)(*[float(x) for x in mesh.period]), bt.shape[0], _np(bp), _np(bv), _np(bt))
+        o = ReconOpts(order, lambda_c, eps, max_layers)
+        h = C.c_void_p()
+        check(L.ucns_mesh_build(C.byref(d), C.byref(o), int(n_threads), C.byref(h)))
+        self.h = h
+        self._keep = None
+        info = np.zeros(16, np.int64)
+        check(L.ucns_mesh_info(self.h, _np(info)))
+        (self.n_cell, self.n_face, self.K, self.qmax, self.nfmax, self.mc_pad, self.nd_max, self.md_pad,
+         self.n_bnd, self.n_dropped, self.mc_min, _, self.order) = (int(x) for x in info[:13])
+        fs, ff, gw, rs = (np.zeros(1, np.int64) for _ in range(4))
+        check(L.ucns_workspace_elems(self.h, _np(fs), _np(ff), _np(gw), _np(rs)))
+        self.n_face_state, self.n_face_flux, self.n_grad, self.n_reduce = int(fs[0]), int(ff[0]), int(gw[0]), int(rs[0])
+        self.arenas = {}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ucns_mesh_free(self.h)
+            self.h = None
+
+    # ---- host inspection
+    def arena_bytes(self, precision):
+        n = C.c_size_t()
+        check(lib().ucns_mesh_arena_bytes(self.h, precision, C.byref(n)))
+        return int(n.value)
+
+    def faces(self):
+        c2f = np.zeros((self.n_cell, MAX_FACES), np.int32)
+        fcell = np.zeros((self.n_face, 2), np.int64)
+        qp = np.zeros((self.n_face, self.qmax, 3))
+        shift = np.zeros((self.n_face, 3))
+        check(lib().ucns_mesh_faces(self.h, _np(c2f), _np(fcell), _np(qp), _np(shift)))
+        return c2f, fcell, qp, shift
+
+    def cell_geometry(self):
+        vol, cen, hb = np.zeros(self.n_cell), np.zeros((self.n_cell, 3)), np.zeros(self.n_cell)
+        check(lib().ucns_mesh_cell_geometry(self.h, _np(vol), _np(cen), _np(hb)))
+        return vol, cen, hb
+
+    def stencil(self, cell):
+        cen = np.zeros(64, np.int64)
+        n = np.zeros(1, np.int32)
+        d = np.zeros((MAX_FACES, MAX_DIR), np.int64)
+        nd = np.zeros(MAX_FACES, np.int32)
+        df = np.zeros(MAX_FACES, np.int32)
+        rc = lib().ucns_mesh_stencil(self.h, int(cell), _np(cen), _np(n), _np(d), _np(nd), _np(df))
+        if rc < 0:
+            check(rc)
+        return cen[:n[0]].copy(), [d[s, :nd[s]].copy() for s in range(rc)], df[:rc].copy()
+
+    def operators(self, cell):
+        cen, dirs, _ = self.stencil(cell)
+        K = self.K
+        Bc = np.zeros((K, len(cen)))
+        Bd = np.zeros((MAX_FACES, 3, MAX_DIR))
+        O = np.zeros((K, K))
+        Phi = np.zeros((self.nfmax, self.qmax, K))
+        check(lib().ucns_mesh_operators(self.h, int(cell), _np(Bc), _np(Bd), _np(O), _np(Phi)))
+        return dict(Bc=Bc, Bd=[Bd[s, :, :len(dirs[s])].copy() for s in range(len(dirs))], O=O, Phi=Phi)
+
+    # ---- device
+    def upload(self, precision, device="cuda"):
+        import torch
+
+        nbytes = self.arena_bytes(precision)
+        arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        check(lib().ucns_mesh_upload(self.h, precision, _dp(arena), nbytes, _stream()))
+        self.arenas[precision] = arena
+        return arena
+
+
+def _t(precision):
+    import torch
+
+    return torch.float64 if precision == F64 else torch.float32
+
+
+class Workspace:
+    """Caller-owned device workspaces of one precision."""
+
+    def __init__(self, mesh: Mesh, precision, viscous, device="cuda"):
+        import torch
+
+        dt = _t(precision)
+        self.face_state = torch.empty(mesh.n_face_state, dtype=dt, device=device)
+        self.face_flux = torch.empty(mesh.n_face_flux, dtype=dt, device=device)
+        self.gradW = torch.empty(mesh.n_grad, dtype=dt, device=device) if viscous else None
+        self.reduce = torch.empty(mesh.n_reduce, dtype=torch.float64, device=device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        self.ke = torch.zeros(1, dtype=torch.float64, device=device)
+        self.U0 = None
+        self.R = None
+
+
+# ------------------------------------------------------------ entry points
+
+def dt(mesh, ph, U, cfl, scratch, dt_dev, stream=None):
+    check(lib().ucns_dt(mesh.h, C.byref(ph), _dp(U), float(cfl), _dp(scratch), _dp(dt_dev), _stream(stream)))
+
+
+def reconstruct(mesh, ph, U, precision, face_state, gate_mask=None, flags=None, label=None, stream=None):
+    g = Gate(C.c_void_p(gate_mask.data_ptr())) if gate_mask is not None else None
+    check(lib().ucns_reconstruct(mesh.h, C.byref(ph), _dp(U), precision, None if g is None else C.byref(g),
+                                 _dp(face_state), _dp(flags), _dp(label), _stream(stream)))
+
+
+def gradients(mesh, ph, bcs, U, precision, gradW, stream=None):
+    check(lib().ucns_gradients(mesh.h, C.byref(ph), None if bcs is None else C.byref(bcs), _dp(U), precision,
+                               _dp(gradW), _stream(stream)))
+
+
+def face_flux(mesh, ph, bcs, face_state, gradW, precision, ff, stream=None):
+    check(lib().ucns_face_flux(mesh.h, C.byref(ph), None if bcs is None else C.byref(bcs), _dp(face_state),
+                               _dp(gradW), precision, _dp(ff), _stream(stream)))
+
+
+def residual(mesh, ff, precision, R, stream=None):
+    check(lib().ucns_residual(mesh.h, _dp(ff), precision, _dp(R), _stream(stream)))
+
+
+def rk_stage(mesh, stage, dt_dev, U0, R, U, stream=None):
+    check(lib().ucns_rk_stage(mesh.h, int(stage), _dp(dt_dev), _dp(U0), _dp(R), _dp(U), _stream(stream)))
+
+
+def residual_rk_stage(mesh, ff, precision, stage, dt_dev, U0, U, stream=None):
+    check(lib().ucns_residual_rk_stage(mesh.h, _dp(ff), precision, int(stage), _dp(dt_dev), _dp(U0), _dp(U),
+                                       _stream(stream)))
+
+
+def diag_ke(mesh, U, scratch, ke_dev, stream=None):
+    check(lib().ucns_diag_ke(mesh.h, _dp(U), _dp(scratch), _dp(ke_dev), _stream(stream)))
+
+
+class Solver:
+    """SSP-RK3 driver over the C-ABI calls (one stream, no host syncs)."""
+
+    def __init__(self, mesh: Mesh, ph: Phys, precision=F64, bcs=None, cfl=0.5, gate_mask=None, device="cuda"):
+        import torch
+
+        self.mesh, self.ph, self.precision, self.bcs, self.cfl = mesh, ph, precision, bcs, cfl
+        if precision not in mesh.arenas:
+            mesh.upload(precision, device)
+        self.ws = Workspace(mesh, precision, bool(ph.viscous), device)
+        self.U0 = torch.empty((5, mesh.n_cell), dtype=torch.float64, device=device)
+        self.gate_mask = gate_mask
+
+    def rhs_stage(self, U):
+        ws = self.ws
+        reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask)
+        if self.ph.viscous:
+            gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
+        face_flux(self.mesh, self.ph, self.bcs, ws.face_state, ws.gradW, self.precision, ws.face_flux)
+
+    def step(self, U, ke=False):
+        ws = self.ws
+        dt(self.mesh, self.ph, U, self.cfl, ws.reduce, ws.dt)
+        for s in range(3):  # stage 0 stores U^n into U0
+            self.rhs_stage(U)
+            residual_rk_stage(self.mesh, ws.face_flux, self.precision, s, ws.dt, self.U0, U)
+        if ke:
+            diag_ke(self.mesh, U, ws.reduce, ws.ke)
+
+    def run(self, U, n_steps, ke_history=False):
+        import torch
+
+        hist, dts = [], []
+        if ke_history:
+            diag_ke(self.mesh, U, self.ws.reduce, self.ws.ke)
+            hist.append(self.ws.ke.clone())
+        for _ in range(n_steps):
+            self.step(U, ke=ke_history)
+            if ke_history:
+                hist.append(self.ws.ke.clone())
+                dts.append(self.ws.dt.clone())
+        if ke_history:
+            return torch.cat(hist).cpu().numpy(), torch.cat(dts).cpu().numpy()
+        return None

@@ -1,0 +1,95 @@
+"""Helpers shared by the GPU parity tests: run one stage / n steps through the
+C-ABI and through the oracle on the same seeded inputs, and align face data."""
+import numpy as np
+
+import oracle
+from paper_2609_07387_amd import ucns
+
+
+def grouped_rel_linf(A, B):
+    """Relative L-inf per group {rho}, {rho u, rho v, rho w}, {rho E}; the max
+    over groups (error of A against the reference B)."""
+    out = 0.0
+    for g in ([0], [1, 2, 3], [4]):
+        den = np.abs(B[g]).max()
+        out = max(out, np.abs(A[g] - B[g]).max() / (den if den > 0 else 1.0))
+    return out
+
+
+def face_maps(lm, om):
+    """Aligned (library face, oracle face, side) triples over every (cell, local face)."""
+    c2f_l, _, _, _ = lm.faces()
+    c2f_o, side_o = om.cell_faces()
+    ok = c2f_o >= 0
+    fl = (c2f_l[ok] >> 1).astype(np.int64)
+    sl = (c2f_l[ok] & 1).astype(np.int64)
+    fo = c2f_o[ok]
+    assert np.array_equal(sl, side_o[ok].astype(np.int64))
+    return fl, fo, sl
+
+
+def lib_arrays(lm, precision, device="cuda"):
+    import torch
+
+    dt = torch.float64 if precision == ucns.F64 else torch.float32
+    fs = torch.full((lm.n_face_state,), float("nan"), dtype=dt, device=device)
+    ff = torch.zeros(lm.n_face_flux, dtype=dt, device=device)
+    gw = torch.zeros(lm.n_grad, dtype=dt, device=device)
+    R = torch.zeros((5, lm.n_cell), dtype=torch.float64, device=device)
+    return fs, ff, gw, R
+
+
+def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
+    """One residual evaluation on the GPU; returns host copies of
+    (face_state [nf,2,Q,5], gradW [12,nc] or None, face_flux [nf,5], R [5,nc], flags)."""
+    import torch
+
+    if precision not in lm.arenas:
+        lm.upload(precision, device)
+    U = torch.tensor(U_np, dtype=torch.float64, device=device).contiguous()
+    fs, ff, gw, R = lib_arrays(lm, precision, device)
+    flags = torch.zeros(lm.n_cell, dtype=torch.uint8, device=device)
+    gm = None if gate_mask is None else torch.tensor(gate_mask, dtype=torch.uint8, device=device)
+    ucns.reconstruct(lm, ph, U, precision, fs, gm, flags)
+    if ph.viscous:
+        ucns.gradients(lm, ph, bcs, U, precision, gw)
+    ucns.face_flux(lm, ph, bcs, fs, gw if ph.viscous else None, precision, ff)
+    ucns.residual(lm, ff, precision, R)
+    torch.cuda.synchronize()
+    return (fs.double().cpu().numpy().reshape(lm.n_face, 2, lm.qmax, 5),
+            gw.double().cpu().numpy().reshape(12, lm.n_cell) if ph.viscous else None,
+            ff.double().cpu().numpy().reshape(lm.n_face, 5), R.cpu().numpy(), flags.cpu().numpy())
+
+
+def gpu_run(lm, ph, U_np, precision, n_steps, cfl, bcs=None, gate_mask=None, device="cuda"):
+    import torch
+
+    gm = None if gate_mask is None else torch.tensor(gate_mask, dtype=torch.uint8, device=device)
+    s = ucns.Solver(lm, ph, precision, bcs, cfl, gm, device)
+    U = torch.tensor(U_np, dtype=torch.float64, device=device).contiguous()
+    ke, dts = s.run(U, n_steps, ke_history=True)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), ke, dts
+
+
+def oracle_stage(om, ph, U, bcs=None, gate_mask=None):
+    fs, flags, label = om.reconstruct(U, ph, gate_mask, with_flags=True)
+    g = om.gradients(U, ph, bcs) if ph.viscous else None
+    ff = om.face_flux(fs, ph, g, bcs)
+    R = om.residual(ff)
+    return fs, g, ff, R, flags, label
+
+
+def as_oracle_phys(ph):
+    return oracle.Phys(ph.gamma, ph.mach, ph.reynolds, ph.prandtl, ph.viscous, ph.flux)
+
+
+def as_oracle_bc(b):
+    if b is None:
+        return None
+    o = oracle.BC()
+    for t in range(8):
+        o.kind[t] = b.kind[t]
+        for v in range(5):
+            o.state[t][v] = b.state[t][v]
+    return o
