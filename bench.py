@@ -64,15 +64,15 @@ def time_steps(solver, U, steps, warmup, torch):
     return e0.elapsed_time(e1), wall
 
 
-def time_recon(lm, ph, U, precision, fs, reps, torch, ucns):
+def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns):
     s = torch.cuda.current_stream()
     for _ in range(3):
-        ucns.reconstruct(lm, ph, U, precision, fs)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        ucns.reconstruct(lm, ph, U, precision, fs)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -133,7 +133,7 @@ def main():
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
         rate = nc * 3 * args.steps / (ms / 1e3)
-        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, 20, torch, ucns)
+        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns)
         rb = recon_bytes_per_cell(lm, prec) * nc
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
                           "recon_ms": rms, "recon_GBs": rb / (rms / 1e3) / 1e9,

@@ -177,8 +177,9 @@ int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, doubl
  * weights, blend, and the polynomial values at the cell's face quadrature
  * points written to face_state.  Positivity of density and pressure at every
  * point is enforced with the fallback gated-linear -> full CWENOZ -> first
- * order; flags[c] (device, may be NULL) records bit0 linear taken, bit1
- * CWENOZ fallback, bit2 first-order fallback.  label (device float [n_cell],
+ * order, run as a second pass over the cells that need it; flags[c]
+ * (device [n_cell], required) records bit0 linear taken, bit1 CWENOZ
+ * fallback, bit2 first-order fallback.  label (device float [n_cell],
  * may be NULL) receives max over variables and stencils of |omega - lambda|. */
 int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
                      const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream);

@@ -855,6 +855,8 @@ int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads,
         }
     }
     m->qmax = std::max(has_quad ? o->order * o->order : 0, has_tri ? 3 : 0);
+    for (int64_t c = 1; c < m->nc; ++c)
+        if (m->type[c] != m->type[0]) m->uniform_type = false;
     int rc = build_faces(*m);
     if (rc == UCNS_OK) rc = match_boundaries(*m, d);
     if (rc != UCNS_OK) {

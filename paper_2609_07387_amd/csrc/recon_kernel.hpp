@@ -1,0 +1,294 @@
+// CWENOZ reconstruction kernel (included by ucns_kernels.hip).
+//
+// Sec. 2.2 of the UCNS3D v4 paper: least-squares central and directional
+// polynomials (eq. lsq_system), smoothness indicators and WENO-Z nonlinear
+// weights (eq. cwenoz_weights), the CWENOZ blend (eq. cwenoz_poly) and the
+// point values at the cell's face quadrature points.
+//
+// One thread per cell, all five conserved variables, so every operator value
+// is loaded once and used five times.  Every stream of loads (stencil
+// members, directional members, face points) is software-pipelined one
+// element ahead: while element i is accumulated, the index of element i+2
+// and the state and operator values of element i+1 are already in flight,
+// so a wave keeps two elements' worth of loads outstanding instead of
+// waiting a full memory round trip per stencil member.
+
+template <class T, int K>
+__device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c, const double* ui, T a[K][5]) {
+    const int64_t nc = A.nc;
+    const int MC = A.MC;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) a[k][v] = T(0);
+    const int32_t* sp = A.sten_c + c;
+    const T* bp = A.Bc + c;
+    const int64_t kstride = int64_t(MC) * nc;
+    // prologue: member 0 operands, index of member 1
+    int32_t j1 = sp[(MC > 1 ? 1 : 0) * nc];
+    const int32_t j0 = sp[0];
+    double u0[5];
+    T b0[K];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u0[v] = A.U[v * nc + j0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) b0[k] = bp[k * kstride];
+#pragma unroll 1
+    for (int m = 0; m < MC; ++m) {
+        const int mn = m + 1 < MC ? m + 1 : m;
+        const int32_t j2 = sp[int64_t(m + 2 < MC ? m + 2 : mn) * nc];
+        double u1[5];
+        T b1[K];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u1[v] = A.U[v * nc + j1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) b1[k] = bp[k * kstride + int64_t(mn) * nc];
+        T bv[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) a[k][v] += b0[k] * bv[v];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u0[v] = u1[v];
+#pragma unroll
+        for (int k = 0; k < K; ++k) b0[k] = b1[k];
+        j1 = j2;
+    }
+}
+
+// Steps per cell:
+//  (i)   stencil jumps b_m = U_m - U_i in FP64, rounded to T
+//  (ii)  a_opt = B_c b
+//  (iii) a_s = B_s b_s per directional (linear) stencil
+//  (iv)  SI_1 = a_opt^T O a_opt, SI_s = a_s^T O_lin a_s
+//  (v)   tau = mean |SI_1 - SI_s|, w~ = lambda (1 + tau/(eps + SI))
+//  (vi)  Levy-Puppo-Russo blend accumulated in one pass over the stencils:
+//        abar = s1 a_opt + (tau/W) G on the linear modes, with
+//        s1 = (1 + tau/(eps+SI_1))/W, W = 1 + tau sum_s lambda_s/(eps+SI_s),
+//        G = sum_{s>=2} lambda_s (1/(eps+SI_s) - 1/(eps+SI_1)) a_s
+//  (vii) point values U_i + Phi_q . abar at the cell's face points, with the
+//        positivity fallback linear -> CWENOZ -> first order.
+template <class T, int K, bool LABEL>
+__device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab) {
+    const int64_t nc = A.nc;
+    T a[K][5];
+    central_coeffs<T, K>(A, c, ui, a);
+    T s1[5], g[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        s1[v] = mode == 2 ? T(0) : T(1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k][v] = T(0);
+    }
+        const int nd = A.ndir[c];
+        if (mode == 1 && nd > 0) {
+            const T lam_s = T(1) / (A.lam_c + T(nd));
+            const T lam_1 = A.lam_c * lam_s;
+            T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                SI1[v] = T(0);
+                tsum[v] = T(0);
+            }
+            // SI_1 = a^T O a with O stored as its upper triangle
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T okk = A.O[int64_t(tri_index(K, k, k)) * nc + c];
+                T t[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) t[v] = okk * a[k][v];
+#pragma unroll
+                for (int l = k + 1; l < K; ++l) {
+                    const T o2 = T(2) * A.O[int64_t(tri_index(K, k, l)) * nc + c];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) t[v] += o2 * a[l][v];
+                }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) SI1[v] += a[k][v] * t[v];
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                inv1[v] = T(1) / (A.eps + SI1[v]);
+                Lam[v] = lam_1 * inv1[v];
+                rmin[v] = inv1[v];
+                rmax[v] = inv1[v];
+            }
+            const T o00 = A.O[0 * nc + c], o01 = A.O[1 * nc + c], o02 = A.O[2 * nc + c];
+            const T o11 = A.O[int64_t(K) * nc + c], o12 = A.O[int64_t(K + 1) * nc + c];
+            const T o22 = A.O[int64_t(2 * K - 1) * nc + c];
+            // all directional members as one pipelined stream t = s * MD + m
+            const int MD = A.MD, total = nd * MD;
+            const int32_t* sp = A.sten_d + c;
+            const T* bp = A.Bd + c;
+            const int64_t kstride = int64_t(MD) * nc;  // between the 3 rows of one stencil
+            int32_t j1 = sp[int64_t(total > 1 ? 1 : 0) * nc];
+            const int32_t j0 = sp[0];
+            double u0[5];
+            T b0[3];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u0[v] = A.U[v * nc + j0];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b0[k] = bp[k * kstride];
+            T as[3][5];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+            int m = 0, s = 0;
+#pragma unroll 1
+            for (int t = 0; t < total; ++t) {
+                // element t+1 is (s, m+1) or (s+1, 0); its operator rows sit at
+                // (3 s' + k) MD + m' = t' + 2 s' MD + k MD for t' = s' MD + m'
+                const int tn = t + 1 < total ? t + 1 : t;
+                const int sn = (m + 1 < MD) ? s : s + 1;
+                const int sn_c = t + 1 < total ? sn : s;
+                const int t2 = t + 2 < total ? t + 2 : tn;
+                const int32_t j2 = sp[int64_t(t2) * nc];
+                double u1[5];
+                T b1[3];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) u1[v] = A.U[v * nc + j1];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b1[k] = bp[int64_t(tn + 2 * sn_c * MD) * nc + k * kstride];
+                T bv[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) as[k][v] += b0[k] * bv[v];
+                if (m + 1 == MD) {
+                    // stencil s complete: its indicator and its share of the blend
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) {
+                        const T x = as[0][v], y = as[1][v], z = as[2][v];
+                        const T SIs =
+                            x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z;
+                        tsum[v] += fabs(SI1[v] - SIs);
+                        const T r = T(1) / (A.eps + SIs);
+                        Lam[v] += lam_s * r;
+                        rmin[v] = fmin(rmin[v], r);
+                        rmax[v] = fmax(rmax[v], r);
+                        const T coef = lam_s * (r - inv1[v]);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            g[k][v] += coef * as[k][v];
+                            as[k][v] = T(0);
+                        }
+                    }
+                    m = 0;
+                    ++s;
+                } else {
+                    ++m;
+                }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) u0[v] = u1[v];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b0[k] = b1[k];
+                j1 = j2;
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T tau = tsum[v] / T(nd);
+                const T W = T(1) + tau * Lam[v];
+                s1[v] = (T(1) + tau * inv1[v]) / W;
+                const T tw = tau / W;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) g[k][v] *= tw;
+                if constexpr (LABEL) {
+                    // |omega_s - lambda_s| = lambda_s |(1 + tau r_s)/W - 1|: extreme at rmin or rmax
+                    const float d1 = float(fabs(lam_1 * (s1[v] - T(1))));
+                    const float d2 = float(fabs(lam_s * ((T(1) + tau * rmin[v]) / W - T(1))));
+                    const float d3 = float(fabs(lam_s * ((T(1) + tau * rmax[v]) / W - T(1))));
+                    lab = fmaxf(lab, fmaxf(d1, fmaxf(d2, d3)));
+                }
+            }
+        }
+        // blended coefficients, then the point values at the face points
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) a[k][v] = s1[v] * a[k][v] + (k < 3 ? g[k < 3 ? k : 0][v] : T(0));
+        bool ok = true;
+        const int NF = A.NF, Q = A.Q;
+#pragma unroll 1
+        for (int lf = 0; lf < NF; ++lf) {
+            const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
+            if (f2 < 0) continue;
+            const int64_t f = f2 >> 1;
+            const int side = f2 & 1;
+            const int nq = A.fnq[f];
+            const T* pp = A.Phi + int64_t(lf) * Q * K * nc + c;
+            T p0[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) p0[k] = pp[k * nc];
+#pragma unroll 1
+            for (int q = 0; q < nq; ++q) {
+                const int qn = q + 1 < nq ? q + 1 : q;
+                T p1[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) p1[k] = pp[(int64_t(qn) * K + k) * nc];
+                T d[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) d[v] = T(0);
+                if (mode != 2) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) d[v] += p0[k] * a[k][v];
+                }
+                T val[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
+                const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+                ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
+                T* out = A.fs + ((f * 2 + side) * Q + q) * 5;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) out[v] = val[v];
+#pragma unroll
+                for (int k = 0; k < K; ++k) p0[k] = p1[k];
+            }
+        }
+    return ok;
+}
+
+// Main pass: gated cells take the linear central polynomial, the others
+// full CWENOZ.  A cell whose point states violate positivity is marked with
+// bit 7 of its flag for the fallback pass.
+template <class T, int K, bool LABEL>
+__global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= A.nc) return;
+    double ui[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
+    const int mode = (A.gate && A.gate[c]) ? 0 : 1;  // 0 linear, 1 CWENOZ
+    float lab = 0.f;
+    const bool ok = recon_cell<T, K, LABEL>(A, c, ui, mode, lab);
+    A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
+    if constexpr (LABEL) A.label[c] = lab;
+}
+
+// Fallback pass over the marked cells: gated-linear -> full CWENOZ -> first
+// order, rewriting the cell's point states (bit1 / bit2 record the steps).
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void reconstruct_fallback_kernel(ReconArgs<T> A) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= A.nc) return;
+    uint8_t fl = A.flags[c];
+    if (!(fl & 0x80)) return;
+    double ui[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
+    int mode = (fl & 1) ? 0 : 1;
+    fl &= 0x7f;
+    float lab = 0.f;
+    while (true) {
+        fl |= mode == 0 ? 2 : 4;
+        ++mode;
+        if (recon_cell<T, K, false>(A, c, ui, mode, lab) || mode == 2) break;
+    }
+    A.flags[c] = fl;
+}

@@ -37,6 +37,7 @@ struct Mesh {
     double period[3] = {0, 0, 0};
     // ---- options
     int order = 2, K = 9, qmax = 4, nfmax = 6, max_layers = 3;
+    bool uniform_type = true;  // every cell of one type
     double lambda_c = 1000.0, eps = 1e-12;
     // ---- faces (numbered by owner cell, then owner-local face)
     int64_t nf = 0, nbnd = 0;

@@ -94,170 +94,7 @@ struct ReconArgs {
 
 __device__ __forceinline__ int tri_index(int K, int k, int l) { return k * K - (k * (k - 1)) / 2 + (l - k); }
 
-// One thread per cell, all five conserved variables.
-//  (i)   stencil jumps b_m = U_m - U_i in FP64, then rounded to T
-//  (ii)  a_opt = B_c b (central, eq. lsq_system)
-//  (iii) a_s = B_s b_s per directional stencil (linear)
-//  (iv)  SI_1 = a_opt^T O a_opt, SI_s = a_s^T O_lin a_s
-//  (v)   tau = mean |SI_1 - SI_s|, w~ = lambda (1 + tau/(eps + SI)) (eq. cwenoz_weights)
-//  (vi)  Levy-Puppo-Russo blend (eq. cwenoz_poly), accumulated in one pass:
-//        abar = s1 a_opt + (tau/W) G on the linear modes, with
-//        s1 = (1 + tau/(eps+SI_1))/W, W = 1 + tau sum_s lambda_s/(eps+SI_s),
-//        G = sum_{s>=2} lambda_s (1/(eps+SI_s) - 1/(eps+SI_1)) a_s
-//  (vii) point values U_i + Phi_q . abar at the cell's face points, with the
-//        positivity fallback linear -> CWENOZ -> first order.
-template <class T, int K>
-__global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= A.nc) return;
-    const int64_t nc = A.nc;
-    double ui[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) ui[v] = A.U[v * nc + c];
-
-    T a[K][5];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) a[k][v] = T(0);
-    for (int m = 0; m < A.MC; ++m) {
-        const int64_t j = A.sten_c[m * nc + c];
-        T b[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) b[v] = T(A.U[v * nc + j] - ui[v]);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const T w = A.Bc[(int64_t(k) * A.MC + m) * nc + c];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) a[k][v] += w * b[v];
-        }
-    }
-
-    int mode = (A.gate && A.gate[c]) ? 0 : 1;  // 0 linear, 1 CWENOZ, 2 first order
-    uint8_t fl = mode == 0 ? 1 : 0;
-    float lab = 0.f;
-    while (true) {
-        T s1[5], g[3][5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            s1[v] = mode == 2 ? T(0) : T(1);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) g[k][v] = T(0);
-        }
-        const int nd = A.ndir[c];
-        if (mode == 1 && nd > 0) {
-            const T lam_s = T(1) / (A.lam_c + T(nd));
-            const T lam_1 = A.lam_c * lam_s;
-            T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                T s = T(0);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    T t = T(0);
-#pragma unroll
-                    for (int l = k + 1; l < K; ++l) t += A.O[int64_t(tri_index(K, k, l)) * nc + c] * a[l][v];
-                    s += a[k][v] * (A.O[int64_t(tri_index(K, k, k)) * nc + c] * a[k][v] + T(2) * t);
-                }
-                SI1[v] = s;
-                inv1[v] = T(1) / (A.eps + s);
-                tsum[v] = T(0);
-                Lam[v] = lam_1 * inv1[v];
-                rmin[v] = inv1[v];
-                rmax[v] = inv1[v];
-            }
-            const T o00 = A.O[0 * nc + c], o01 = A.O[1 * nc + c], o02 = A.O[2 * nc + c];
-            const T o11 = A.O[int64_t(K) * nc + c], o12 = A.O[int64_t(K + 1) * nc + c];
-            const T o22 = A.O[int64_t(2 * K - 1) * nc + c];
-            for (int s = 0; s < nd; ++s) {
-                T as[3][5];
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) as[k][v] = T(0);
-                for (int m = 0; m < A.MD; ++m) {
-                    const int64_t j = A.sten_d[(int64_t(s) * A.MD + m) * nc + c];
-                    T b[5];
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) b[v] = T(A.U[v * nc + j] - ui[v]);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const T w = A.Bd[((int64_t(s) * 3 + k) * A.MD + m) * nc + c];
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) as[k][v] += w * b[v];
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    const T x = as[0][v], y = as[1][v], z = as[2][v];
-                    const T SIs = x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z;
-                    tsum[v] += fabs(SI1[v] - SIs);
-                    const T r = T(1) / (A.eps + SIs);
-                    Lam[v] += lam_s * r;
-                    rmin[v] = fmin(rmin[v], r);
-                    rmax[v] = fmax(rmax[v], r);
-                    const T coef = lam_s * (r - inv1[v]);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) g[k][v] += coef * as[k][v];
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const T tau = tsum[v] / T(nd);
-                const T W = T(1) + tau * Lam[v];
-                s1[v] = (T(1) + tau * inv1[v]) / W;
-                const T tw = tau / W;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) g[k][v] *= tw;
-                if (A.label) {
-                    // |omega_s - lambda_s| = lambda_s |(1 + tau r_s)/W - 1|: extreme at rmin or rmax
-                    float d1 = float(fabs(lam_1 * (s1[v] - T(1))));
-                    float d2 = float(fabs(lam_s * ((T(1) + tau * rmin[v]) / W - T(1))));
-                    float d3 = float(fabs(lam_s * ((T(1) + tau * rmax[v]) / W - T(1))));
-                    lab = fmaxf(lab, fmaxf(d1, fmaxf(d2, d3)));
-                }
-            }
-        }
-        // point values at the cell's face quadrature points
-        bool ok = true;
-        for (int lf = 0; lf < A.NF; ++lf) {
-            const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
-            if (f2 < 0) continue;
-            const int64_t f = f2 >> 1;
-            const int side = f2 & 1;
-            const int nq = A.fnq[f];
-            for (int q = 0; q < nq; ++q) {
-                T d[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) d[v] = T(0);
-                if (mode != 2) {
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        const T phi = A.Phi[((int64_t(lf) * A.Q + q) * K + k) * nc + c];
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) {
-                            const T coef = k < 3 ? s1[v] * a[k][v] + g[k < 3 ? k : 0][v] : s1[v] * a[k][v];
-                            d[v] += phi * coef;
-                        }
-                    }
-                }
-                T val[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
-                const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-                ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
-                T* out = A.fs + ((f * 2 + side) * A.Q + q) * 5;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) out[v] = val[v];
-            }
-        }
-        if (ok || mode == 2) break;
-        fl |= mode == 0 ? 2 : 4;
-        ++mode;
-    }
-    if (A.flags) A.flags[c] = fl;
-    if (A.label) A.label[c] = lab;
-}
+#include "recon_kernel.hpp"
 
 // ------------------------------------------------------------------ physics
 
@@ -335,10 +172,20 @@ __device__ __forceinline__ void prim_W(const PhysT<T>& P, const T* u, T* W) {
 
 template <class T>
 __device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, T* out) {
-    const int kind = B.kind[tag];
+    // select the tag's entry with compile-time indices (a run-time index into
+    // the by-value table would move it to scratch memory)
+    int kind = UCNS_BC_TRANSMISSIVE;
+    T st[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int t = 1; t < 8; ++t)
+        if (t == tag) {
+            kind = B.kind[t];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) st[v] = B.state[t][v];
+        }
     if (kind == UCNS_BC_DIRICHLET) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) out[v] = B.state[tag][v];
+        for (int v = 0; v < 5; ++v) out[v] = st[v];
     } else if (kind == UCNS_BC_WALL) {
         out[0] = in[0];
         out[1] = -in[1];
@@ -686,8 +533,20 @@ int launch_recon_k(const Mesh& m, const Arena& ar, double gm1, const double* U, 
     A.lam_c = T(m.lambda_c);
     A.eps = T(m.eps);
     A.gm1 = T(gm1);
-    hipLaunchKernelGGL((reconstruct_kernel<T, K>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
+    if (label)
+        hipLaunchKernelGGL((reconstruct_kernel<T, K, true>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
+    else
+        hipLaunchKernelGGL((reconstruct_kernel<T, K, false>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL((reconstruct_fallback_kernel<T, K>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
     return UCNS_OK;
+}
+
+template <class T>
+int launch_recon(const Mesh& m, const Arena& ar, double gm1, const double* U, const uint8_t* gate, void* fs,
+                 uint8_t* flags, float* label, hipStream_t st) {
+    if (m.K == 9) return launch_recon_k<T, 9>(m, ar, gm1, U, gate, fs, flags, label, st);
+    if (m.K == 19) return launch_recon_k<T, 19>(m, ar, gm1, U, gate, fs, flags, label, st);
+    return UCNS_EINVAL;
 }
 
 }  // namespace
@@ -835,7 +694,7 @@ int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, doubl
 
 int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
                      const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream) {
-    UCNS_REQUIRE(mesh && phys && U && face_state, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(mesh && phys && U && face_state && flags, UCNS_EINVAL, "null argument");
     UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
     UCNS_REQUIRE(aligned(U) && aligned(face_state), UCNS_EINVAL, "device buffers must be 256-byte aligned");
     const Mesh& m = *mesh->m;
@@ -844,14 +703,8 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const uint8_t* gm = gate ? gate->mask : nullptr;
     const double gm1 = phys->gamma - 1.0;
-    int rc = UCNS_EINVAL;
-    if (precision == UCNS_F64) {
-        if (m.K == 9) rc = launch_recon_k<double, 9>(m, ar, gm1, U, gm, face_state, flags, label, st);
-        if (m.K == 19) rc = launch_recon_k<double, 19>(m, ar, gm1, U, gm, face_state, flags, label, st);
-    } else {
-        if (m.K == 9) rc = launch_recon_k<float, 9>(m, ar, gm1, U, gm, face_state, flags, label, st);
-        if (m.K == 19) rc = launch_recon_k<float, 19>(m, ar, gm1, U, gm, face_state, flags, label, st);
-    }
+    const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gm, face_state, flags, label, st)
+                                         : launch_recon<float>(m, ar, gm1, U, gm, face_state, flags, label, st);
     if (rc != UCNS_OK) {
         set_error("unsupported reconstruction order");
         return rc;

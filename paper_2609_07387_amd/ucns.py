@@ -236,6 +236,7 @@ class Workspace:
         self.face_flux = torch.empty(mesh.n_face_flux, dtype=dt, device=device)
         self.gradW = torch.empty(mesh.n_grad, dtype=dt, device=device) if viscous else None
         self.reduce = torch.empty(mesh.n_reduce, dtype=torch.float64, device=device)
+        self.flags = torch.zeros(mesh.n_cell, dtype=torch.uint8, device=device)
         self.dt = torch.zeros(1, dtype=torch.float64, device=device)
         self.ke = torch.zeros(1, dtype=torch.float64, device=device)
         self.U0 = None
@@ -296,7 +297,7 @@ class Solver:
 
     def rhs_stage(self, U):
         ws = self.ws
-        reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask)
+        reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags)
         if self.ph.viscous:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
         face_flux(self.mesh, self.ph, self.bcs, ws.face_state, ws.gradW, self.precision, ws.face_flux)
