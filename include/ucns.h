@@ -105,12 +105,27 @@ typedef struct {
     double state[8][5]; /* conserved state for UCNS_BC_DIRICHLET */
 } ucns_bc;
 
-/* Troubled-cell gate: per-cell mask (1 = smooth: take the linear central
- * polynomial and skip the directional stencils, smoothness indicators and
- * nonlinear weights).  NULL gate = full CWENOZ everywhere. */
+/* Troubled-cell gate for ucns_reconstruct.  A cell taken as smooth uses the
+ * linear central polynomial and skips the directional stencils, smoothness
+ * indicators and nonlinear weights; the others take full CWENOZ.  Either a
+ * precomputed mask (1 = smooth) or the network's parameters (the network then
+ * runs inside the reconstruction kernel on each cell's features, smooth when
+ * sigmoid(z) < theta); not both.  mask_out (may be NULL) records the
+ * network's decisions.  A NULL gate = full CWENOZ everywhere. */
 typedef struct {
-    const uint8_t* mask;  /* device [n_cell] */
+    const uint8_t* mask;  /* device [n_cell] or NULL */
+    const float* mlp;     /* device parameter block (UCNS_MLP_NPARAM floats) or NULL */
+    uint8_t* mask_out;    /* device [n_cell] or NULL */
 } ucns_gate;
+
+/* Gate network parameter block (float32) offsets: mu[16] isig[16]
+ * W1[16][64] b1[64] W2[64][64] b2[64] w3[64] b3 theta; inputs are the 12
+ * features standardised as (f - mu) * isig, W1[k][n] maps input k to hidden
+ * unit n, W2[i][n] hidden i to hidden n. */
+enum {
+    UCNS_MLP_MU = 0, UCNS_MLP_ISIG = 16, UCNS_MLP_W1 = 32, UCNS_MLP_B1 = 1056, UCNS_MLP_W2 = 1120,
+    UCNS_MLP_B2 = 5216, UCNS_MLP_W3 = 5280, UCNS_MLP_B3 = 5344, UCNS_MLP_THETA = 5345, UCNS_MLP_NPARAM = 5348
+};
 
 const char* ucns_last_error(void);
 
@@ -219,26 +234,29 @@ int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* reduce_scratch,
 
 /* ---------------------------------------------------------------- gate */
 
-/* Twelve gate features per cell from cell averages (row-major [n_cell][12],
- * float32): for v in (rho, rho E): log(1e-12 + x) of the max and mean
- * normalised central-stencil jump, the normalised central-polynomial
- * gradient, and the max/mean/min face-neighbour deviation from the linear
- * prediction. */
-int ucns_gate_features(const ucns_mesh* mesh, const double* U, float* features, ucns_stream stream);
+/* The gate is this library's addition to the paper's method: a learned
+ * troubled-cell indicator that lets smooth cells skip the work of
+ * eq. cwenoz_weights.  Twelve features per cell (row-major [n_cell][12],
+ * float32, computed in the precision's arithmetic): for v in (rho, rho E),
+ * log(1e-12 + x) of the max and mean of |v_m - v_i|/|v_i| over the central
+ * stencil, of h |grad p_opt| / |v_i|, and of the max/mean/min over face
+ * neighbours of |v_j - v_i - grad p_opt . (c_j - c_i)| /
+ * (|v_j - v_i| + h |grad p_opt| + 1e-12 |v_i|). */
+int ucns_gate_features(const ucns_mesh* mesh, const double* U, int precision, float* features, ucns_stream stream);
 
-/* MLP 12 -> 64 -> 64 -> 1 (ReLU, sigmoid output) on BF16 matrix cores with
- * FP32 accumulation.  params (device float32, packed): mu[12], sigma[12],
- * W1[64][16] (input padded to 16), b1[64], W2[64][64], b2[64], w3[64], b3[1],
- * theta[1].  ucns_gate_mask writes mask[c] = (sigmoid(z) < theta) for the
- * standardised features. */
+/* Network 12 -> 64 -> 64 -> 1 (ReLU, sigmoid output) on BF16 matrix cores
+ * with FP32 accumulation, on n feature rows: prob = sigmoid(z); ucns_gate_mask
+ * writes mask = (prob < theta), 1 = smooth. */
 int ucns_mlp_forward(const float* params, const float* features, int64_t n, float* prob, ucns_stream stream);
 int ucns_gate_mask(const float* params, const float* features, int64_t n, uint8_t* mask, ucns_stream stream);
 
-/* One training step of the MLP on a batch: forward, class-weighted binary
- * cross-entropy, backward (BF16 matrix-core products, FP32 accumulation) and
- * Adam (FP32 master weights).  grads (device float32, same packing as the
- * weights) receives the batch gradient; loss_dev the mean loss.  adam_state:
- * m and v (2 x n_params floats) and step counter handled by the caller via t. */
+/* One training step on a batch of n rows (labels 0/1 as float): forward,
+ * class-weighted binary cross-entropy (weight pos_weight on label 1),
+ * backward with BF16 matrix-core products and FP32 accumulation, and Adam
+ * (beta 0.9/0.999, eps 1e-8, FP32 master weights in params, step t >= 1).
+ * grads receives the batch gradient (parameter layout), adam_state holds m
+ * then v (2 x UCNS_MLP_NPARAM floats), loss_dev the mean loss.  Only the
+ * slots W1 .. b3 are trained; mu, isig and theta are the caller's. */
 int ucns_mlp_train_step(float* params, float* grads, float* adam_state, const float* features,
                         const float* labels, int64_t n, float pos_weight, float lr, int t, float* loss_dev,
                         ucns_stream stream);

@@ -925,6 +925,29 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     auto* fw = reinterpret_cast<T*>(base + a.fw);
     auto* fdc = reinterpret_cast<T*>(base + a.fdc);
     auto* fnq = reinterpret_cast<uint8_t*>(base + a.fnq);
+    auto* nbr = reinterpret_cast<int32_t*>(base + a.nbr);
+    auto* ndc = reinterpret_cast<T*>(base + a.ndc);
+    auto* hb = reinterpret_cast<T*>(base + a.hb);
+    auto* ncen = reinterpret_cast<uint8_t*>(base + a.ncen);
+    for (int64_t c = 0; c < nc; ++c) {
+        hb[c] = T(m.hb[c]);
+        ncen[c] = uint8_t(m.ncen[c]);
+        for (int lf = 0; lf < NF; ++lf) {
+            const int32_t fs = m.c2f[c * kMaxFaces + lf];
+            int32_t j = -1;
+            double d[3] = {0, 0, 0};
+            if (fs >= 0) {
+                const int64_t f = fs >> 1, side = fs & 1;
+                const int64_t other = m.fcell[2 * f + (1 - side)];
+                if (other >= 0) {
+                    j = int32_t(other);
+                    for (int k = 0; k < 3; ++k) d[k] = (side ? -1.0 : 1.0) * m.fdc[3 * f + k];
+                }
+            }
+            nbr[size_t(lf) * nc + c] = j;
+            for (int k = 0; k < 3; ++k) ndc[(size_t(lf) * 3 + k) * nc + c] = T(d[k]);
+        }
+    }
     std::vector<int> perm(kMaxCentral);
     for (int64_t c = 0; c < nc; ++c) {
         const int64_t* ids = &m.cand[size_t(c) * kMaxCentral];
@@ -1002,6 +1025,10 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.fw = take(ts * Q * nf);
     a.fdc = take(ts * 3 * nf);
     a.fnq = take(nf);
+    a.nbr = take(4 * NF * nc);
+    a.ndc = take(ts * NF * 3 * nc);
+    a.hb = take(ts * nc);
+    a.ncen = take(nc);
     a.bytes = off;
     if (image) {
         image->assign(a.bytes, 0);

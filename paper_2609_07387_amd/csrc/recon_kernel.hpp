@@ -13,14 +13,19 @@
 // so a wave keeps two elements' worth of loads outstanding instead of
 // waiting a full memory round trip per stencil member.
 
-template <class T, int K>
-__device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c, const double* ui, T a[K][5]) {
+// a = B_c b over the central stencil.  With FEAT, js[] also receives the max
+// and the sum of |b| for rho (js[0], js[1]) and rho E (js[2], js[3]), which
+// the gate features use (padding members contribute zero jumps).
+template <class T, int K, bool FEAT = false>
+__device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c, const double* ui, T a[K][5],
+                                               T* js = nullptr) {
     const int64_t nc = A.nc;
     const int MC = A.MC;
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int v = 0; v < 5; ++v) a[k][v] = T(0);
+    if constexpr (FEAT) js[0] = js[1] = js[2] = js[3] = T(0);
     const int32_t* sp = A.sten_c + c;
     const T* bp = A.Bc + c;
     const int64_t kstride = int64_t(MC) * nc;
@@ -46,6 +51,12 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
         T bv[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
+        if constexpr (FEAT) {
+            js[0] = fmax(js[0], fabs(bv[0]));
+            js[1] += fabs(bv[0]);
+            js[2] = fmax(js[2], fabs(bv[4]));
+            js[3] += fabs(bv[4]);
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -55,6 +66,48 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
 #pragma unroll
         for (int k = 0; k < K; ++k) b0[k] = b1[k];
         j1 = j2;
+    }
+}
+
+// Twelve gate features of a cell, for v in (rho, rho E): log(1e-12 + x) of
+//  (1) max and (2) mean of |v_m - v_i| / |v_i| over the central stencil,
+//  (3) h |grad p_opt| / |v_i| (the central polynomial's gradient at the
+//      centroid is a_lin / h),
+//  (4-6) max, mean and min over the face neighbours j of
+//      |v_j - v_i - grad p_opt . (c_j - c_i)| / (|v_j - v_i| + h |grad p_opt| + 1e-12 |v_i|).
+template <class T, int K>
+__device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, const double* ui, const T a[K][5],
+                                              const T* js, float* f) {
+    const int64_t nc = A.nc;
+    const T h = A.hb[c], ninv = T(1) / T(A.ncen[c]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int v = t ? 4 : 0;
+        const T au = fabs(T(ui[v]));
+        const T gx = a[0][v], gy = a[1][v], gz = a[2][v];
+        const T gn = sqrt(gx * gx + gy * gy + gz * gz);
+        T dmax = T(0), dsum = T(0), dmin = T(INFINITY);
+        int cnt = 0;
+        for (int lf = 0; lf < A.NF; ++lf) {
+            const int32_t j = A.nbr[int64_t(lf) * nc + c];
+            if (j < 0) continue;
+            const T dx = A.ndc[(int64_t(lf) * 3 + 0) * nc + c];
+            const T dy = A.ndc[(int64_t(lf) * 3 + 1) * nc + c];
+            const T dz = A.ndc[(int64_t(lf) * 3 + 2) * nc + c];
+            const T du = T(A.U[v * nc + j] - ui[v]);
+            const T rr = fabs(du - (gx * dx + gy * dy + gz * dz) / h) / (fabs(du) + gn + T(1e-12) * au);
+            dmax = fmax(dmax, rr);
+            dmin = fmin(dmin, rr);
+            dsum += rr;
+            ++cnt;
+        }
+        float* o = f + 6 * t;
+        o[0] = float(log(T(1e-12) + js[2 * t] / au));
+        o[1] = float(log(T(1e-12) + js[2 * t + 1] * ninv / au));
+        o[2] = float(log(T(1e-12) + gn / au));
+        o[3] = float(log(T(1e-12) + dmax));
+        o[4] = float(log(T(1e-12) + dsum / T(cnt > 0 ? cnt : 1)));
+        o[5] = float(log(T(1e-12) + (cnt > 0 ? dmin : T(0))));
     }
 }
 
@@ -70,11 +123,11 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
 //        G = sum_{s>=2} lambda_s (1/(eps+SI_s) - 1/(eps+SI_1)) a_s
 //  (vii) point values U_i + Phi_q . abar at the cell's face points, with the
 //        positivity fallback linear -> CWENOZ -> first order.
+// a holds the central coefficients on entry; it is overwritten by the blend.
 template <class T, int K, bool LABEL>
-__device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab) {
+__device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab,
+                                           T a[K][5]) {
     const int64_t nc = A.nc;
-    T a[K][5];
-    central_coeffs<T, K>(A, c, ui, a);
     T s1[5], g[3][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -257,18 +310,66 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 // Main pass: gated cells take the linear central polynomial, the others
 // full CWENOZ.  A cell whose point states violate positivity is marked with
 // bit 7 of its flag for the fallback pass.
-template <class T, int K, bool LABEL>
+//
+// GATE: the troubled-cell network runs inside this kernel.  Right after the
+// central coefficients (which it needs anyway) each cell forms its features,
+// the wave evaluates the network for its 64 cells on the matrix cores, and
+// cells with P(troubled) < theta skip the directional stencils, smoothness
+// indicators and nonlinear weights.
+template <class T, int K, bool LABEL, bool GATE>
 __global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool valid = c < A.nc;
+    double ui[5];
+    T a[K][5];
+    int mode;
+    if constexpr (GATE) {
+        __shared__ MlpWeights S;
+        __shared__ MlpWaveLds Wv[kBlock / 64];
+        mlp_stage(A.mlp, S, threadIdx.x, blockDim.x);
+        __syncthreads();
+        float f[12];
+        if (valid) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
+            T js[4];
+            central_coeffs<T, K, true>(A, c, ui, a, js);
+            gate_features<T, K>(A, c, ui, a, js, f);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) f[k] = S.mu[k];
+        }
+        const float z = mlp_wave_forward(S, Wv[threadIdx.x >> 6], f);  // all lanes of the wave
+        if (!valid) return;
+        mode = 1.f / (1.f + __expf(-z)) < S.theta ? 0 : 1;
+        if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
+    } else {
+        if (!valid) return;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
+        central_coeffs<T, K>(A, c, ui, a);
+        mode = (A.gate && A.gate[c]) ? 0 : 1;  // 0 linear, 1 CWENOZ
+    }
+    float lab = 0.f;
+    const bool ok = recon_cell<T, K, LABEL>(A, c, ui, mode, lab, a);
+    A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
+    if constexpr (LABEL) A.label[c] = lab;
+}
+
+// Gate features only ([n_cell][12] float), from the central coefficients.
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void gate_features_kernel(ReconArgs<T> A, float* out) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= A.nc) return;
     double ui[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
-    const int mode = (A.gate && A.gate[c]) ? 0 : 1;  // 0 linear, 1 CWENOZ
-    float lab = 0.f;
-    const bool ok = recon_cell<T, K, LABEL>(A, c, ui, mode, lab);
-    A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
-    if constexpr (LABEL) A.label[c] = lab;
+    T a[K][5], js[4];
+    central_coeffs<T, K, true>(A, c, ui, a, js);
+    float f[12];
+    gate_features<T, K>(A, c, ui, a, js, f);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[c * 12 + k] = f[k];
 }
 
 // Fallback pass over the marked cells: gated-linear -> full CWENOZ -> first
@@ -288,7 +389,9 @@ __global__ __launch_bounds__(kBlock) void reconstruct_fallback_kernel(ReconArgs<
     while (true) {
         fl |= mode == 0 ? 2 : 4;
         ++mode;
-        if (recon_cell<T, K, false>(A, c, ui, mode, lab) || mode == 2) break;
+        T a[K][5];
+        central_coeffs<T, K>(A, c, ui, a);
+        if (recon_cell<T, K, false>(A, c, ui, mode, lab, a) || mode == 2) break;
     }
     A.flags[c] = fl;
 }

@@ -90,10 +90,18 @@ struct ReconArgs {
     uint8_t* flags;
     float* label;
     T lam_c, eps, gm1;
+    // troubled-cell gate (network inside the kernel) and its features
+    const float* mlp;
+    uint8_t* mask_out;
+    const int32_t* nbr;
+    const T* ndc;
+    const T* hb;
+    const uint8_t* ncen;
 };
 
 __device__ __forceinline__ int tri_index(int K, int k, int l) { return k * K - (k * (k - 1)) / 2 + (l - k); }
 
+#include "mlp_kernels.hpp"
 #include "recon_kernel.hpp"
 
 // ------------------------------------------------------------------ physics
@@ -507,9 +515,9 @@ const T* arena_ptr(const Arena& a, size_t off) {
     return reinterpret_cast<const T*>(static_cast<const unsigned char*>(a.dev) + off);
 }
 
-template <class T, int K>
-int launch_recon_k(const Mesh& m, const Arena& ar, double gm1, const double* U, const uint8_t* gate, void* fs,
-                   uint8_t* flags, float* label, hipStream_t st) {
+template <class T>
+ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const double* U, const ucns_gate* gate,
+                             void* fs, uint8_t* flags, float* label) {
     ReconArgs<T> A;
     A.U = U;
     A.nc = m.nc;
@@ -526,27 +534,59 @@ int launch_recon_k(const Mesh& m, const Arena& ar, double gm1, const double* U, 
     A.fnq = arena_ptr<uint8_t>(ar, ar.fnq);
     A.Q = m.qmax;
     A.NF = m.nfmax;
-    A.gate = gate;
+    A.gate = gate ? gate->mask : nullptr;
+    A.mlp = gate ? gate->mlp : nullptr;
+    A.mask_out = gate ? gate->mask_out : nullptr;
+    A.nbr = arena_ptr<int32_t>(ar, ar.nbr);
+    A.ndc = arena_ptr<T>(ar, ar.ndc);
+    A.hb = arena_ptr<T>(ar, ar.hb);
+    A.ncen = arena_ptr<uint8_t>(ar, ar.ncen);
     A.fs = static_cast<T*>(fs);
     A.flags = flags;
     A.label = label;
     A.lam_c = T(m.lambda_c);
     A.eps = T(m.eps);
     A.gm1 = T(gm1);
-    if (label)
-        hipLaunchKernelGGL((reconstruct_kernel<T, K, true>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
-    else
-        hipLaunchKernelGGL((reconstruct_kernel<T, K, false>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
-    hipLaunchKernelGGL((reconstruct_fallback_kernel<T, K>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A);
+    return A;
+}
+
+template <class T, int K>
+int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
+    const dim3 grid(grid_for(A.nc)), block(kBlock);
+    if (A.mlp) {
+        if (A.label)
+            hipLaunchKernelGGL((reconstruct_kernel<T, K, true, true>), grid, block, 0, st, A);
+        else
+            hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
+    } else {
+        if (A.label)
+            hipLaunchKernelGGL((reconstruct_kernel<T, K, true, false>), grid, block, 0, st, A);
+        else
+            hipLaunchKernelGGL((reconstruct_kernel<T, K, false, false>), grid, block, 0, st, A);
+    }
+    hipLaunchKernelGGL((reconstruct_fallback_kernel<T, K>), grid, block, 0, st, A);
     return UCNS_OK;
 }
 
 template <class T>
-int launch_recon(const Mesh& m, const Arena& ar, double gm1, const double* U, const uint8_t* gate, void* fs,
+int launch_recon(const Mesh& m, const Arena& ar, double gm1, const double* U, const ucns_gate* gate, void* fs,
                  uint8_t* flags, float* label, hipStream_t st) {
-    if (m.K == 9) return launch_recon_k<T, 9>(m, ar, gm1, U, gate, fs, flags, label, st);
-    if (m.K == 19) return launch_recon_k<T, 19>(m, ar, gm1, U, gate, fs, flags, label, st);
+    const ReconArgs<T> A = make_recon_args<T>(m, ar, gm1, U, gate, fs, flags, label);
+    if (m.K == 9) return launch_recon_k<T, 9>(A, st);
+    if (m.K == 19) return launch_recon_k<T, 19>(A, st);
     return UCNS_EINVAL;
+}
+
+template <class T>
+int launch_features(const Mesh& m, const Arena& ar, const double* U, float* out, hipStream_t st) {
+    const ReconArgs<T> A = make_recon_args<T>(m, ar, 0.4, U, nullptr, nullptr, nullptr, nullptr);
+    if (m.K == 9)
+        hipLaunchKernelGGL((gate_features_kernel<T, 9>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A, out);
+    else if (m.K == 19)
+        hipLaunchKernelGGL((gate_features_kernel<T, 19>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A, out);
+    else
+        return UCNS_EINVAL;
+    return UCNS_OK;
 }
 
 }  // namespace
@@ -701,10 +741,10 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     const Arena& ar = m.arena[precision];
     UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const uint8_t* gm = gate ? gate->mask : nullptr;
+    UCNS_REQUIRE(!(gate && gate->mask && gate->mlp), UCNS_EINVAL, "gate: give a mask or a network, not both");
     const double gm1 = phys->gamma - 1.0;
-    const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gm, face_state, flags, label, st)
-                                         : launch_recon<float>(m, ar, gm1, U, gm, face_state, flags, label, st);
+    const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
+                                         : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);
     if (rc != UCNS_OK) {
         set_error("unsupported reconstruction order");
         return rc;
@@ -838,22 +878,45 @@ int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* scratch, double
     return hip_check("ucns_diag_ke");
 }
 
-int ucns_gate_features(const ucns_mesh*, const double*, float*, ucns_stream) {
-    set_error("gate features not available in this build");
-    return UCNS_ESTATE;
+int ucns_gate_features(const ucns_mesh* mesh, const double* U, int precision, float* features, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && U && features, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(aligned(U) && aligned(features), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    const Mesh& m = *mesh->m;
+    const Arena& ar = m.arena[precision];
+    UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int rc = precision == UCNS_F64 ? launch_features<double>(m, ar, U, features, st)
+                                         : launch_features<float>(m, ar, U, features, st);
+    if (rc != UCNS_OK) {
+        set_error("unsupported reconstruction order");
+        return rc;
+    }
+    return hip_check("ucns_gate_features");
 }
-int ucns_mlp_forward(const float*, const float*, int64_t, float*, ucns_stream) {
-    set_error("mlp not available in this build");
-    return UCNS_ESTATE;
+
+int ucns_mlp_forward(const float* params, const float* features, int64_t n, float* prob, ucns_stream stream) {
+    UCNS_REQUIRE(params && features && prob && n >= 0, UCNS_EINVAL, "bad argument");
+    if (n == 0) return UCNS_OK;
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), params, features, n, prob, nullptr);
+    return hip_check("ucns_mlp_forward");
 }
-int ucns_gate_mask(const float*, const float*, int64_t, uint8_t*, ucns_stream) {
-    set_error("mlp not available in this build");
-    return UCNS_ESTATE;
+
+int ucns_gate_mask(const float* params, const float* features, int64_t n, uint8_t* mask, ucns_stream stream) {
+    UCNS_REQUIRE(params && features && mask && n >= 0, UCNS_EINVAL, "bad argument");
+    if (n == 0) return UCNS_OK;
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), params, features, n, nullptr, mask);
+    return hip_check("ucns_gate_mask");
 }
-int ucns_mlp_train_step(float*, float*, float*, const float*, const float*, int64_t, float, float, int, float*,
-                        ucns_stream) {
-    set_error("mlp not available in this build");
-    return UCNS_ESTATE;
+
+int ucns_mlp_train_step(float* params, float* grads, float* adam_state, const float* features, const float* labels,
+                        int64_t n, float pos_weight, float lr, int t, float* loss_dev, ucns_stream stream) {
+    UCNS_REQUIRE(params && grads && adam_state && features && labels && n > 0 && t >= 1, UCNS_EINVAL, "bad argument");
+    hipLaunchKernelGGL(mlp_train_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), params, grads,
+                       adam_state, adam_state + mlp::kNParam, features, labels, n, pos_weight, lr, t, loss_dev);
+    return hip_check("ucns_mlp_train_step");
 }
 
 }  // extern "C"

@@ -1,0 +1,227 @@
+"""Troubled-cell gate: data, training and evaluation on the GPU.
+
+The gate is this project's addition to the paper's CWENOZ scheme (Sec. 2.2,
+eqs. cwenoz_poly and cwenoz_weights): a small network predicts, from twelve
+features of a cell's stencil, whether the nonlinear weights will leave the
+linear weights; cells predicted smooth take the linear central polynomial and
+skip the directional stencils, smoothness indicators and weights.
+
+Workload (shocked box): 4 x 1 x 1 box, periodic in y and z, of 148 x 37 x 37
+lattice hexes each split into 6 jittered tetrahedra (1,215,672 cells), P2,
+HLLC, Euler; a Mach-3 normal shock at x = 0.5 runs into rho = 1 + 0.2 sin 5x
++ 0.05 sin(13y + 7z), supersonic inflow at x = 0 and transmissive outflow at
+x = 4.  Labels come from plain FP64 CWENOZ runs: label = 1 when
+max |omega - lambda| over variables and stencils exceeds 0.1.
+
+Every step runs in libucns kernels: features (ucns_gate_features), labels
+(ucns_reconstruct with the label output), training (ucns_mlp_train_step: BF16
+matrix-core forward/backward + Adam), inference (ucns_mlp_forward) and the
+gated solver (the network inside ucns_reconstruct).
+"""
+from __future__ import annotations
+
+import math
+import os
+import time
+
+import numpy as np
+
+from . import inputs, ucns
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "gate_params.npy")
+
+
+def shock_box_case(seed, n=(148, 37, 37), lengths=(4.0, 1.0, 1.0)):
+    """(mesh, U0, phys, bcs) of the shocked tetrahedral box for one jitter seed."""
+    m = inputs.kuhn_tet_mesh(n, lengths, (False, True, True), 0.15, seed=seed)
+    U0 = inputs.shock_box_initial(m)
+    ph = ucns.phys(flux="hllc", viscous=False, mach=1.0)
+    rho2, u2, p2 = inputs.normal_shock_states(3.0)
+    inflow = [rho2, rho2 * u2, 0.0, 0.0, p2 / 0.4 + 0.5 * rho2 * u2 * u2]
+    bcs = ucns.bc({1: (ucns.BC_DIRICHLET, inflow), 2: (ucns.BC_TRANSMISSIVE, None)})
+    return m, U0, ph, bcs
+
+
+def collect(seed, n_cells=10000, steps=500, first=50, every=50, n=(148, 37, 37), cfl=0.5, log=print):
+    """Features and labels of `n_cells` cells sampled uniformly over the
+    sampling steps first, first+every, ..., steps of a plain FP64 CWENOZ run."""
+    import torch
+
+    m, U0, ph, bcs = shock_box_case(seed, n)
+    t0 = time.perf_counter()
+    lm = ucns.Mesh(m, order=2)
+    log(f"[gate] seed {seed}: {lm.n_cell} cells, mesh build {time.perf_counter() - t0:.1f} s")
+    solver = ucns.Solver(lm, ph, ucns.F64, bcs, cfl, label=True)
+    U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+    sample_steps = list(range(first, steps + 1, every))
+    per = n_cells // len(sample_steps)
+    rng = np.random.default_rng(1000 + seed)
+    feats = torch.empty((lm.n_cell, 12), dtype=torch.float32, device="cuda")
+    F, Y = [], []
+    for step in range(1, steps + 1):
+        solver.step(U)
+        if step in sample_steps:
+            ucns.gate_features(lm, U, ucns.F64, feats)
+            ucns.reconstruct(lm, ph, U, ucns.F64, solver.ws.face_state, None, solver.ws.flags, solver.ws.label)
+            idx = torch.from_numpy(rng.choice(lm.n_cell, per, replace=False)).cuda()
+            F.append(feats[idx].cpu().numpy())
+            Y.append((solver.ws.label[idx] > 0.1).float().cpu().numpy())
+    torch.cuda.synchronize()
+    F, Y = np.concatenate(F), np.concatenate(Y)
+    log(f"[gate] seed {seed}: {len(Y)} samples, {Y.mean():.3%} troubled")
+    return F, Y
+
+
+def standardisation(F):
+    mu = F.mean(0)
+    sd = F.std(0)
+    sd[sd < 1e-6] = 1.0
+    return mu, sd
+
+
+def init_params(mu, sd, seed=0):
+    """He-initialised parameter block (seeded), standardisation set from data."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(ucns.MLP_NPARAM, np.float32)
+    o = ucns.MLP_OFF
+    p[o["mu"]:o["mu"] + 12] = mu
+    p[o["isig"]:o["isig"] + 12] = 1.0 / sd
+    W1 = np.zeros((16, 64), np.float32)
+    W1[:12] = rng.normal(0, math.sqrt(2.0 / 12), (12, 64))
+    p[o["W1"]:o["W1"] + 1024] = W1.ravel()
+    p[o["W2"]:o["W2"] + 4096] = rng.normal(0, math.sqrt(2.0 / 64), 4096)
+    p[o["w3"]:o["w3"] + 64] = rng.normal(0, math.sqrt(1.0 / 64), 64)
+    p[o["theta"]] = 0.5
+    return p
+
+
+def train(F, Y, epochs=30, batch=1024, lr=1e-3, seed=0, log=print):
+    """Adam training of the gate on the GPU with the library's kernels."""
+    import torch
+
+    mu, sd = standardisation(F)
+    pos = max(float(Y.sum()), 1.0)
+    pos_weight = float((len(Y) - pos) / pos)
+    params = torch.tensor(init_params(mu, sd, seed), device="cuda")
+    grads = torch.zeros_like(params)
+    adam = torch.zeros(2 * ucns.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    Fd = torch.tensor(F, dtype=torch.float32, device="cuda")
+    Yd = torch.tensor(Y, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(seed)
+    t = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(len(Y))).cuda()
+        tot = 0.0
+        nb = 0
+        for s in range(0, len(Y) - batch + 1, batch):
+            idx = perm[s:s + batch]
+            fb, yb = Fd[idx].contiguous(), Yd[idx].contiguous()
+            t += 1
+            ucns.mlp_train_step(params, grads, adam, fb, yb, pos_weight, lr, t, loss)
+            tot += float(loss.item())
+            nb += 1
+        hist.append(tot / max(nb, 1))
+        if ep % 5 == 0 or ep == epochs - 1:
+            log(f"[gate] epoch {ep}: mean loss {hist[-1]:.4f}")
+    return params.cpu().numpy(), hist, pos_weight
+
+
+def predict(params, F):
+    import torch
+
+    p = torch.tensor(params, device="cuda")
+    Fd = torch.tensor(F, dtype=torch.float32, device="cuda")
+    prob = torch.empty(len(F), dtype=torch.float32, device="cuda")
+    ucns.mlp_forward(p, Fd, prob)
+    return prob.cpu().numpy()
+
+
+def calibrate_theta(params, F, Y, recall=0.995):
+    """Largest theta with troubled-cell recall >= `recall`: cells with
+    probability below theta are taken as smooth."""
+    prob = predict(params, F)
+    pt = np.sort(prob[Y > 0.5])
+    if len(pt) == 0:
+        return 0.5, prob
+    k = int(math.floor((1.0 - recall) * len(pt)))
+    return float(pt[k]), prob
+
+
+def evaluate(params, seed=6, steps=500, n=(148, 37, 37), cfl=0.5, precision=ucns.F32, log=print):
+    """Full CWENOZ against the gated solver from the same start: relative L1
+    difference after `steps` steps, fraction gated, and both throughputs."""
+    import torch
+
+    m, U0, ph, bcs = shock_box_case(seed, n)
+    lm = ucns.Mesh(m, order=2)
+    vol = torch.tensor(lm.cell_geometry()[0], device="cuda")
+    out = {}
+    P = torch.tensor(params, device="cuda")
+    res = {}
+    for name, mlp_p in (("full", None), ("gated", P)):
+        s = ucns.Solver(lm, ph, precision, bcs, cfl, mlp=mlp_p)
+        U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+        frac = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(steps):
+            s.step(U)
+            if mlp_p is not None and k % 50 == 0:
+                frac.append(s.ws.mask_out.float().mean())
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[name] = U
+        out[name] = {"cell_stage_per_s": lm.n_cell * 3 * steps / (ms / 1e3), "ms_per_step": ms / steps}
+        if frac:
+            out[name]["fraction_gated"] = float(torch.stack(frac).mean())
+    d = (res["gated"] - res["full"]).abs()
+    groups = {"rho": [0], "momentum": [1, 2, 3], "rhoE": [4]}
+    rel_l1 = {k: float((d[g] * vol).sum() / (res["full"][g].abs() * vol).sum()) for k, g in groups.items()}
+    out["rel_L1_gated_vs_full"] = max(rel_l1.values())
+    out["rel_L1_per_group"] = rel_l1
+    out["speedup"] = out["gated"]["cell_stage_per_s"] / out["full"]["cell_stage_per_s"]
+    log(f"[gate] eval seed {seed}: rel L1 {out['rel_L1_gated_vs_full']:.2e}, gated "
+        f"{out['gated'].get('fraction_gated', 0):.1%}, speedup {out['speedup']:.2f}")
+    return out
+
+
+def main():
+    """Dataset from seeds 1-5 (train 1-4, validate 5), train, calibrate, save
+    the parameters next to this module, evaluate on seed 6."""
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, nargs=3, default=[148, 37, 37])
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args()
+    n = tuple(args.n)
+    data = {s: collect(s, steps=args.steps, first=args.steps // 10, every=args.steps // 10, n=n) for s in range(1, 6)}
+    Ftr = np.concatenate([data[s][0] for s in range(1, 5)])
+    Ytr = np.concatenate([data[s][1] for s in range(1, 5)])
+    Fva, Yva = data[5]
+    params, hist, pw = train(Ftr, Ytr, epochs=args.epochs)
+    theta, prob = calibrate_theta(params, Fva, Yva)
+    params[ucns.MLP_OFF["theta"]] = theta
+    smooth_val = float((prob < theta).mean())
+    np.save(args.out, params)
+    ev = evaluate(params, steps=args.steps, n=n)
+    rep = {"train_samples": int(len(Ytr)), "val_samples": int(len(Yva)), "train_troubled": float(Ytr.mean()),
+           "pos_weight": pw, "loss_history": hist, "theta": theta, "val_fraction_smooth": smooth_val,
+           "val_recall": float((prob[Yva > 0.5] >= theta).mean()) if Yva.sum() else 1.0, "eval": ev}
+    print(json.dumps(rep))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(rep, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,7 +53,12 @@ class BC(C.Structure):
 
 
 class Gate(C.Structure):
-    _fields_ = [("mask", C.c_void_p)]
+    _fields_ = [("mask", C.c_void_p), ("mlp", C.c_void_p), ("mask_out", C.c_void_p)]
+
+
+# gate network parameter block (float32) offsets, as in include/ucns.h
+MLP_OFF = {"mu": 0, "isig": 16, "W1": 32, "b1": 1056, "W2": 1120, "b2": 5216, "w3": 5280, "b3": 5344, "theta": 5345}
+MLP_NPARAM = 5348
 
 
 _lib = None
@@ -87,7 +92,7 @@ def lib():
         L.ucns_rk_stage.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ucns_residual_rk_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
         L.ucns_diag_ke.argtypes = [vp, vp, vp, vp, vp]
-        L.ucns_gate_features.argtypes = [vp, vp, vp, vp]
+        L.ucns_gate_features.argtypes = [vp, vp, i32, vp, vp]
         L.ucns_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.ucns_gate_mask.argtypes = [vp, vp, i64, vp, vp]
         L.ucns_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i64, flt, flt, i32, vp, vp]
@@ -249,10 +254,34 @@ def dt(mesh, ph, U, cfl, scratch, dt_dev, stream=None):
     check(lib().ucns_dt(mesh.h, C.byref(ph), _dp(U), float(cfl), _dp(scratch), _dp(dt_dev), _stream(stream)))
 
 
-def reconstruct(mesh, ph, U, precision, face_state, gate_mask=None, flags=None, label=None, stream=None):
-    g = Gate(C.c_void_p(gate_mask.data_ptr())) if gate_mask is not None else None
+def reconstruct(mesh, ph, U, precision, face_state, gate_mask=None, flags=None, label=None, stream=None, mlp=None,
+                mask_out=None):
+    """gate_mask (uint8, 1 = smooth) or mlp (float32 parameter block) selects the gate."""
+    g = None
+    if gate_mask is not None or mlp is not None:
+        g = Gate(None if gate_mask is None else C.c_void_p(gate_mask.data_ptr()),
+                 None if mlp is None else C.c_void_p(mlp.data_ptr()),
+                 None if mask_out is None else C.c_void_p(mask_out.data_ptr()))
     check(lib().ucns_reconstruct(mesh.h, C.byref(ph), _dp(U), precision, None if g is None else C.byref(g),
                                  _dp(face_state), _dp(flags), _dp(label), _stream(stream)))
+
+
+def gate_features(mesh, U, precision, out, stream=None):
+    check(lib().ucns_gate_features(mesh.h, _dp(U), precision, _dp(out), _stream(stream)))
+
+
+def mlp_forward(params, feats, prob, stream=None):
+    check(lib().ucns_mlp_forward(_dp(params), _dp(feats), int(feats.shape[0]), _dp(prob), _stream(stream)))
+
+
+def gate_mask(params, feats, mask, stream=None):
+    check(lib().ucns_gate_mask(_dp(params), _dp(feats), int(feats.shape[0]), _dp(mask), _stream(stream)))
+
+
+def mlp_train_step(params, grads, adam_state, feats, labels, pos_weight, lr, t, loss, stream=None):
+    check(lib().ucns_mlp_train_step(_dp(params), _dp(grads), _dp(adam_state), _dp(feats), _dp(labels),
+                                    int(feats.shape[0]), float(pos_weight), float(lr), int(t), _dp(loss),
+                                    _stream(stream)))
 
 
 def gradients(mesh, ph, bcs, U, precision, gradW, stream=None):
@@ -285,19 +314,27 @@ def diag_ke(mesh, U, scratch, ke_dev, stream=None):
 class Solver:
     """SSP-RK3 driver over the C-ABI calls (one stream, no host syncs)."""
 
-    def __init__(self, mesh: Mesh, ph: Phys, precision=F64, bcs=None, cfl=0.5, gate_mask=None, device="cuda"):
+    def __init__(self, mesh: Mesh, ph: Phys, precision=F64, bcs=None, cfl=0.5, gate_mask=None, device="cuda",
+                 mlp=None, label=False):
+        """gate_mask: fixed per-cell mask (1 = smooth); mlp: gate network
+        parameters (device float32) evaluated inside every reconstruction;
+        label: also record max |omega - lambda| per cell (ws.label)."""
         import torch
 
         self.mesh, self.ph, self.precision, self.bcs, self.cfl = mesh, ph, precision, bcs, cfl
         if precision not in mesh.arenas:
             mesh.upload(precision, device)
         self.ws = Workspace(mesh, precision, bool(ph.viscous), device)
+        self.ws.label = torch.zeros(mesh.n_cell, dtype=torch.float32, device=device) if label else None
+        self.ws.mask_out = torch.zeros(mesh.n_cell, dtype=torch.uint8, device=device) if mlp is not None else None
         self.U0 = torch.empty((5, mesh.n_cell), dtype=torch.float64, device=device)
         self.gate_mask = gate_mask
+        self.mlp = mlp
 
     def rhs_stage(self, U):
         ws = self.ws
-        reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags)
+        reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags, ws.label,
+                    mlp=self.mlp, mask_out=ws.mask_out)
         if self.ph.viscous:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
         face_flux(self.mesh, self.ph, self.bcs, ws.face_state, ws.gradW, self.precision, ws.face_flux)

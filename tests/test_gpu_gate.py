@@ -1,0 +1,171 @@
+"""GPU tests of the troubled-cell gate: features, network forward and
+backward against the oracle, training, and the network fused into the
+reconstruction kernel."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_2609_07387_amd import gate, inputs, ucns
+from parity_helpers import as_oracle_phys
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _shock_box(n=(16, 4, 4), seed=3):
+    return gate.shock_box_case(seed, n)
+
+
+def _random_params(seed=0):
+    rng = np.random.default_rng(seed)
+    mu, sd = rng.normal(size=12) * 0.5 - 3.0, rng.uniform(0.5, 2.0, 12)
+    p = gate.init_params(mu, sd, seed)
+    o = ucns.MLP_OFF
+    p[o["b1"]:o["b1"] + 64] = rng.normal(0, 0.1, 64)
+    p[o["b2"]:o["b2"] + 64] = rng.normal(0, 0.1, 64)
+    p[o["b3"]] = 0.2
+    return p
+
+
+def test_features_parity(torch_cuda):
+    """GPU features (FP64 arena) equal the oracle's definition; FP32 arena
+    within single-precision error (log space)."""
+    torch = torch_cuda
+    m, U0, ph, bcs = _shock_box()
+    lm = ucns.Mesh(m, order=2)
+    om = oracle.OracleMesh(m, order=2)
+    ref = om.gate_features(U0, as_oracle_phys(ph))
+    U = torch.tensor(U0, device="cuda")
+    for prec in (ucns.F64, ucns.F32):
+        lm.upload(prec)
+        f = torch.empty((m.n_cell, 12), dtype=torch.float32, device="cuda")
+        ucns.gate_features(lm, U, prec, f)
+        torch.cuda.synchronize()
+        d = np.abs(f.cpu().numpy().astype(np.float64) - ref)
+        if prec == ucns.F64:
+            # float32 output of FP64 arithmetic: float32 resolution of the log values
+            assert np.all(d <= 1e-10 + 2e-7 * np.abs(ref)), d.max()
+        else:
+            # FP32 arithmetic: the face-neighbour ratios cancel, so only most
+            # entries reach single-precision agreement
+            assert np.percentile(d, 99) < 1e-3 and d.max() < 0.5, (np.percentile(d, 99), d.max())
+
+
+def test_mlp_forward_parity(torch_cuda):
+    """Matrix-core forward against the oracle with the same bf16 rounding
+    points (FP32 accumulation order differs)."""
+    torch = torch_cuda
+    p = _random_params(1)
+    rng = np.random.default_rng(2)
+    F = (rng.normal(size=(333, 12)) - 3.0).astype(np.float32)  # ragged: 333 rows
+    prob = torch.empty(len(F), dtype=torch.float32, device="cuda")
+    ucns.mlp_forward(torch.tensor(p, device="cuda"), torch.tensor(F, device="cuda"), prob)
+    z, _ = omlp.forward(p.astype(np.float64), F.astype(np.float64), emulate_bf16=True)
+    ref = omlp.sigmoid(z)
+    got = prob.cpu().numpy()
+    assert np.abs(got - ref).max() < 2e-4, np.abs(got - ref).max()
+    # the plain FP64 network differs only by bf16 rounding
+    z64, _ = omlp.forward(p.astype(np.float64), F.astype(np.float64))
+    assert np.abs(got - omlp.sigmoid(z64)).max() < 0.05
+
+
+def test_mlp_train_step_parity(torch_cuda):
+    """One training step: loss and gradient against the oracle's backward with
+    the same bf16 rounding points; the Adam update against the oracle's Adam
+    applied to the device gradient."""
+    torch = torch_cuda
+    p = _random_params(3)
+    rng = np.random.default_rng(4)
+    n = 200  # ragged: 3 full chunks of 64 and a partial one
+    F = (rng.normal(size=(n, 12)) - 3.0).astype(np.float32)
+    Y = (rng.random(n) < 0.3).astype(np.float32)
+    P = torch.tensor(p, device="cuda")
+    G = torch.zeros_like(P)
+    A = torch.zeros(2 * ucns.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    L = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ucns.mlp_train_step(P, G, A, torch.tensor(F, device="cuda"), torch.tensor(Y, device="cuda"), 2.5, 1e-3, 1, L)
+    torch.cuda.synchronize()
+    loss_ref, g_ref = omlp.loss_and_grad(p.astype(np.float64), F.astype(np.float64), Y, 2.5, emulate_bf16=True)
+    g = G.cpu().numpy().astype(np.float64)
+    assert abs(L.item() - loss_ref) < 1e-5 * max(1, loss_ref)
+    for name, a, b in (("W1", 32, 32 + 12 * 64), ("b1", 1056, 1120), ("W2", 1120, 5216), ("b2", 5216, 5280),
+                       ("w3", 5280, 5344), ("b3", 5344, 5345)):
+        err = np.abs(g[a:b] - g_ref[a:b]).max() / max(np.abs(g_ref[a:b]).max(), 1e-12)
+        assert err < 2e-2, (name, err)
+    m, v = np.zeros(omlp.N_PARAM), np.zeros(omlp.N_PARAM)
+    p_ref = omlp.adam_step(p.astype(np.float64).copy(), g, m, v, 1, 1e-3)
+    assert np.abs(P.cpu().numpy() - p_ref).max() < 1e-6
+
+
+def test_training_learns_separable_labels(torch_cuda):
+    """GPU training on a synthetic, separable labelling drives the loss down
+    and classifies held-out rows."""
+    rng = np.random.default_rng(5)
+    F = rng.normal(size=(8192, 12)).astype(np.float32)
+    Y = ((F[:, 0] + 0.5 * F[:, 3] - 0.3 * F[:, 7]) > 0.8).astype(np.float32)
+    params, hist, _ = gate.train(F[:6144], Y[:6144], epochs=25, batch=512, lr=3e-3, log=lambda *a: None)
+    assert hist[-1] < 0.4 * hist[0], hist
+    prob = gate.predict(params, F[6144:])
+    acc = ((prob > 0.5) == (Y[6144:] > 0.5)).mean()
+    assert acc > 0.95, acc
+
+
+def test_fused_gate_matches_standalone(torch_cuda):
+    """The network inside the reconstruction kernel takes the same decision as
+    features + ucns_gate_mask, and its point states equal the masked path's."""
+    torch = torch_cuda
+    m, U0, ph, bcs = _shock_box((24, 4, 4), 4)
+    lm = ucns.Mesh(m, order=2)
+    p = _random_params(6)
+    p[ucns.MLP_OFF["theta"]] = 0.5
+    P = torch.tensor(p, device="cuda")
+    U = torch.tensor(U0, device="cuda")
+    for prec in (ucns.F64, ucns.F32):
+        lm.upload(prec)
+        dt = torch.float64 if prec == ucns.F64 else torch.float32
+        fsA = torch.zeros(lm.n_face_state, dtype=dt, device="cuda")
+        fsB = torch.zeros_like(fsA)
+        flags = torch.zeros(lm.n_cell, dtype=torch.uint8, device="cuda")
+        mask_out = torch.zeros(lm.n_cell, dtype=torch.uint8, device="cuda")
+        ucns.reconstruct(lm, ph, U, prec, fsA, None, flags, mlp=P, mask_out=mask_out)
+        feats = torch.empty((lm.n_cell, 12), dtype=torch.float32, device="cuda")
+        ucns.gate_features(lm, U, prec, feats)
+        mask = torch.empty(lm.n_cell, dtype=torch.uint8, device="cuda")
+        ucns.gate_mask(P, feats, mask)
+        ucns.reconstruct(lm, ph, U, prec, fsB, mask_out, flags)
+        torch.cuda.synchronize()
+        mo, ms = mask_out.cpu().numpy(), mask.cpu().numpy()
+        assert np.array_equal(mo, ms)
+        assert 0 < mo.mean() < 1  # both branches exercised
+        assert torch.equal(fsA, fsB)
+
+
+def test_gate_end_to_end_small(torch_cuda):
+    """Dataset from plain CWENOZ runs on a small shocked box, GPU training,
+    recall calibration, and gated vs full CWENOZ: the trained gate sends most
+    cells down the linear path and stays within 1e-3 relative L1."""
+    n = (32, 6, 6)
+    data = [gate.collect(s, n_cells=2000, steps=60, first=6, every=6, n=n, log=lambda *a: None) for s in (1, 2)]
+    F = np.concatenate([d[0] for d in data])
+    Y = np.concatenate([d[1] for d in data])
+    assert 0 < Y.mean() < 0.5
+    params, hist, _ = gate.train(F, Y, epochs=30, batch=256, log=lambda *a: None)
+    theta, prob = gate.calibrate_theta(params, F, Y)
+    params[ucns.MLP_OFF["theta"]] = theta
+    assert (prob[Y > 0.5] >= theta).mean() >= 0.995
+    ev = gate.evaluate(params, seed=6, steps=60, n=n, log=lambda *a: None)
+    print(f"[gpu] small gate: theta {theta:.3g}, gated {ev['gated']['fraction_gated']:.1%}, "
+          f"rel L1 {ev['rel_L1_gated_vs_full']:.2e}", flush=True)
+    assert ev["gated"]["fraction_gated"] > 0.5
+    assert ev["rel_L1_gated_vs_full"] < 1e-3
