@@ -207,9 +207,11 @@ int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
 /* Face fluxes (Sec. 2.2, eq. fv_update and eq. viscous_gradient_penalty with
  * alpha = 4/3): F_f = |S_f| sum_q w_q (F_c(U_L, U_R; n) - F_v), HLLC or
  * Rusanov convective flux; the Gauss-point sum is a cross-lane reduction.
- * gradW may be NULL for Euler.  face_flux [n_face][5]. */
-int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const void* face_state,
-                   const void* gradW, int precision, void* face_flux, ucns_stream stream);
+ * U (device double [5][n_cell]) supplies the ghost state of transmissive
+ * boundary faces (the owner's cell average).  gradW may be NULL for Euler.
+ * face_flux [n_face][5]. */
+int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const double* U,
+                   const void* face_state, const void* gradW, int precision, void* face_flux, ucns_stream stream);
 
 /* Residual R_i = -(1/|V_i|) sum_f s_if F_f (eq. fv_update), a per-cell gather
  * over the cell's faces in fixed local order (no atomics).  R [5][n_cell]. */

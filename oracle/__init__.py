@@ -85,7 +85,7 @@ def _declare(L):
     L.oracle_cell_quadrature.argtypes = [vp, i64, vp, vp, i32]
     L.oracle_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp, vp]
     L.oracle_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, vp]
-    L.oracle_face_flux.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp]
+    L.oracle_face_flux.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp, vp]
     L.oracle_residual.argtypes = [vp, vp, vp]
     L.oracle_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp]
     L.oracle_rk_stage.argtypes = [vp, i32, dbl, vp, vp, vp]
@@ -224,11 +224,12 @@ class OracleMesh:
         _check(lib().oracle_gradients(self.h, C.byref(ph), None if bcs is None else C.byref(bcs), _p(U), _p(g)))
         return g
 
-    def face_flux(self, fs, ph, gradW=None, bcs=None):
+    def face_flux(self, U, fs, ph, gradW=None, bcs=None):
         ff = np.zeros((self.n_face, 5))
         gw = None if gradW is None else np.ascontiguousarray(gradW)
         _check(lib().oracle_face_flux(self.h, C.byref(ph), None if bcs is None else C.byref(bcs),
-                                      _p(np.ascontiguousarray(fs)), _p(gw), _p(ff)))
+                                      _p(np.ascontiguousarray(U, np.float64)), _p(np.ascontiguousarray(fs)),
+                                      _p(gw), _p(ff)))
         return ff
 
     def residual(self, ff):
@@ -247,7 +248,7 @@ class OracleMesh:
     def rhs(self, U, ph, bcs=None, gate_mask=None):
         fs = self.reconstruct(U, ph, gate_mask)
         g = self.gradients(U, ph, bcs) if ph.viscous else None
-        ff = self.face_flux(fs, ph, g, bcs)
+        ff = self.face_flux(U, fs, ph, g, bcs)
         return self.residual(ff)
 
     def kinetic_energy(self, U):

@@ -49,7 +49,8 @@ typedef struct {
 } oracle_phys;
 
 /* Boundary condition per face tag (1..7): kind 0 none, 1 Dirichlet state,
- * 2 transmissive (copy interior state), 3 no-slip adiabatic wall. */
+ * 2 transmissive (ghost = interior cell average), 3 no-slip adiabatic wall
+ * (ghost = interior point state with mirrored velocity). */
 typedef struct {
     int kind[8];
     double state[8][5];
@@ -96,8 +97,9 @@ int oracle_reconstruct(const oracle_mesh* m, const oracle_phys* ph, const double
 /* Green-Gauss gradients of (u, v, w, T): gradW [12][n_cell], row = 3*var + dir */
 int oracle_gradients(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc,
                      const double* U, double* gradW);
-/* Face fluxes [n_face][5] (owner -> neighbour, integrated over the face) */
-int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc,
+/* Face fluxes [n_face][5] (owner -> neighbour, integrated over the face); U
+ * (cell averages) supplies the transmissive boundary ghost state */
+int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, const double* U,
                      const double* face_state, const double* gradW, double* face_flux);
 /* R [5][n_cell] = -(1/|V|) sum of outward face fluxes */
 int oracle_residual(const oracle_mesh* m, const double* face_flux, double* R);

@@ -60,14 +60,17 @@ static void cwenoz_one_var(const oracle_mesh* m, int64_t c, const double* U, int
             for (int j = 0; j < st->nd[s]; ++j) t += op->Bd[s][k * st->nd[s] + j] * (U[v * nc + st->dir[s][j]] - ui);
             a_s[s][k] = t;
         }
+    /* SI is a sum of squared derivative integrals (non-negative); a rounded
+     * quadratic form below zero is rounding, clamped at zero. */
     SI[0] = 0;
     for (int k = 0; k < K; ++k)
         for (int l = 0; l < K; ++l) SI[0] += a_opt[k] * op->O[k * K + l] * a_opt[l];
+    SI[0] = fmax(SI[0], 0.0);
     for (int s = 0; s < nd; ++s) {
         double t = 0;
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l) t += a_s[s][k] * op->O[k * K + l] * a_s[s][l];
-        SI[s + 1] = t;
+        SI[s + 1] = fmax(t, 0.0);
     }
     double tau = 0;
     for (int s = 0; s < nd; ++s) tau += fabs(SI[0] - SI[s + 1]);
@@ -166,10 +169,13 @@ static void prim_W(const oracle_phys* ph, const double* u, double* W) {
     W[3] = ph->gamma * ph->mach * ph->mach * pressure(ph, u) / u[0];
 }
 
-/* Ghost state across a boundary face from the interior state (tag kinds in
- * oracle.h).  The wall ghost mirrors the full velocity (no slip). */
-static void ghost_state(const oracle_bc* bc, int tag, const double* in, const double* n, double* out) {
-    (void)n;
+/* Ghost state across a boundary face (tag kinds in oracle.h): Dirichlet takes
+ * the prescribed state; the no-slip wall mirrors the full velocity of the
+ * interior point state `in`; transmissive (zero-gradient) outflow copies the
+ * interior cell's average `avg` (zeroth-order extrapolation: copying the
+ * reconstructed point value instead feeds a one-sided extrapolation back
+ * into the boundary cell). */
+static void ghost_state(const oracle_bc* bc, int tag, const double* in, const double* avg, double* out) {
     int kind = bc ? bc->kind[tag] : 2;
     if (kind == 1) {
         memcpy(out, bc->state[tag], sizeof(double) * NV);
@@ -180,7 +186,7 @@ static void ghost_state(const oracle_bc* bc, int tag, const double* in, const do
         out[3] = -in[3];
         out[4] = in[4];
     } else {
-        memcpy(out, in, sizeof(double) * NV);
+        memcpy(out, avg, sizeof(double) * NV);
     }
 }
 
@@ -262,7 +268,7 @@ int oracle_gradients(const oracle_mesh* m, const oracle_phys* ph, const oracle_b
             if (other >= 0) {
                 for (int v = 0; v < NV; ++v) uo[v] = U[v * nc + other];
             } else {
-                ghost_state(bc, (int)(-1 - other), ui, n, uo);
+                ghost_state(bc, (int)(-1 - other), ui, ui, uo);
             }
             prim_W(ph, uo, Wo);
             for (int var = 0; var < 4; ++var)
@@ -310,14 +316,15 @@ static void viscous_flux(const oracle_phys* ph, const double* uL, const double* 
 }
 
 /* F_f = |S_f| sum_q w_q (F_c(U_L, U_R; n) - F_v) (Sec. 2.2, eq. fv_update). */
-int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, const double* face_state,
-                     const double* gradW, double* face_flux) {
+int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, const double* U,
+                     const double* face_state, const double* gradW, double* face_flux) {
     int64_t nf = m->n_face, nc = m->n_cell;
 #pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nf; ++f) {
         int64_t cL = m->fcell[2 * f], cR = m->fcell[2 * f + 1];
         const double* n = m->fnrm + 3 * f;
-        double acc[NV] = {0};
+        double acc[NV] = {0}, uavg[NV];
+        for (int v = 0; v < NV; ++v) uavg[v] = U[v * nc + cL];
         double gL[12], gR[12], Lint = 1.0;
         if (ph->viscous) {
             for (int k = 0; k < 12; ++k) gL[k] = gradW[k * nc + cL];
@@ -340,7 +347,7 @@ int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_b
             if (cR >= 0) {
                 uR = face_state + (((size_t)f * 2 + 1) * OR_QM + q) * NV;
             } else {
-                ghost_state(bc, (int)(-1 - cR), uL, n, uRb);
+                ghost_state(bc, (int)(-1 - cR), uL, uavg, uRb);
                 uR = uRb;
             }
             double F[NV];
@@ -457,7 +464,7 @@ static int eval_rhs(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc
     int rc = oracle_reconstruct(m, ph, U, gate_mask, fs, NULL, NULL);
     if (rc) return rc;
     if (ph->viscous) oracle_gradients(m, ph, bc, U, gw);
-    oracle_face_flux(m, ph, bc, fs, ph->viscous ? gw : NULL, ff);
+    oracle_face_flux(m, ph, bc, U, fs, ph->viscous ? gw : NULL, ff);
     return oracle_residual(m, ff, R);
 }
 

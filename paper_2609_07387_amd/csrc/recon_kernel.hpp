@@ -163,6 +163,8 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
+                // SI is a sum of squares: a rounded value below zero is rounding only
+                SI1[v] = fmax(SI1[v], T(0));
                 inv1[v] = T(1) / (A.eps + SI1[v]);
                 Lam[v] = lam_1 * inv1[v];
                 rmin[v] = inv1[v];
@@ -217,8 +219,9 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 #pragma unroll
                     for (int v = 0; v < 5; ++v) {
                         const T x = as[0][v], y = as[1][v], z = as[2][v];
-                        const T SIs =
-                            x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z;
+                        const T SIs = fmax(
+                            x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z,
+                            T(0));
                         tsum[v] += fabs(SI1[v] - SIs);
                         const T r = T(1) / (A.eps + SIs);
                         Lam[v] += lam_s * r;

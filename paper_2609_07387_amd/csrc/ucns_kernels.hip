@@ -178,8 +178,13 @@ __device__ __forceinline__ void prim_W(const PhysT<T>& P, const T* u, T* W) {
     W[3] = P.gM2 * pressure(P, u) * ir;
 }
 
+// Ghost state across a boundary face: Dirichlet takes the prescribed state,
+// the no-slip wall mirrors the velocity of the interior point state `in`,
+// transmissive outflow copies the interior cell average `avg` (zeroth-order
+// extrapolation; copying the reconstructed point value would feed the
+// boundary cell's one-sided extrapolation back into it).
 template <class T>
-__device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, T* out) {
+__device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, const T* avg, T* out) {
     // select the tag's entry with compile-time indices (a run-time index into
     // the by-value table would move it to scratch memory)
     int kind = UCNS_BC_TRANSMISSIVE;
@@ -202,7 +207,7 @@ __device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, T* 
         out[4] = in[4];
     } else {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) out[v] = in[v];
+        for (int v = 0; v < 5; ++v) out[v] = avg[v];
     }
 }
 
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<
 #pragma unroll
             for (int v = 0; v < 5; ++v) uo[v] = T(A.U[v * nc + other]);
         } else {
-            ghost(B, -1 - other, ui, uo);
+            ghost(B, -1 - other, ui, ui, uo);
         }
         prim_W(P, uo, Wo);
         const T s = (side ? T(-0.5) : T(0.5)) * A.farea[f];
@@ -264,6 +269,7 @@ __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<
 
 template <class T>
 struct FluxArgs {
+    const double* U;  // cell averages (transmissive ghost)
     const T* fs;
     int64_t nf, nc;
     int Q;
@@ -330,7 +336,11 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
 #pragma unroll
             for (int v = 0; v < 5; ++v) uR[v] = pR[v];
         } else {
-            ghost(B, -1 - cR, uL, uR);
+            const int32_t cL = A.fcell[2 * f];
+            T avg[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) avg[v] = T(A.U[v * A.nc + cL]);
+            ghost(B, -1 - cR, uL, avg, uR);
         }
         if (P.flux == UCNS_HLLC)
             hllc_flux(P, uL, uR, n, F);
@@ -776,9 +786,9 @@ int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
     return hip_check("ucns_gradients");
 }
 
-int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const void* face_state,
-                   const void* gradW, int precision, void* face_flux, ucns_stream stream) {
-    UCNS_REQUIRE(mesh && phys && face_state && face_flux, UCNS_EINVAL, "null argument");
+int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const double* U,
+                   const void* face_state, const void* gradW, int precision, void* face_flux, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && U && face_state && face_flux, UCNS_EINVAL, "null argument");
     UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
     UCNS_REQUIRE(!phys->viscous || gradW, UCNS_EINVAL, "viscous flux needs gradients");
     UCNS_REQUIRE(aligned(face_state) && aligned(face_flux), UCNS_EINVAL, "device buffers must be 256-byte aligned");
@@ -791,7 +801,7 @@ int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
     const int64_t nthreads = m.nf * QG;
     auto go = [&](auto zero) {
         using T = decltype(zero);
-        FluxArgs<T> A{static_cast<const T*>(face_state), m.nf, m.nc, m.qmax, arena_ptr<int32_t>(ar, ar.fcell),
+        FluxArgs<T> A{U, static_cast<const T*>(face_state), m.nf, m.nc, m.qmax, arena_ptr<int32_t>(ar, ar.fcell),
                       arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<T>(ar, ar.fw),
                       arena_ptr<T>(ar, ar.fdc), arena_ptr<uint8_t>(ar, ar.fnq), static_cast<const T*>(gradW),
                       static_cast<T*>(face_flux)};

@@ -87,7 +87,7 @@ def lib():
         L.ucns_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp, vp, vp]
         L.ucns_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, vp, vp]
         L.ucns_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, i32, vp, vp]
-        L.ucns_face_flux.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, i32, vp, vp]
+        L.ucns_face_flux.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp, i32, vp, vp]
         L.ucns_residual.argtypes = [vp, vp, i32, vp, vp]
         L.ucns_rk_stage.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ucns_residual_rk_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
@@ -289,8 +289,8 @@ def gradients(mesh, ph, bcs, U, precision, gradW, stream=None):
                                _dp(gradW), _stream(stream)))
 
 
-def face_flux(mesh, ph, bcs, face_state, gradW, precision, ff, stream=None):
-    check(lib().ucns_face_flux(mesh.h, C.byref(ph), None if bcs is None else C.byref(bcs), _dp(face_state),
+def face_flux(mesh, ph, bcs, U, face_state, gradW, precision, ff, stream=None):
+    check(lib().ucns_face_flux(mesh.h, C.byref(ph), None if bcs is None else C.byref(bcs), _dp(U), _dp(face_state),
                                _dp(gradW), precision, _dp(ff), _stream(stream)))
 
 
@@ -337,7 +337,7 @@ class Solver:
                     mlp=self.mlp, mask_out=ws.mask_out)
         if self.ph.viscous:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
-        face_flux(self.mesh, self.ph, self.bcs, ws.face_state, ws.gradW, self.precision, ws.face_flux)
+        face_flux(self.mesh, self.ph, self.bcs, U, ws.face_state, ws.gradW, self.precision, ws.face_flux)
 
     def step(self, U, ke=False):
         ws = self.ws

@@ -53,7 +53,7 @@ def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
     ucns.reconstruct(lm, ph, U, precision, fs, gm, flags)
     if ph.viscous:
         ucns.gradients(lm, ph, bcs, U, precision, gw)
-    ucns.face_flux(lm, ph, bcs, fs, gw if ph.viscous else None, precision, ff)
+    ucns.face_flux(lm, ph, bcs, U, fs, gw if ph.viscous else None, precision, ff)
     ucns.residual(lm, ff, precision, R)
     torch.cuda.synchronize()
     return (fs.double().cpu().numpy().reshape(lm.n_face, 2, lm.qmax, 5),
@@ -75,7 +75,7 @@ def gpu_run(lm, ph, U_np, precision, n_steps, cfl, bcs=None, gate_mask=None, dev
 def oracle_stage(om, ph, U, bcs=None, gate_mask=None):
     fs, flags, label = om.reconstruct(U, ph, gate_mask, with_flags=True)
     g = om.gradients(U, ph, bcs) if ph.viscous else None
-    ff = om.face_flux(fs, ph, g, bcs)
+    ff = om.face_flux(U, fs, ph, g, bcs)
     R = om.residual(ff)
     return fs, g, ff, R, flags, label
 

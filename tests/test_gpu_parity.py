@@ -200,7 +200,7 @@ def test_full_size_tgv64_sampled(torch_cuda):
     oph = as_oracle_phys(ph)
     ofs = om.reconstruct(U, oph)
     og = om.gradients(U, oph)
-    off = om.face_flux(ofs, oph, og)
+    off = om.face_flux(U, ofs, oph, og)
     oR = om.residual(off)
     vol = om.cell_data()[0]
     faces = np.unique([f2 >> 1 for c in sample for f2 in c2f[c] if f2 >= 0])

@@ -427,8 +427,8 @@ def test_green_gauss_and_viscous_flux_linear_shear():
     assert np.allclose(g[1, interior], a, rtol=1e-13)
     assert np.abs(np.delete(g[:, interior], 1, axis=0)).max() < 1e-12
     fs = om.reconstruct(U, ph, gate_mask=np.ones(om.n_cell, np.uint8))
-    fv = om.face_flux(fs, ph, g, bcs)
-    fi = om.face_flux(fs, oracle.phys(viscous=False, flux="hllc"), None, bcs)
+    fv = om.face_flux(U, fs, ph, g, bcs)
+    fi = om.face_flux(U, fs, oracle.phys(viscous=False, flux="hllc"), None, bcs)
     fd = om.face_data()
     mu = 1.0 / 50.0
     cnt = 0
