@@ -25,23 +25,29 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "cell-stage updates/s, P2 CWENO+HLLC: FP64 plain vs FP32+MLP gate; % HBM peak"
 
 
-def recon_bytes_per_cell(lm, precision, gated=False):
+def recon_bytes_per_cell(lm, precision, linear=False, gate=False):
     """Algorithmic HBM bytes of one reconstruction of one cell: every operator
     value and index read once, the cell's own state read once, its face-point
-    states written once (neighbour states are re-reads of resident data)."""
+    states and flag written once (neighbour states are re-reads of resident
+    data).  linear: the cell takes the central polynomial only (no
+    directional operators or indices).  gate: the in-kernel network's
+    per-cell inputs (face-neighbour ids and offsets, basis scale, stencil
+    size) and its mask output."""
     t = 8 if precision == 0 else 4
     K, MC, MD, ND, NF, Q = lm.K, lm.mc_pad, max(1, lm.md_pad), max(1, lm.nd_max), lm.nfmax, lm.qmax
-    ops = K * MC + K * (K + 1) // 2 + NF * Q * K + (0 if gated else ND * 3 * MD)
-    idx = MC + NF + (0 if gated else ND * MD)
-    return t * ops + 4 * idx + 1 + 40 + t * 5 * NF * Q + NF
+    ops = K * MC + NF * Q * K + (0 if linear else K * (K + 1) // 2 + ND * 3 * MD)
+    idx = MC + NF + (0 if linear else ND * MD)
+    extra = (4 * NF + 3 * NF * t + t + 4 + 1) if gate else 0
+    return t * ops + 4 * idx + 1 + 40 + t * 5 * NF * Q + NF + extra
 
 
-def step_bytes_per_cell(lm, precision, viscous=True):
-    """Algorithmic HBM bytes of one stage of the whole path per cell."""
+def step_bytes_per_cell(lm, precision, viscous=True, recon=None):
+    """Algorithmic HBM bytes of one stage of the whole path per cell (recon:
+    the reconstruction's share, default the full CWENOZ one)."""
     t = 8 if precision == 0 else 4
     faces_per_cell = lm.n_face / lm.n_cell
     Q, NF = lm.qmax, lm.nfmax
-    recon = recon_bytes_per_cell(lm, precision)
+    recon = recon_bytes_per_cell(lm, precision) if recon is None else recon
     flux = faces_per_cell * (2 * Q * 5 * t + t * (7 + Q) + 9 + 5 * t + (24 * t if viscous else 0))
     grad = (40 + 4 * NF + 12 * t + faces_per_cell * (8 + 4 * t)) if viscous else 0
     resid = 4 * NF + 5 * t * NF + 8 + 40 * 3
@@ -64,18 +70,30 @@ def time_steps(solver, U, steps, warmup, torch):
     return e0.elapsed_time(e1), wall
 
 
-def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns):
+def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns, mlp=None, mask_out=None):
+    """Mean duration of the reconstruction launch (main + fallback pass),
+    HIP events recorded on the stream the kernels are launched on."""
     s = torch.cuda.current_stream()
     for _ in range(3):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def copy_calibration(torch, nbytes=256 << 20):
+    """One plain device copy of known size (read nbytes, write nbytes) outside
+    the timed region: the reference for the HBM byte counters."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
 
 
 def cpu_baseline(seconds=12.0):
@@ -127,37 +145,55 @@ def main():
     print(f"[bench] mesh build {time.perf_counter() - t0:.1f} s, {lm.n_cell} cells, {lm.n_face} faces", file=sys.stderr,
           flush=True)
     nc = lm.n_cell
+    import numpy as np
+
+    from paper_2609_07387_amd import gate
+
+    runs = [("fp64_plain", ucns.F64, None), ("fp32", ucns.F32, None)]
+    mlp = None
+    if os.path.exists(gate.WEIGHTS):
+        mlp = torch.tensor(np.load(gate.WEIGHTS).astype(np.float32), device="cuda")
+        runs.append(("fp32_gate", ucns.F32, mlp))
     variants = {}
-    for name, prec in (("fp64_plain", ucns.F64), ("fp32", ucns.F32)):
-        solver = ucns.Solver(lm, ph, prec, cfl=0.5)
+    for name, prec, net in runs:
+        solver = ucns.Solver(lm, ph, prec, cfl=0.5, mlp=net)
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
         rate = nc * 3 * args.steps / (ms / 1e3)
-        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns)
-        rb = recon_bytes_per_cell(lm, prec) * nc
+        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns, net,
+                         solver.ws.mask_out)
+        frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
+        gate = net is not None
+        rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate)
+               + frac * recon_bytes_per_cell(lm, prec, linear=True, gate=gate))
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
-                          "recon_ms": rms, "recon_GBs": rb / (rms / 1e3) / 1e9,
-                          "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec),
-                          "path_GBs": step_bytes_per_cell(lm, prec) * rate / 1e9}
-        print(f"[bench] {name}: {rate:.3e} cell-stage/s, {ms / args.steps:.3f} ms/step, recon {rms:.3f} ms",
-              file=sys.stderr, flush=True)
+                          "recon_ms": rms, "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
+                          "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, recon=rbc),
+                          "path_GBs": step_bytes_per_cell(lm, prec, recon=rbc) * rate / 1e9}
+        if net is not None:
+            variants[name]["fraction_gated"] = frac
+        print(f"[bench] {name}: {rate:.3e} cell-stage/s, {ms / args.steps:.3f} ms/step, recon {rms:.3f} ms"
+              + (f", gated {frac:.1%}" if net is not None else ""), file=sys.stderr, flush=True)
         del solver
-    head = "fp64_plain"
+    copy_calibration(torch)
+    head = "fp32_gate" if "fp32_gate" in variants else "fp64_plain"
     hv = variants[head]
-    recon_prec = ucns.F64
-    achieved = recon_bytes_per_cell(lm, recon_prec) * nc / (hv["recon_ms"] / 1e3) / 1e9
+    kname = "reconstruct_kernel<float,9,false,true>" if head == "fp32_gate" else "reconstruct_kernel<double,9,false,false>"
+    achieved = hv["recon_GBs"]
     out = {
         "metric": METRIC, "value": hv["value"], "unit": "cell-stage updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32" if head != "fp64_plain" else "f64", "data": "synthetic",
         "config": {"workload": f"TGV {args.n}^3 periodic hex, P2 CWENOZ, HLLC, Navier-Stokes Re 1600 Mach 0.1, "
                                "Green-Gauss, SSP-RK3 CFL 0.5, per-step KE", "cells": nc, "faces": lm.n_face,
-                   "variant": head},
+                   "variant": head + (" (FP32 reconstruction/flux, FP64 state/RK/reductions, BF16 gate network)"
+                                      if head == "fp32_gate" else "")},
         "variants": variants,
-        "speedup_fp32_over_fp64": variants["fp32"]["value"] / variants["fp64_plain"]["value"],
-        "roofline": {"kernel": "reconstruct_kernel<double,9>", "bound": "hbm", "achieved": achieved,
+        "fp64_plain_value": variants["fp64_plain"]["value"],
+        "speedup_vs_fp64_plain": hv["value"] / variants["fp64_plain"]["value"],
+        "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_cell": recon_bytes_per_cell(lm, recon_prec)},
+                     "bytes_per_cell": hv["recon_bytes_per_cell"]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
