@@ -27,8 +27,11 @@
  *  - precision: UCNS_F64 (all arithmetic in FP64) or UCNS_F32 (operators,
  *    reconstruction, gradients and fluxes in FP32 with FP32 accumulation;
  *    state, residual and RK update stay FP64).
- *  - Face states: [n_face][2][QMAX][5] in the precision's type, side 0 the
- *    owner (lower cell id), side 1 the neighbour; face fluxes [n_face][5];
+ *  - Face states: each cell's point values at its own face quadrature
+ *    points, [NFMAX][QMAX][5][n_cell] (cell fastest) in the precision's type;
+ *    slot (lf, q) holds the value at point q of local face lf, the points
+ *    numbered in the owner's order on both sides of a face (owner = lower
+ *    cell id); face fluxes [n_face][5];
  *    gradients [12][n_cell] (row 3*var + dir, var in u, v, w, T).
  *  - A handle may be used by several threads for compute calls at once;
  *    ucns_mesh_upload and ucns_mesh_free must not race with other calls on it.
@@ -111,11 +114,16 @@ typedef struct {
  * precomputed mask (1 = smooth) or the network's parameters (the network then
  * runs inside the reconstruction kernel on each cell's features, smooth when
  * sigmoid(z) < theta); not both.  mask_out (may be NULL) records the
- * network's decisions.  A NULL gate = full CWENOZ everywhere. */
+ * network's decisions.  With the network, the cells it sends to full CWENOZ
+ * are listed in work (device int32 [n_cell + 64], required, 256-byte
+ * aligned, contents scratch) and reconstructed in a second pass; calls that
+ * share a work buffer must not overlap.  A NULL gate = full CWENOZ
+ * everywhere. */
 typedef struct {
     const uint8_t* mask;  /* device [n_cell] or NULL */
     const float* mlp;     /* device parameter block (UCNS_MLP_NPARAM floats) or NULL */
     uint8_t* mask_out;    /* device [n_cell] or NULL */
+    int32_t* work;        /* device [n_cell + 64], required with mlp */
 } ucns_gate;
 
 /* Gate network parameter block (float32) offsets: mu[16] isig[16]
@@ -143,7 +151,7 @@ int ucns_mesh_build(const ucns_mesh_desc* desc, const ucns_recon_opts* opts, int
 void ucns_mesh_free(ucns_mesh* mesh);
 
 /* info[0..15]: n_cell, n_face, K (unknowns), QMAX (points per face slot),
- * max faces per cell, padded central stencil, max directional stencils per
+ * NFMAX (max faces per cell), padded central stencil, max directional stencils per
  * cell, padded directional stencil, n_boundary_faces, dropped directional
  * stencils, min central stencil size, max central stencil size, order,
  * 0, 0, 0. */

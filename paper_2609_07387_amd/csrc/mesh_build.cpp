@@ -920,6 +920,7 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     auto* vol = reinterpret_cast<double*>(base + a.vol);
     auto* hdt = reinterpret_cast<double*>(base + a.hdt);
     auto* fcell = reinterpret_cast<int32_t*>(base + a.fcell);
+    auto* flf = reinterpret_cast<uint8_t*>(base + a.flf);
     auto* fnrm = reinterpret_cast<T*>(base + a.fnrm);
     auto* farea = reinterpret_cast<T*>(base + a.farea);
     auto* fw = reinterpret_cast<T*>(base + a.fw);
@@ -987,6 +988,7 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     for (int64_t f = 0; f < nf; ++f) {
         fcell[2 * f] = int32_t(m.fcell[2 * f]);
         fcell[2 * f + 1] = int32_t(m.fcell[2 * f + 1]);
+        for (int side = 0; side < 2; ++side) flf[2 * f + side] = m.flf[2 * f + side] >= 0 ? uint8_t(m.flf[2 * f + side]) : 0xff;
         for (int a = 0; a < 3; ++a) {
             fnrm[3 * f + a] = T(m.fnrm[3 * f + a]);
             fdc[3 * f + a] = T(m.fdc[3 * f + a]);
@@ -1020,6 +1022,7 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.vol = take(8 * nc);
     a.hdt = take(8 * nc);
     a.fcell = take(8 * nf);
+    a.flf = take(2 * nf);
     a.fnrm = take(ts * 3 * nf);
     a.farea = take(ts * nf);
     a.fw = take(ts * Q * nf);

@@ -124,7 +124,9 @@ __device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, 
 //  (vii) point values U_i + Phi_q . abar at the cell's face points, with the
 //        positivity fallback linear -> CWENOZ -> first order.
 // a holds the central coefficients on entry; it is overwritten by the blend.
-template <class T, int K, bool LABEL>
+// FULL = false compiles the linear and first-order paths only (mode 1 is then
+// never asked for).
+template <class T, int K, bool LABEL, bool FULL = true>
 __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab,
                                            T a[K][5]) {
     const int64_t nc = A.nc;
@@ -135,8 +137,8 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 #pragma unroll
         for (int k = 0; k < 3; ++k) g[k][v] = T(0);
     }
-        const int nd = A.ndir[c];
-        if (mode == 1 && nd > 0) {
+        const int nd = FULL ? A.ndir[c] : 0;
+        if (FULL && mode == 1 && nd > 0) {
             const T lam_s = T(1) / (A.lam_c + T(nd));
             const T lam_1 = A.lam_c * lam_s;
             T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5];
@@ -273,9 +275,7 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
         for (int lf = 0; lf < NF; ++lf) {
             const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
             if (f2 < 0) continue;
-            const int64_t f = f2 >> 1;
-            const int side = f2 & 1;
-            const int nq = A.fnq[f];
+            const int nq = A.fnq[f2 >> 1];
             const T* pp = A.Phi + int64_t(lf) * Q * K * nc + c;
             T p0[K];
 #pragma unroll
@@ -300,9 +300,10 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
                 for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
                 const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
                 ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
-                T* out = A.fs + ((f * 2 + side) * Q + q) * 5;
+                // cell-fastest slots [lf][q][v][cell]: the wave's stores are contiguous
+                T* out = A.fs + (int64_t(lf * Q + q) * 5) * nc + c;
 #pragma unroll
-                for (int v = 0; v < 5; ++v) out[v] = val[v];
+                for (int v = 0; v < 5; ++v) out[v * nc] = val[v];
 #pragma unroll
                 for (int k = 0; k < K; ++k) p0[k] = p1[k];
             }
@@ -317,11 +318,14 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 // GATE: the troubled-cell network runs inside this kernel.  Right after the
 // central coefficients (which it needs anyway) each cell forms its features,
 // the wave evaluates the network for its 64 cells on the matrix cores, and
-// cells with P(troubled) < theta skip the directional stencils, smoothness
-// indicators and nonlinear weights.
+// cells with P(troubled) < theta take the linear central polynomial here.
+// The others are appended to a work list (one atomic per wave) and get full
+// CWENOZ in reconstruct_list_kernel, so that a few troubled lanes do not hold
+// a whole wave in the directional stencils.  Each cell's result does not
+// depend on its place in the list.
 template <class T, int K, bool LABEL, bool GATE>
 __global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     const bool valid = c < A.nc;
     double ui[5];
     T a[K][5];
@@ -343,9 +347,26 @@ __global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
             for (int k = 0; k < 12; ++k) f[k] = S.mu[k];
         }
         const float z = mlp_wave_forward(S, Wv[threadIdx.x >> 6], f);  // all lanes of the wave
-        if (!valid) return;
         mode = 1.f / (1.f + __expf(-z)) < S.theta ? 0 : 1;
+        const bool listed = valid && mode == 1;
+        const uint64_t bal = __ballot(listed);
+        if (bal) {
+            const int lane = int(threadIdx.x & 63);
+            const int leader = __ffsll(static_cast<unsigned long long>(bal)) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(A.work, int(__popcll(bal)));
+            base = __shfl(base, leader);
+            if (listed)
+                A.work[kListOff + base + int(__popcll(bal & ((uint64_t(1) << lane) - 1)))] = int32_t(c);
+        }
+        if (!valid) return;
         if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
+        if (listed) return;
+        float lab = 0.f;
+        const bool ok = recon_cell<T, K, false, false>(A, c, ui, 0, lab, a);
+        A.flags[c] = uint8_t(1 | (ok ? 0 : 0x80));
+        if constexpr (LABEL) A.label[c] = 0.f;
+        return;
     } else {
         if (!valid) return;
 #pragma unroll
@@ -359,10 +380,27 @@ __global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
     if constexpr (LABEL) A.label[c] = lab;
 }
 
+// Second pass of the gated reconstruction: full CWENOZ on the listed cells.
+template <class T, int K, bool LABEL>
+__global__ __launch_bounds__(kBlock) void reconstruct_list_kernel(ReconArgs<T> A) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= A.work[0]) return;
+    const int64_t c = A.work[kListOff + i];
+    double ui[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
+    T a[K][5];
+    central_coeffs<T, K>(A, c, ui, a);
+    float lab = 0.f;
+    const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
+    A.flags[c] = uint8_t(ok ? 0 : 0x80);
+    if constexpr (LABEL) A.label[c] = lab;
+}
+
 // Gate features only ([n_cell][12] float), from the central coefficients.
 template <class T, int K>
 __global__ __launch_bounds__(kBlock) void gate_features_kernel(ReconArgs<T> A, float* out) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= A.nc) return;
     double ui[5];
 #pragma unroll
@@ -379,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void gate_features_kernel(ReconArgs<T> A, f
 // order, rewriting the cell's point states (bit1 / bit2 record the steps).
 template <class T, int K>
 __global__ __launch_bounds__(kBlock) void reconstruct_fallback_kernel(ReconArgs<T> A) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= A.nc) return;
     uint8_t fl = A.flags[c];
     if (!(fl & 0x80)) return;

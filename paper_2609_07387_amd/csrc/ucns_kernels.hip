@@ -29,6 +29,17 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
+constexpr int kListOff = 64;      // gate work list: counter in [0], cell ids from [64]
+
+// The dispatcher hands workgroups to the eight XCDs round robin (block b runs
+// on XCD b mod 8).  Renumbered this way, each XCD takes one contiguous range
+// of blocks, so a cell's stencil neighbours and the face slots that adjacent
+// cells both write mostly live in the same L2.  A bijection on [0, gridDim).
+__device__ __forceinline__ int64_t xcd_block() {
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
+    return int64_t(x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
 
 template <class T>
 struct PhysT {
@@ -93,6 +104,7 @@ struct ReconArgs {
     // troubled-cell gate (network inside the kernel) and its features
     const float* mlp;
     uint8_t* mask_out;
+    int32_t* work;  // counter + list of the cells the network sends to full CWENOZ
     const int32_t* nbr;
     const T* ndc;
     const T* hb;
@@ -229,7 +241,7 @@ struct GradArgs {
 // Green-Gauss: grad W_i = (1/|V_i|) sum_f (W_i + W_j)/2 n_f |S_f| (outward).
 template <class T>
 __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<T> P, BcT<T> B) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= A.nc) return;
     const int64_t nc = A.nc;
     T ui[5], Wi[4], g[12];
@@ -274,6 +286,7 @@ struct FluxArgs {
     int64_t nf, nc;
     int Q;
     const int32_t* fcell;
+    const uint8_t* flf;  // local face index of each side
     const T* fnrm;
     const T* farea;
     const T* fw;
@@ -318,7 +331,7 @@ __device__ void viscous_flux(const PhysT<T>& P, const T* uL, const T* uR, const 
 // sum is a butterfly over the group's lanes.
 template <class T, int QG>
 __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<T> P, BcT<T> B) {
-    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t tid = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t f = tid / QG;
     const int q = int(tid % QG);
     if (f >= A.nf) return;  // whole groups leave together
@@ -326,17 +339,17 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
     const int nq = A.fnq[f];
     if (q < nq) {
         const T n[3] = {A.fnrm[3 * f], A.fnrm[3 * f + 1], A.fnrm[3 * f + 2]};
-        const int32_t cR = A.fcell[2 * f + 1];
+        const int32_t cL = A.fcell[2 * f], cR = A.fcell[2 * f + 1];
         T uL[5], uR[5];
-        const T* pL = A.fs + ((f * 2) * A.Q + q) * 5;
+        // point states in the cell-fastest slots [lf][q][v][cell] of each side
+        const T* pL = A.fs + int64_t(A.flf[2 * f] * A.Q + q) * 5 * A.nc + cL;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) uL[v] = pL[v];
+        for (int v = 0; v < 5; ++v) uL[v] = pL[v * A.nc];
         if (cR >= 0) {
-            const T* pR = A.fs + ((f * 2 + 1) * A.Q + q) * 5;
+            const T* pR = A.fs + int64_t(A.flf[2 * f + 1] * A.Q + q) * 5 * A.nc + cR;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) uR[v] = pR[v];
+            for (int v = 0; v < 5; ++v) uR[v] = pR[v * A.nc];
         } else {
-            const int32_t cL = A.fcell[2 * f];
             T avg[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) avg[v] = T(A.U[v * A.nc + cL]);
@@ -347,7 +360,6 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         else
             rusanov_flux(P, uL, uR, n, F);
         if (P.viscous) {
-            const int32_t cL = A.fcell[2 * f];
             T gL[12], gR[12], Fv[5];
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
@@ -394,7 +406,7 @@ struct ResArgs {
 // R_i = -(1/|V_i|) sum_f s_if F_f over the cell's faces in local order.
 template <class T, bool RK>
 __global__ __launch_bounds__(kBlock) void residual_kernel(ResArgs<T> A) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= A.nc) return;
     double acc[5] = {0, 0, 0, 0, 0};
     for (int lf = 0; lf < A.NF; ++lf) {
@@ -547,6 +559,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.gate = gate ? gate->mask : nullptr;
     A.mlp = gate ? gate->mlp : nullptr;
     A.mask_out = gate ? gate->mask_out : nullptr;
+    A.work = gate ? gate->work : nullptr;
     A.nbr = arena_ptr<int32_t>(ar, ar.nbr);
     A.ndc = arena_ptr<T>(ar, ar.ndc);
     A.hb = arena_ptr<T>(ar, ar.hb);
@@ -560,14 +573,20 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     return A;
 }
 
+__global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
+
 template <class T, int K>
 int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
     const dim3 grid(grid_for(A.nc)), block(kBlock);
     if (A.mlp) {
-        if (A.label)
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, st, A.work);
+        if (A.label) {
             hipLaunchKernelGGL((reconstruct_kernel<T, K, true, true>), grid, block, 0, st, A);
-        else
+            hipLaunchKernelGGL((reconstruct_list_kernel<T, K, true>), grid, block, 0, st, A);
+        } else {
             hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
+            hipLaunchKernelGGL((reconstruct_list_kernel<T, K, false>), grid, block, 0, st, A);
+        }
     } else {
         if (A.label)
             hipLaunchKernelGGL((reconstruct_kernel<T, K, true, false>), grid, block, 0, st, A);
@@ -720,7 +739,7 @@ int ucns_workspace_elems(const ucns_mesh* mesh, int64_t* face_state, int64_t* fa
                          int64_t* reduce_scratch) {
     UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
     const Mesh& m = *mesh->m;
-    if (face_state) *face_state = m.nf * 2 * m.qmax * 5;
+    if (face_state) *face_state = int64_t(m.nfmax) * m.qmax * 5 * m.nc;
     if (face_flux) *face_flux = m.nf * 5;
     if (gradW) *gradW = 12 * m.nc;
     if (reduce_scratch) *reduce_scratch = kRedBlocks;
@@ -752,6 +771,8 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     UCNS_REQUIRE(!(gate && gate->mask && gate->mlp), UCNS_EINVAL, "gate: give a mask or a network, not both");
+    UCNS_REQUIRE(!(gate && gate->mlp) || (gate->work && aligned(gate->work)), UCNS_EINVAL,
+                 "gate: the network needs a 256-byte aligned work buffer");
     const double gm1 = phys->gamma - 1.0;
     const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
                                          : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);
@@ -802,7 +823,7 @@ int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
     auto go = [&](auto zero) {
         using T = decltype(zero);
         FluxArgs<T> A{U, static_cast<const T*>(face_state), m.nf, m.nc, m.qmax, arena_ptr<int32_t>(ar, ar.fcell),
-                      arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<T>(ar, ar.fw),
+                      arena_ptr<uint8_t>(ar, ar.flf), arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<T>(ar, ar.fw),
                       arena_ptr<T>(ar, ar.fdc), arena_ptr<uint8_t>(ar, ar.fnq), static_cast<const T*>(gradW),
                       static_cast<T*>(face_flux)};
         if (QG == 4)

@@ -13,6 +13,12 @@ HLLC, Euler; a Mach-3 normal shock at x = 0.5 runs into rho = 1 + 0.2 sin 5x
 x = 4.  Labels come from plain FP64 CWENOZ runs: label = 1 when
 max |omega - lambda| over variables and stencils exceeds 0.1.
 
+Smooth flows (Taylor-Green vortex at Mach 0.1, Navier-Stokes Re 1600, on a
+32^3 periodic hex cube and on a 24^3 x 6 jittered periodic tet cube with 1 %
+velocity noise) add samples from the same plain runs, so that the network has
+seen low-Mach vortical flow, where the shocked box has no cells; a 48^3 hex
+cube is held out to check that the gate lets such flow through.
+
 Every step runs in libucns kernels: features (ucns_gate_features), labels
 (ucns_reconstruct with the label output), training (ucns_mlp_train_step: BF16
 matrix-core forward/backward + Adam), inference (ucns_mlp_forward) and the
@@ -43,23 +49,39 @@ def shock_box_case(seed, n=(148, 37, 37), lengths=(4.0, 1.0, 1.0)):
     return m, U0, ph, bcs
 
 
-def collect(seed, n_cells=10000, steps=500, first=50, every=50, n=(148, 37, 37), cfl=0.5, log=print):
-    """Features and labels of `n_cells` cells sampled uniformly over the
-    sampling steps first, first+every, ..., steps of a plain FP64 CWENOZ run."""
+SMOOTH_CASES = ("tgv_hex32", "tgv_tet24", "tgv_hex48")
+
+
+def smooth_case(name):
+    """(mesh, U0, phys, bcs) of a smooth periodic Taylor-Green run."""
+    L = 2.0 * math.pi
+    if name.startswith("tgv_hex"):
+        m = inputs.periodic_hex_mesh(int(name[7:]))
+        U0 = inputs.tgv_initial(m)
+    elif name == "tgv_tet24":
+        m = inputs.kuhn_tet_mesh((24, 24, 24), (L, L, L), (True, True, True), 0.15, seed=7)
+        U0 = inputs.tgv_initial(m, noise_seed=1007)
+    else:
+        raise ValueError(name)
+    return m, U0, ucns.phys(flux="hllc", viscous=True, mach=0.1, reynolds=1600.0), None
+
+
+def _collect_run(case, tag, n_cells, sample_steps, rng_seed, cfl, log):
+    """Features and labels of `n_cells` cells drawn uniformly over the given
+    steps of a plain FP64 CWENOZ run of `case` = (mesh, U0, phys, bcs)."""
     import torch
 
-    m, U0, ph, bcs = shock_box_case(seed, n)
+    m, U0, ph, bcs = case
     t0 = time.perf_counter()
     lm = ucns.Mesh(m, order=2)
-    log(f"[gate] seed {seed}: {lm.n_cell} cells, mesh build {time.perf_counter() - t0:.1f} s")
+    log(f"[gate] {tag}: {lm.n_cell} cells, mesh build {time.perf_counter() - t0:.1f} s")
     solver = ucns.Solver(lm, ph, ucns.F64, bcs, cfl, label=True)
     U = torch.tensor(U0, dtype=torch.float64, device="cuda")
-    sample_steps = list(range(first, steps + 1, every))
     per = n_cells // len(sample_steps)
-    rng = np.random.default_rng(1000 + seed)
+    rng = np.random.default_rng(rng_seed)
     feats = torch.empty((lm.n_cell, 12), dtype=torch.float32, device="cuda")
     F, Y = [], []
-    for step in range(1, steps + 1):
+    for step in range(1, max(sample_steps) + 1):
         solver.step(U)
         if step in sample_steps:
             ucns.gate_features(lm, U, ucns.F64, feats)
@@ -69,8 +91,19 @@ def collect(seed, n_cells=10000, steps=500, first=50, every=50, n=(148, 37, 37),
             Y.append((solver.ws.label[idx] > 0.1).float().cpu().numpy())
     torch.cuda.synchronize()
     F, Y = np.concatenate(F), np.concatenate(Y)
-    log(f"[gate] seed {seed}: {len(Y)} samples, {Y.mean():.3%} troubled")
+    log(f"[gate] {tag}: {len(Y)} samples, {Y.mean():.3%} troubled")
     return F, Y
+
+
+def collect(seed, n_cells=10000, steps=500, first=50, every=50, n=(148, 37, 37), cfl=0.5, log=print):
+    """Shocked-box samples of one jitter seed at steps first, first+every, ..., steps."""
+    return _collect_run(shock_box_case(seed, n), f"seed {seed}", n_cells, list(range(first, steps + 1, every)),
+                        1000 + seed, cfl, log)
+
+
+def collect_smooth(name, n_cells=10000, steps=(1, 2, 5, 10, 20, 50, 100, 150, 200), cfl=0.5, log=print):
+    """Smooth-flow samples of one Taylor-Green case (see SMOOTH_CASES)."""
+    return _collect_run(smooth_case(name), name, n_cells, list(steps), 2000 + SMOOTH_CASES.index(name), cfl, log)
 
 
 def standardisation(F):
@@ -150,12 +183,15 @@ def calibrate_theta(params, F, Y, recall=0.995):
     return float(pt[k]), prob
 
 
-def evaluate(params, seed=6, steps=500, n=(148, 37, 37), cfl=0.5, precision=ucns.F32, log=print):
+def evaluate(params, seed=6, steps=500, n=(148, 37, 37), cfl=0.5, precision=ucns.F32, case=None, tag=None,
+             log=print):
     """Full CWENOZ against the gated solver from the same start: relative L1
-    difference after `steps` steps, fraction gated, and both throughputs."""
+    difference after `steps` steps, fraction gated, and both throughputs.
+    The case is the shocked box of `seed` unless `case` is given."""
     import torch
 
-    m, U0, ph, bcs = shock_box_case(seed, n)
+    m, U0, ph, bcs = shock_box_case(seed, n) if case is None else case
+    tag = f"seed {seed}" if tag is None else tag
     lm = ucns.Mesh(m, order=2)
     vol = torch.tensor(lm.cell_geometry()[0], device="cuda")
     out = {}
@@ -185,14 +221,16 @@ def evaluate(params, seed=6, steps=500, n=(148, 37, 37), cfl=0.5, precision=ucns
     out["rel_L1_gated_vs_full"] = max(rel_l1.values())
     out["rel_L1_per_group"] = rel_l1
     out["speedup"] = out["gated"]["cell_stage_per_s"] / out["full"]["cell_stage_per_s"]
-    log(f"[gate] eval seed {seed}: rel L1 {out['rel_L1_gated_vs_full']:.2e}, gated "
+    log(f"[gate] eval {tag}: rel L1 {out['rel_L1_gated_vs_full']:.2e}, gated "
         f"{out['gated'].get('fraction_gated', 0):.1%}, speedup {out['speedup']:.2f}")
     return out
 
 
 def main():
-    """Dataset from seeds 1-5 (train 1-4, validate 5), train, calibrate, save
-    the parameters next to this module, evaluate on seed 6."""
+    """Dataset from shocked-box seeds 1-5 (train 1-4, validate 5) and the
+    smooth cases (train hex32 and tet24, hold out hex48), train, calibrate,
+    save the parameters next to this module, evaluate on seed 6 and on the
+    64^3 hex Taylor-Green vortex."""
     import argparse
     import json
 
@@ -205,18 +243,24 @@ def main():
     args = ap.parse_args()
     n = tuple(args.n)
     data = {s: collect(s, steps=args.steps, first=args.steps // 10, every=args.steps // 10, n=n) for s in range(1, 6)}
-    Ftr = np.concatenate([data[s][0] for s in range(1, 5)])
-    Ytr = np.concatenate([data[s][1] for s in range(1, 5)])
+    smooth = {c: collect_smooth(c) for c in SMOOTH_CASES}
+    Ftr = np.concatenate([data[s][0] for s in range(1, 5)] + [smooth[c][0] for c in SMOOTH_CASES[:2]])
+    Ytr = np.concatenate([data[s][1] for s in range(1, 5)] + [smooth[c][1] for c in SMOOTH_CASES[:2]])
     Fva, Yva = data[5]
     params, hist, pw = train(Ftr, Ytr, epochs=args.epochs)
     theta, prob = calibrate_theta(params, Fva, Yva)
     params[ucns.MLP_OFF["theta"]] = theta
     smooth_val = float((prob < theta).mean())
+    Fho, Yho = smooth[SMOOTH_CASES[2]]
+    prob_ho = predict(params, Fho)
     np.save(args.out, params)
     ev = evaluate(params, steps=args.steps, n=n)
+    ev_tgv = evaluate(params, steps=200, case=smooth_case("tgv_hex64"), tag="tgv_hex64")
     rep = {"train_samples": int(len(Ytr)), "val_samples": int(len(Yva)), "train_troubled": float(Ytr.mean()),
            "pos_weight": pw, "loss_history": hist, "theta": theta, "val_fraction_smooth": smooth_val,
-           "val_recall": float((prob[Yva > 0.5] >= theta).mean()) if Yva.sum() else 1.0, "eval": ev}
+           "val_recall": float((prob[Yva > 0.5] >= theta).mean()) if Yva.sum() else 1.0,
+           "holdout_tgv_hex48": {"troubled": float(Yho.mean()), "fraction_smooth": float((prob_ho < theta).mean())},
+           "eval": ev, "eval_tgv_hex64": ev_tgv}
     print(json.dumps(rep))
     if args.report:
         with open(args.report, "w") as f:

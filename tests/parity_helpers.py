@@ -39,6 +39,20 @@ def lib_arrays(lm, precision, device="cuda"):
     return fs, ff, gw, R
 
 
+def face_major(lm, fs_cells):
+    """Library face states [NFMAX][Q][5][n_cell] (cell fastest) as
+    [n_face][2][Q][5] (NaN where a face has no such side)."""
+    c2f, _, _, _ = lm.faces()
+    NF, Q, nc = lm.nfmax, lm.qmax, lm.n_cell
+    fsc = np.asarray(fs_cells).reshape(NF, Q, 5, nc)
+    out = np.full((lm.n_face, 2, Q, 5), np.nan)
+    for lf in range(NF):
+        f2 = c2f[:, lf].astype(np.int64)
+        ok = f2 >= 0
+        out[f2[ok] >> 1, f2[ok] & 1] = fsc[lf].transpose(2, 0, 1)[ok]
+    return out
+
+
 def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
     """One residual evaluation on the GPU; returns host copies of
     (face_state [nf,2,Q,5], gradW [12,nc] or None, face_flux [nf,5], R [5,nc], flags)."""
@@ -56,7 +70,7 @@ def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
     ucns.face_flux(lm, ph, bcs, U, fs, gw if ph.viscous else None, precision, ff)
     ucns.residual(lm, ff, precision, R)
     torch.cuda.synchronize()
-    return (fs.double().cpu().numpy().reshape(lm.n_face, 2, lm.qmax, 5),
+    return (face_major(lm, fs.double().cpu().numpy()),
             gw.double().cpu().numpy().reshape(12, lm.n_cell) if ph.viscous else None,
             ff.double().cpu().numpy().reshape(lm.n_face, 5), R.cpu().numpy(), flags.cpu().numpy())
 
