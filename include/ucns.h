@@ -114,16 +114,14 @@ typedef struct {
  * precomputed mask (1 = smooth) or the network's parameters (the network then
  * runs inside the reconstruction kernel on each cell's features, smooth when
  * sigmoid(z) < theta); not both.  mask_out (may be NULL) records the
- * network's decisions.  With the network, the cells it sends to full CWENOZ
- * are listed in work (device int32 [n_cell + 64], required, 256-byte
- * aligned, contents scratch) and reconstructed in a second pass; calls that
- * share a work buffer must not overlap.  A NULL gate = full CWENOZ
- * everywhere. */
+ * network's decisions.  A NULL gate = full CWENOZ everywhere.  With a gate,
+ * the cells left for full CWENOZ are taken one at a time by their whole wave
+ * (one lane per directional stencil member), so a few troubled cells do not
+ * hold a wave in the directional stencils; labels are not produced. */
 typedef struct {
     const uint8_t* mask;  /* device [n_cell] or NULL */
     const float* mlp;     /* device parameter block (UCNS_MLP_NPARAM floats) or NULL */
     uint8_t* mask_out;    /* device [n_cell] or NULL */
-    int32_t* work;        /* device [n_cell + 64], required with mlp */
 } ucns_gate;
 
 /* Gate network parameter block (float32) offsets: mu[16] isig[16]
@@ -203,7 +201,8 @@ int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, doubl
  * order, run as a second pass over the cells that need it; flags[c]
  * (device [n_cell], required) records bit0 linear taken, bit1 CWENOZ
  * fallback, bit2 first-order fallback.  label (device float [n_cell],
- * may be NULL) receives max over variables and stencils of |omega - lambda|. */
+ * may be NULL; only without a gate) receives max over variables and stencils
+ * of |omega - lambda|. */
 int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
                      const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream);
 

@@ -123,278 +123,401 @@ __device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, 
 //        G = sum_{s>=2} lambda_s (1/(eps+SI_s) - 1/(eps+SI_1)) a_s
 //  (vii) point values U_i + Phi_q . abar at the cell's face points, with the
 //        positivity fallback linear -> CWENOZ -> first order.
-// a holds the central coefficients on entry; it is overwritten by the blend.
-// FULL = false compiles the linear and first-order paths only (mode 1 is then
-// never asked for).
-template <class T, int K, bool LABEL, bool FULL = true>
-__device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab,
-                                           T a[K][5]) {
+
+// SI_1 = a^T O a with O stored as its upper triangle; a sum of squares, so a
+// rounded value below zero is rounding only and is clamped.
+template <class T, int K>
+__device__ __forceinline__ void si_opt(const ReconArgs<T>& A, int64_t c, const T a[K][5], T SI1[5]) {
+    const int64_t nc = A.nc;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) SI1[v] = T(0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const T okk = A.O[int64_t(tri_index(K, k, k)) * nc + c];
+        T t[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) t[v] = okk * a[k][v];
+#pragma unroll
+        for (int l = k + 1; l < K; ++l) {
+            const T o2 = T(2) * A.O[int64_t(tri_index(K, k, l)) * nc + c];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) t[v] += o2 * a[l][v];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) SI1[v] += a[k][v] * t[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) SI1[v] = fmax(SI1[v], T(0));
+}
+
+// Point values at the cell's face quadrature points (step vii) from the
+// coefficients a (first order when mode == 2), stored in the cell-fastest
+// slots [lf][q][v][cell] so that a wave's stores are contiguous; returns
+// whether density and pressure are positive at all of them.
+template <class T, int K>
+__device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, const double* ui, int mode,
+                                            const T a[K][5]) {
+    const int64_t nc = A.nc;
+    bool ok = true;
+    const int NF = A.NF, Q = A.Q;
+#pragma unroll 1
+    for (int lf = 0; lf < NF; ++lf) {
+        const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
+        if (f2 < 0) continue;
+        const int nq = A.fnq[f2 >> 1];
+        const T* pp = A.Phi + int64_t(lf) * Q * K * nc + c;
+        T p0[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) p0[k] = pp[k * nc];
+#pragma unroll 1
+        for (int q = 0; q < nq; ++q) {
+            const int qn = q + 1 < nq ? q + 1 : q;
+            T p1[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) p1[k] = pp[(int64_t(qn) * K + k) * nc];
+            T d[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) d[v] = T(0);
+            if (mode != 2) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) d[v] += p0[k] * a[k][v];
+            }
+            T val[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
+            const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+            ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
+            T* out = A.fs + (int64_t(lf * Q + q) * 5) * nc + c;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) out[v * nc] = val[v];
+#pragma unroll
+            for (int k = 0; k < K; ++k) p0[k] = p1[k];
+        }
+    }
+    return ok;
+}
+
+// One lane per cell: steps (iii)-(vi) for a cell with nd > 0 directional
+// stencils.  a holds the central coefficients on entry; it is overwritten by
+// the blend.
+template <class T, int K, bool LABEL>
+__device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c, const double* ui, int nd, float& lab,
+                                               T a[K][5]) {
     const int64_t nc = A.nc;
     T s1[5], g[3][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        s1[v] = mode == 2 ? T(0) : T(1);
+        s1[v] = T(1);
 #pragma unroll
         for (int k = 0; k < 3; ++k) g[k][v] = T(0);
     }
-        const int nd = FULL ? A.ndir[c] : 0;
-        if (FULL && mode == 1 && nd > 0) {
-            const T lam_s = T(1) / (A.lam_c + T(nd));
-            const T lam_1 = A.lam_c * lam_s;
-            T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5];
+    {
+        const T lam_s = T(1) / (A.lam_c + T(nd));
+        const T lam_1 = A.lam_c * lam_s;
+        T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5];
+        si_opt<T, K>(A, c, a, SI1);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                SI1[v] = T(0);
-                tsum[v] = T(0);
-            }
-            // SI_1 = a^T O a with O stored as its upper triangle
+        for (int v = 0; v < 5; ++v) {
+            tsum[v] = T(0);
+            inv1[v] = T(1) / (A.eps + SI1[v]);
+            Lam[v] = lam_1 * inv1[v];
+            rmin[v] = inv1[v];
+            rmax[v] = inv1[v];
+        }
+        const T o00 = A.O[0 * nc + c], o01 = A.O[1 * nc + c], o02 = A.O[2 * nc + c];
+        const T o11 = A.O[int64_t(K) * nc + c], o12 = A.O[int64_t(K + 1) * nc + c];
+        const T o22 = A.O[int64_t(2 * K - 1) * nc + c];
+        // all directional members as one pipelined stream t = s * MD + m
+        const int MD = A.MD, total = nd * MD;
+        const int32_t* sp = A.sten_d + c;
+        const T* bp = A.Bd + c;
+        const int64_t kstride = int64_t(MD) * nc;  // between the 3 rows of one stencil
+        int32_t j1 = sp[int64_t(total > 1 ? 1 : 0) * nc];
+        const int32_t j0 = sp[0];
+        double u0[5];
+        T b0[3];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const T okk = A.O[int64_t(tri_index(K, k, k)) * nc + c];
-                T t[5];
+        for (int v = 0; v < 5; ++v) u0[v] = A.U[v * nc + j0];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) t[v] = okk * a[k][v];
+        for (int k = 0; k < 3; ++k) b0[k] = bp[k * kstride];
+        T as[3][5];
 #pragma unroll
-                for (int l = k + 1; l < K; ++l) {
-                    const T o2 = T(2) * A.O[int64_t(tri_index(K, k, l)) * nc + c];
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) t[v] += o2 * a[l][v];
-                }
+            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+        int m = 0, s = 0;
+#pragma unroll 1
+        for (int t = 0; t < total; ++t) {
+            // element t+1 is (s, m+1) or (s+1, 0); its operator rows sit at
+            // (3 s' + k) MD + m' = t' + 2 s' MD + k MD for t' = s' MD + m'
+            const int tn = t + 1 < total ? t + 1 : t;
+            const int sn = (m + 1 < MD) ? s : s + 1;
+            const int sn_c = t + 1 < total ? sn : s;
+            const int t2 = t + 2 < total ? t + 2 : tn;
+            const int32_t j2 = sp[int64_t(t2) * nc];
+            double u1[5];
+            T b1[3];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) SI1[v] += a[k][v] * t[v];
-            }
+            for (int v = 0; v < 5; ++v) u1[v] = A.U[v * nc + j1];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                // SI is a sum of squares: a rounded value below zero is rounding only
-                SI1[v] = fmax(SI1[v], T(0));
-                inv1[v] = T(1) / (A.eps + SI1[v]);
-                Lam[v] = lam_1 * inv1[v];
-                rmin[v] = inv1[v];
-                rmax[v] = inv1[v];
-            }
-            const T o00 = A.O[0 * nc + c], o01 = A.O[1 * nc + c], o02 = A.O[2 * nc + c];
-            const T o11 = A.O[int64_t(K) * nc + c], o12 = A.O[int64_t(K + 1) * nc + c];
-            const T o22 = A.O[int64_t(2 * K - 1) * nc + c];
-            // all directional members as one pipelined stream t = s * MD + m
-            const int MD = A.MD, total = nd * MD;
-            const int32_t* sp = A.sten_d + c;
-            const T* bp = A.Bd + c;
-            const int64_t kstride = int64_t(MD) * nc;  // between the 3 rows of one stencil
-            int32_t j1 = sp[int64_t(total > 1 ? 1 : 0) * nc];
-            const int32_t j0 = sp[0];
-            double u0[5];
-            T b0[3];
+            for (int k = 0; k < 3; ++k) b1[k] = bp[int64_t(tn + 2 * sn_c * MD) * nc + k * kstride];
+            T bv[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) u0[v] = A.U[v * nc + j0];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) b0[k] = bp[k * kstride];
-            T as[3][5];
+            for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) as[k][v] = T(0);
-            int m = 0, s = 0;
-#pragma unroll 1
-            for (int t = 0; t < total; ++t) {
-                // element t+1 is (s, m+1) or (s+1, 0); its operator rows sit at
-                // (3 s' + k) MD + m' = t' + 2 s' MD + k MD for t' = s' MD + m'
-                const int tn = t + 1 < total ? t + 1 : t;
-                const int sn = (m + 1 < MD) ? s : s + 1;
-                const int sn_c = t + 1 < total ? sn : s;
-                const int t2 = t + 2 < total ? t + 2 : tn;
-                const int32_t j2 = sp[int64_t(t2) * nc];
-                double u1[5];
-                T b1[3];
+                for (int v = 0; v < 5; ++v) as[k][v] += b0[k] * bv[v];
+            if (m + 1 == MD) {
+                // stencil s complete: its indicator and its share of the blend
 #pragma unroll
-                for (int v = 0; v < 5; ++v) u1[v] = A.U[v * nc + j1];
+                for (int v = 0; v < 5; ++v) {
+                    const T x = as[0][v], y = as[1][v], z = as[2][v];
+                    const T SIs = fmax(
+                        x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z,
+                        T(0));
+                    tsum[v] += fabs(SI1[v] - SIs);
+                    const T r = T(1) / (A.eps + SIs);
+                    Lam[v] += lam_s * r;
+                    rmin[v] = fmin(rmin[v], r);
+                    rmax[v] = fmax(rmax[v], r);
+                    const T coef = lam_s * (r - inv1[v]);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) b1[k] = bp[int64_t(tn + 2 * sn_c * MD) * nc + k * kstride];
-                T bv[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) as[k][v] += b0[k] * bv[v];
-                if (m + 1 == MD) {
-                    // stencil s complete: its indicator and its share of the blend
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) {
-                        const T x = as[0][v], y = as[1][v], z = as[2][v];
-                        const T SIs = fmax(
-                            x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z,
-                            T(0));
-                        tsum[v] += fabs(SI1[v] - SIs);
-                        const T r = T(1) / (A.eps + SIs);
-                        Lam[v] += lam_s * r;
-                        rmin[v] = fmin(rmin[v], r);
-                        rmax[v] = fmax(rmax[v], r);
-                        const T coef = lam_s * (r - inv1[v]);
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            g[k][v] += coef * as[k][v];
-                            as[k][v] = T(0);
-                        }
+                    for (int k = 0; k < 3; ++k) {
+                        g[k][v] += coef * as[k][v];
+                        as[k][v] = T(0);
                     }
-                    m = 0;
-                    ++s;
-                } else {
-                    ++m;
                 }
-#pragma unroll
-                for (int v = 0; v < 5; ++v) u0[v] = u1[v];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) b0[k] = b1[k];
-                j1 = j2;
+                m = 0;
+                ++s;
+            } else {
+                ++m;
             }
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const T tau = tsum[v] / T(nd);
-                const T W = T(1) + tau * Lam[v];
-                s1[v] = (T(1) + tau * inv1[v]) / W;
-                const T tw = tau / W;
+            for (int v = 0; v < 5; ++v) u0[v] = u1[v];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) g[k][v] *= tw;
-                if constexpr (LABEL) {
-                    // |omega_s - lambda_s| = lambda_s |(1 + tau r_s)/W - 1|: extreme at rmin or rmax
-                    const float d1 = float(fabs(lam_1 * (s1[v] - T(1))));
-                    const float d2 = float(fabs(lam_s * ((T(1) + tau * rmin[v]) / W - T(1))));
-                    const float d3 = float(fabs(lam_s * ((T(1) + tau * rmax[v]) / W - T(1))));
-                    lab = fmaxf(lab, fmaxf(d1, fmaxf(d2, d3)));
-                }
+            for (int k = 0; k < 3; ++k) b0[k] = b1[k];
+            j1 = j2;
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const T tau = tsum[v] / T(nd);
+            const T W = T(1) + tau * Lam[v];
+            s1[v] = (T(1) + tau * inv1[v]) / W;
+            const T tw = tau / W;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) g[k][v] *= tw;
+            if constexpr (LABEL) {
+                // |omega_s - lambda_s| = lambda_s |(1 + tau r_s)/W - 1|: extreme at rmin or rmax
+                const float d1 = float(fabs(lam_1 * (s1[v] - T(1))));
+                const float d2 = float(fabs(lam_s * ((T(1) + tau * rmin[v]) / W - T(1))));
+                const float d3 = float(fabs(lam_s * ((T(1) + tau * rmax[v]) / W - T(1))));
+                lab = fmaxf(lab, fmaxf(d1, fmaxf(d2, d3)));
             }
         }
-        // blended coefficients, then the point values at the face points
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int v = 0; v < 5; ++v) a[k][v] = s1[v] * a[k][v] + (k < 3 ? g[k < 3 ? k : 0][v] : T(0));
-        bool ok = true;
-        const int NF = A.NF, Q = A.Q;
-#pragma unroll 1
-        for (int lf = 0; lf < NF; ++lf) {
-            const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
-            if (f2 < 0) continue;
-            const int nq = A.fnq[f2 >> 1];
-            const T* pp = A.Phi + int64_t(lf) * Q * K * nc + c;
-            T p0[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) p0[k] = pp[k * nc];
-#pragma unroll 1
-            for (int q = 0; q < nq; ++q) {
-                const int qn = q + 1 < nq ? q + 1 : q;
-                T p1[K];
-#pragma unroll
-                for (int k = 0; k < K; ++k) p1[k] = pp[(int64_t(qn) * K + k) * nc];
-                T d[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) d[v] = T(0);
-                if (mode != 2) {
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) d[v] += p0[k] * a[k][v];
-                }
-                T val[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
-                const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-                ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
-                // cell-fastest slots [lf][q][v][cell]: the wave's stores are contiguous
-                T* out = A.fs + (int64_t(lf * Q + q) * 5) * nc + c;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) out[v * nc] = val[v];
-#pragma unroll
-                for (int k = 0; k < K; ++k) p0[k] = p1[k];
-            }
-        }
-    return ok;
+    }
 }
 
-// Main pass: gated cells take the linear central polynomial, the others
-// full CWENOZ.  A cell whose point states violate positivity is marked with
-// bit 7 of its flag for the fallback pass.
+// One lane per cell: steps (iii)-(vi) for mode 1, then (vii) for any mode.
+template <class T, int K, bool LABEL>
+__device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab,
+                                           T a[K][5]) {
+    if (mode == 1) {
+        const int nd = A.ndir[c];
+        if (nd > 0) dir_blend_lane<T, K, LABEL>(A, c, ui, nd, lab, a);
+    }
+    return face_values<T, K>(A, c, ui, mode, a);
+}
+
+// Steps (iii)-(v) of one cell co taken by the whole wave: lane l handles
+// member l mod G of stencil l / G (G = MD rounded up to a power of two; 64/G
+// stencils per pass).  The stencil sums a_s are butterflies over each group
+// of G lanes, then every stencil's share of the blend is summed over the
+// groups, so every lane returns
+//   tsum = sum_s |SI_1 - SI_s|, Lsum = sum_s lambda_s / (eps + SI_s),
+//   Gs   = sum_s lambda_s (1/(eps+SI_s) - 1/(eps+SI_1)) a_s.
+// All 64 lanes must call it together.
+template <class T, int K>
+__device__ __forceinline__ void dir_sums_wave(const ReconArgs<T>& A, int64_t co, const double* uo, const T* SI1,
+                                              const T* inv1, int nd, T lam_s, T tsum[5], T Lsum[5], T Gs[3][5]) {
+    const int64_t nc = A.nc;
+    const int MD = A.MD, G = A.MDG, per = 64 / A.MDG;
+    const int lane = int(threadIdx.x & 63);
+    const int m = lane & (G - 1);
+    const T o00 = A.O[0 * nc + co], o01 = A.O[1 * nc + co], o02 = A.O[2 * nc + co];
+    const T o11 = A.O[int64_t(K) * nc + co], o12 = A.O[int64_t(K + 1) * nc + co];
+    const T o22 = A.O[int64_t(2 * K - 1) * nc + co];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        tsum[v] = Lsum[v] = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Gs[k][v] = T(0);
+    }
+#pragma unroll 1
+    for (int s0 = 0; s0 < nd; s0 += per) {
+        const int s = s0 + lane / G;
+        T as[3][5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+        if (s < nd && m < MD) {
+            const int32_t j = A.sten_d[int64_t(s * MD + m) * nc + co];
+            T bv[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) bv[v] = T(A.U[v * nc + j] - uo[v]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T bk = A.Bd[(int64_t(s * 3 + k) * MD + m) * nc + co];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) as[k][v] = bk * bv[v];
+            }
+        }
+        for (int off = 1; off < G; off <<= 1)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) as[k][v] += __shfl_xor(as[k][v], off);
+        // every lane of a group now holds its stencil's a_s; add its share
+        if (s < nd) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T x = as[0][v], y = as[1][v], z = as[2][v];
+                const T SIs = fmax(
+                    x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z, T(0));
+                const T r = T(1) / (A.eps + SIs);
+                tsum[v] += fabs(SI1[v] - SIs);
+                Lsum[v] += lam_s * r;
+                const T coef = lam_s * (r - inv1[v]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Gs[k][v] += coef * as[k][v];
+            }
+        }
+    }
+    // sum over the groups: lanes with equal (lane mod G) hold one copy each
+    for (int off = G; off < 64; off <<= 1)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            tsum[v] += __shfl_xor(tsum[v], off);
+            Lsum[v] += __shfl_xor(Lsum[v], off);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Gs[k][v] += __shfl_xor(Gs[k][v], off);
+        }
+}
+
+// Main pass without a gate (full CWENOZ everywhere), or with a gate (a mask,
+// or the troubled-cell network run inside this kernel).
 //
-// GATE: the troubled-cell network runs inside this kernel.  Right after the
-// central coefficients (which it needs anyway) each cell forms its features,
-// the wave evaluates the network for its 64 cells on the matrix cores, and
-// cells with P(troubled) < theta take the linear central polynomial here.
-// The others are appended to a work list (one atomic per wave) and get full
-// CWENOZ in reconstruct_list_kernel, so that a few troubled lanes do not hold
-// a whole wave in the directional stencils.  Each cell's result does not
-// depend on its place in the list.
+// GATE: right after the central coefficients (which it needs anyway) each
+// cell forms its features and the wave evaluates the network for its 64
+// cells on the matrix cores (or reads the mask).  Cells taken as smooth keep
+// the linear central polynomial.  The cells left for full CWENOZ, usually a
+// few per wave, do not run the directional stencils in their own lanes, which
+// would hold the whole wave for the length of a directional stream: the wave
+// takes them one after the other, all 64 lanes on one cell's directional
+// members at once (dir_sums_wave, two memory round trips per cell).  Where
+// troubled cells cluster and a wave holds more than kCoopMax of them, their
+// lanes run their own streams instead.
+//
+// A cell whose point states violate positivity is marked with bit 7 of its
+// flag for the fallback pass.
 template <class T, int K, bool LABEL, bool GATE>
-__global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GATE && sizeof(T) == 4 && K == 9 ? 3 : 1)))
+void reconstruct_kernel(ReconArgs<T> A) {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     const bool valid = c < A.nc;
     double ui[5];
     T a[K][5];
-    int mode;
     if constexpr (GATE) {
-        __shared__ MlpWeights S;
-        __shared__ MlpWaveLds Wv[kBlock / 64];
-        mlp_stage(A.mlp, S, threadIdx.x, blockDim.x);
-        __syncthreads();
-        float f[12];
-        if (valid) {
+        int mode = 0;
+        if (A.mlp) {
+            __shared__ MlpWeights S;
+            __shared__ MlpWaveLds Wv[kBlock / 64];
+            mlp_stage(A.mlp, S, threadIdx.x, blockDim.x);
+            __syncthreads();
+            float f[12];
+            if (valid) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
+                T js[4];
+                central_coeffs<T, K, true>(A, c, ui, a, js);
+                gate_features<T, K>(A, c, ui, a, js, f);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) f[k] = S.mu[k];
+            }
+            const float z = mlp_wave_forward(S, Wv[threadIdx.x >> 6], f);  // all lanes of the wave
+            mode = 1.f / (1.f + __expf(-z)) < S.theta ? 0 : 1;
+        } else if (valid) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
-            T js[4];
-            central_coeffs<T, K, true>(A, c, ui, a, js);
-            gate_features<T, K>(A, c, ui, a, js, f);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) f[k] = S.mu[k];
+            central_coeffs<T, K>(A, c, ui, a);
+            mode = A.gate[c] ? 0 : 1;
         }
-        const float z = mlp_wave_forward(S, Wv[threadIdx.x >> 6], f);  // all lanes of the wave
-        mode = 1.f / (1.f + __expf(-z)) < S.theta ? 0 : 1;
-        const bool listed = valid && mode == 1;
-        const uint64_t bal = __ballot(listed);
-        if (bal) {
-            const int lane = int(threadIdx.x & 63);
-            const int leader = __ffsll(static_cast<unsigned long long>(bal)) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(A.work, int(__popcll(bal)));
-            base = __shfl(base, leader);
-            if (listed)
-                A.work[kListOff + base + int(__popcll(bal & ((uint64_t(1) << lane) - 1)))] = int32_t(c);
+        const bool full = valid && mode == 1;
+        const int nd = full ? int(A.ndir[c]) : 0;
+        uint64_t bal = __ballot(full && nd > 0);
+        if (__popcll(bal) > kCoopMax) {
+            float lab = 0.f;
+            if (full && nd > 0) dir_blend_lane<T, K, false>(A, c, ui, nd, lab, a);
+            bal = 0;
+        }
+        const T lam_s = T(1) / (A.lam_c + T(nd));
+        const bool mine = bal != 0 && full && nd > 0;  // this lane's cell goes wave-cooperative
+        T SI1[5], inv1[5];
+        if (mine) si_opt<T, K>(A, c, a, SI1);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) inv1[v] = mine ? T(1) / (A.eps + SI1[v]) : T(0);
+        const int lane = int(threadIdx.x & 63);
+        while (bal) {
+            const int o = __ffsll(static_cast<unsigned long long>(bal)) - 1;
+            bal &= bal - 1;
+            const int64_t co = __shfl(int(c), o);
+            const int ndo = __shfl(nd, o);
+            const T lso = __shfl(lam_s, o);
+            double uo[5];
+            T SIo[5], invo[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                uo[v] = __shfl(ui[v], o);
+                SIo[v] = __shfl(SI1[v], o);
+                invo[v] = __shfl(inv1[v], o);
+            }
+            T tsum[5], Lsum[5], Gs[3][5];
+            dir_sums_wave<T, K>(A, co, uo, SIo, invo, ndo, lso, tsum, Lsum, Gs);
+            if (lane == o) {
+                const T lam_1 = A.lam_c * lam_s;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    const T tau = tsum[v] / T(nd);
+                    const T W = T(1) + tau * (lam_1 * inv1[v] + Lsum[v]);
+                    const T s1 = (T(1) + tau * inv1[v]) / W;
+                    const T tw = tau / W;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) a[k][v] = s1 * a[k][v] + (k < 3 ? tw * Gs[k < 3 ? k : 0][v] : T(0));
+                }
+            }
         }
         if (!valid) return;
         if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
-        if (listed) return;
-        float lab = 0.f;
-        const bool ok = recon_cell<T, K, false, false>(A, c, ui, 0, lab, a);
-        A.flags[c] = uint8_t(1 | (ok ? 0 : 0x80));
-        if constexpr (LABEL) A.label[c] = 0.f;
-        return;
+        const bool ok = face_values<T, K>(A, c, ui, 0, a);
+        A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
     } else {
         if (!valid) return;
 #pragma unroll
         for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
         central_coeffs<T, K>(A, c, ui, a);
-        mode = (A.gate && A.gate[c]) ? 0 : 1;  // 0 linear, 1 CWENOZ
+        float lab = 0.f;
+        const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
+        A.flags[c] = uint8_t(ok ? 0 : 0x80);
+        if constexpr (LABEL) A.label[c] = lab;
     }
-    float lab = 0.f;
-    const bool ok = recon_cell<T, K, LABEL>(A, c, ui, mode, lab, a);
-    A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
-    if constexpr (LABEL) A.label[c] = lab;
-}
-
-// Second pass of the gated reconstruction: full CWENOZ on the listed cells.
-template <class T, int K, bool LABEL>
-__global__ __launch_bounds__(kBlock) void reconstruct_list_kernel(ReconArgs<T> A) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= A.work[0]) return;
-    const int64_t c = A.work[kListOff + i];
-    double ui[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
-    T a[K][5];
-    central_coeffs<T, K>(A, c, ui, a);
-    float lab = 0.f;
-    const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
-    A.flags[c] = uint8_t(ok ? 0 : 0x80);
-    if constexpr (LABEL) A.label[c] = lab;
 }
 
 // Gate features only ([n_cell][12] float), from the central coefficients.

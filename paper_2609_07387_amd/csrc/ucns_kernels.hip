@@ -6,8 +6,9 @@
 // cwenoz_weights, viscous_gradient_penalty, fv_update) with the per-stage
 // order of its time-step algorithm (Algorithm 1).
 //
-// Layout: per-cell operators are cell-fastest ([entry][n_cell]) so that one
-// thread per cell streams them coalesced; face arrays are face-major.  The
+// Layout: per-cell operators and the point states each cell writes are
+// cell-fastest ([entry][n_cell]) so that one thread per cell streams them
+// coalesced; face geometry and face fluxes are face-major.  The
 // residual is a per-cell gather of single-valued face fluxes (no atomics),
 // and the two reductions (dt, kinetic energy) use a fixed block count and a
 // fixed tree, so every result is bitwise reproducible.
@@ -29,7 +30,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
-constexpr int kListOff = 64;      // gate work list: counter in [0], cell ids from [64]
+constexpr int kCoopMax = 12;      // gated recon: up to this many full cells per wave go wave-cooperative
 
 // The dispatcher hands workgroups to the eight XCDs round robin (block b runs
 // on XCD b mod 8).  Renumbered this way, each XCD takes one contiguous range
@@ -90,7 +91,7 @@ struct ReconArgs {
     const uint8_t* ndir;
     const int32_t* sten_d;
     const T* Bd;
-    int MD;
+    int MD, MDG;  // padded directional stencil size, and rounded up to a power of two
     const T* O;
     const T* Phi;
     const int32_t* c2f;
@@ -104,7 +105,6 @@ struct ReconArgs {
     // troubled-cell gate (network inside the kernel) and its features
     const float* mlp;
     uint8_t* mask_out;
-    int32_t* work;  // counter + list of the cells the network sends to full CWENOZ
     const int32_t* nbr;
     const T* ndc;
     const T* hb;
@@ -550,6 +550,8 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.sten_d = arena_ptr<int32_t>(ar, ar.sten_d);
     A.Bd = arena_ptr<T>(ar, ar.Bd);
     A.MD = std::max(1, m.md_pad);
+    A.MDG = 1;
+    while (A.MDG < A.MD) A.MDG <<= 1;
     A.O = arena_ptr<T>(ar, ar.O);
     A.Phi = arena_ptr<T>(ar, ar.Phi);
     A.c2f = arena_ptr<int32_t>(ar, ar.c2f);
@@ -559,7 +561,6 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.gate = gate ? gate->mask : nullptr;
     A.mlp = gate ? gate->mlp : nullptr;
     A.mask_out = gate ? gate->mask_out : nullptr;
-    A.work = gate ? gate->work : nullptr;
     A.nbr = arena_ptr<int32_t>(ar, ar.nbr);
     A.ndc = arena_ptr<T>(ar, ar.ndc);
     A.hb = arena_ptr<T>(ar, ar.hb);
@@ -573,20 +574,11 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     return A;
 }
 
-__global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
-
 template <class T, int K>
 int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
     const dim3 grid(grid_for(A.nc)), block(kBlock);
-    if (A.mlp) {
-        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, st, A.work);
-        if (A.label) {
-            hipLaunchKernelGGL((reconstruct_kernel<T, K, true, true>), grid, block, 0, st, A);
-            hipLaunchKernelGGL((reconstruct_list_kernel<T, K, true>), grid, block, 0, st, A);
-        } else {
-            hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
-            hipLaunchKernelGGL((reconstruct_list_kernel<T, K, false>), grid, block, 0, st, A);
-        }
+    if (A.mlp || A.gate) {
+        hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
     } else {
         if (A.label)
             hipLaunchKernelGGL((reconstruct_kernel<T, K, true, false>), grid, block, 0, st, A);
@@ -771,8 +763,8 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     UCNS_REQUIRE(!(gate && gate->mask && gate->mlp), UCNS_EINVAL, "gate: give a mask or a network, not both");
-    UCNS_REQUIRE(!(gate && gate->mlp) || (gate->work && aligned(gate->work)), UCNS_EINVAL,
-                 "gate: the network needs a 256-byte aligned work buffer");
+    UCNS_REQUIRE(!(gate && (gate->mask || gate->mlp) && label), UCNS_EINVAL,
+                 "labels are produced by the ungated reconstruction only");
     const double gm1 = phys->gamma - 1.0;
     const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
                                          : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);

@@ -115,19 +115,42 @@ def test_steps_fp64(torch_cuda, name, steps):
 
 
 def test_gate_mask_semantics(torch_cuda):
-    """mask all ones = linear central path; all zeros = full CWENOZ (bitwise
-    against the ungated launch); both against the oracle's gated path."""
+    """mask all ones = linear central path; all zeros = full CWENOZ taken by
+    the wave-cooperative directional evaluation of the gated kernel (equal to
+    the ungated one-lane-per-cell launch up to summation order, bitwise
+    reproducible); both against the oracle."""
     m, order, ph, U, bcs = _setup("tet4_p2_hllc")
     lm = ucns.Mesh(m, order=order)
     om = oracle.OracleMesh(m, order=order)
     ones = np.ones(m.n_cell, np.uint8)
+    zeros = np.zeros(m.n_cell, np.uint8)
     fs1, _, _, R1, fl1 = gpu_stage(lm, ph, U, ucns.F64, gate_mask=ones)
-    fs0, _, _, R0, _ = gpu_stage(lm, ph, U, ucns.F64, gate_mask=np.zeros(m.n_cell, np.uint8))
-    fsn, _, _, Rn, _ = gpu_stage(lm, ph, U, ucns.F64)
-    assert np.array_equal(R0, Rn) and np.array_equal(fs0, fsn, equal_nan=True)
+    fs0, _, _, R0, fl0 = gpu_stage(lm, ph, U, ucns.F64, gate_mask=zeros)
+    fs0b, _, _, R0b, _ = gpu_stage(lm, ph, U, ucns.F64, gate_mask=zeros)
+    fsn, _, _, Rn, fln = gpu_stage(lm, ph, U, ucns.F64)
+    assert np.array_equal(R0, R0b) and np.array_equal(fs0, fs0b, equal_nan=True)
+    assert np.array_equal(np.isnan(fs0), np.isnan(fsn)) and np.array_equal(fl0, fln)
+    ok = ~np.isnan(fsn)
+    scale = np.abs(fsn[ok]).max()
+    assert np.abs(fs0[ok] - fsn[ok]).max() / scale < 1e-13
+    assert grouped_rel_linf(R0, Rn) < 1e-11
     assert np.all(fl1 & 1)
-    _, _, _, oR1, _, _ = oracle_stage(om, as_oracle_phys(ph), U, None, ones)
+    oph = as_oracle_phys(ph)
+    _, _, _, oR1, _, _ = oracle_stage(om, oph, U, None, ones)
+    _, _, _, oR0, _, _ = oracle_stage(om, oph, U, None, zeros)
     assert grouped_rel_linf(R1, oR1) < 1e-11
+    assert grouped_rel_linf(R0, oR0) < 1e-11
+    # sparse troubled cells (a few per wave): the wave-cooperative path
+    sparse = np.ones(m.n_cell, np.uint8)
+    sparse[::13] = 0
+    fss, _, _, Rs, fls = gpu_stage(lm, ph, U, ucns.F64, gate_mask=sparse)
+    ofss, _, _, oRs, ofls, _ = oracle_stage(om, oph, U, None, sparse)
+    assert np.array_equal(fls, ofls)
+    assert grouped_rel_linf(Rs, oRs) < 1e-11
+    fl, fo, sl = face_maps(lm, om)
+    a, b = fss[fl, sl, :lm.qmax], ofss[fo, sl, :lm.qmax]
+    valid = ~np.isnan(b[..., 0])
+    assert np.abs(a - b)[valid].max() / np.abs(b[valid]).max() < 1e-12
 
 
 def test_determinism_bitwise(torch_cuda):
