@@ -957,8 +957,8 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
         std::sort(perm.begin(), perm.begin() + n, [&](int x, int y) { return ids[x] < ids[y]; });
         for (int j = 0; j < MC; ++j) {
             sten_c[size_t(j) * nc + c] = j < n ? int32_t(ids[perm[j]]) : int32_t(c);
-            for (int k = 0; k < K; ++k)
-                Bc[(size_t(k) * MC + j) * nc + c] = j < n ? T(m.Bc[(size_t(c) * K + k) * MC + perm[j]]) : T(0);
+            for (int k = 0; k < K; ++k)  // member-major rows: (j, k) at (j K + k) nc
+                Bc[(size_t(j) * K + k) * nc + c] = j < n ? T(m.Bc[(size_t(c) * K + k) * MC + perm[j]]) : T(0);
         }
         ndir[c] = uint8_t(m.ndir[c]);
         for (int s = 0; s < ND; ++s) {
@@ -968,8 +968,8 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
             std::sort(perm.begin(), perm.begin() + nd, [&](int x, int y) { return dids[x] < dids[y]; });
             for (int j = 0; j < MD; ++j) {
                 sten_d[(size_t(s) * MD + j) * nc + c] = j < nd ? int32_t(dids[perm[j]]) : int32_t(c);
-                for (int k = 0; k < 3; ++k)
-                    Bd[((size_t(s) * 3 + k) * MD + j) * nc + c] =
+                for (int k = 0; k < 3; ++k)  // member-major rows: (s, j, k) at ((s MD + j) 3 + k) nc
+                    Bd[((size_t(s) * MD + j) * 3 + k) * nc + c] =
                         j < nd ? T(m.Bd[((size_t(c) * m.nd_max + s) * 3 + k) * m.md_pad + perm[j]]) : T(0);
             }
         }

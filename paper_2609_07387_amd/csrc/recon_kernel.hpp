@@ -13,6 +13,30 @@
 // so a wave keeps two elements' worth of loads outstanding instead of
 // waiting a full memory round trip per stencil member.
 
+// Buffer loads: the array's base and size sit in a resource descriptor in
+// scalar registers, a row offset (wave-uniform) in a scalar register and the
+// lane's byte offset in one 32-bit vector register, so no access needs
+// per-lane 64-bit address arithmetic.  Each descriptor covers at most 4 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                             int(bytes < 0xffffffffull ? uint32_t(bytes) : 0xffffffffu), 0x00020000);
+}
+template <class T>
+__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, int(voff), int(soff), 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, int(voff), int(soff), 0));
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ void bst(T val, __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, val), rs, int(voff), int(soff), 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, val), rs, int(voff), int(soff), 0);
+}
+
 // a = B_c b over the central stencil.  With FEAT, js[] also receives the max
 // and the sum of |b| for rho (js[0], js[1]) and rho E (js[2], js[3]), which
 // the gate features use (padding members contribute zero jumps).
@@ -21,33 +45,39 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
                                                T* js = nullptr) {
     const int64_t nc = A.nc;
     const int MC = A.MC;
+    // member m's id at sten_c[m][c]; its K operator rows at Bc[m][k][c]; U[v][j]
+    const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
+    const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
+    const auto rS = rsrc(A.sten_c, uint64_t(MC) * rowI);
+    const auto rU = rsrc(A.U, uint64_t(5) * rowU);
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int v = 0; v < 5; ++v) a[k][v] = T(0);
     if constexpr (FEAT) js[0] = js[1] = js[2] = js[3] = T(0);
-    const int32_t* sp = A.sten_c + c;
-    const T* bp = A.Bc + c;
-    const int64_t kstride = int64_t(MC) * nc;
     // prologue: member 0 operands, index of member 1
-    int32_t j1 = sp[(MC > 1 ? 1 : 0) * nc];
-    const int32_t j0 = sp[0];
+    int32_t j1 = bld<int32_t>(rS, c4, MC > 1 ? rowI : 0u);
+    const int32_t j0 = bld<int32_t>(rS, c4, 0u);
     double u0[5];
     T b0[K];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) u0[v] = A.U[v * nc + j0];
+    for (int v = 0; v < 5; ++v) u0[v] = bld<double>(rU, uint32_t(j0) * 8u, uint32_t(v) * rowU);
+    {
+        const auto rB = rsrc(A.Bc, uint64_t(K) * rowT);
 #pragma unroll
-    for (int k = 0; k < K; ++k) b0[k] = bp[k * kstride];
-#pragma unroll 1
+        for (int k = 0; k < K; ++k) b0[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+    }
+#pragma unroll 2
     for (int m = 0; m < MC; ++m) {
         const int mn = m + 1 < MC ? m + 1 : m;
-        const int32_t j2 = sp[int64_t(m + 2 < MC ? m + 2 : mn) * nc];
+        const int32_t j2 = bld<int32_t>(rS, c4, uint32_t(m + 2 < MC ? m + 2 : mn) * rowI);
         double u1[5];
         T b1[K];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) u1[v] = A.U[v * nc + j1];
+        for (int v = 0; v < 5; ++v) u1[v] = bld<double>(rU, uint32_t(j1) * 8u, uint32_t(v) * rowU);
+        const auto rB = rsrc(A.Bc + int64_t(mn) * K * nc, uint64_t(K) * rowT);
 #pragma unroll
-        for (int k = 0; k < K; ++k) b1[k] = bp[k * kstride + int64_t(mn) * nc];
+        for (int k = 0; k < K; ++k) b1[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
         T bv[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
@@ -158,40 +188,51 @@ template <class T, int K>
 __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, const double* ui, int mode,
                                             const T a[K][5]) {
     const int64_t nc = A.nc;
-    bool ok = true;
     const int NF = A.NF, Q = A.Q;
+    const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T));
+    const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
+    const auto rC = rsrc(A.c2f, uint64_t(NF) * rowI);
+    bool ok = true;
+    // the loops are wave-uniform (every lane walks all NF x Q slots); a lane
+    // skips the slots its cell does not have.  Phi of point (lf, q) in rows
+    // ((lf Q + q) K + k), the point's state in rows ((lf Q + q) 5 + v).
 #pragma unroll 1
     for (int lf = 0; lf < NF; ++lf) {
-        const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
-        if (f2 < 0) continue;
-        const int nq = A.fnq[f2 >> 1];
-        const T* pp = A.Phi + int64_t(lf) * Q * K * nc + c;
+        const int32_t f2 = bld<int32_t>(rC, c4, uint32_t(lf) * rowI);
+        const int nq = f2 < 0 ? 0 : int(A.fnq[f2 >> 1]);
         T p0[K];
+        {
+            const auto rP = rsrc(A.Phi + int64_t(lf) * Q * K * nc, uint64_t(K) * rowT);
 #pragma unroll
-        for (int k = 0; k < K; ++k) p0[k] = pp[k * nc];
+            for (int k = 0; k < K; ++k) p0[k] = bld<T>(rP, cT, uint32_t(k) * rowT);
+        }
 #pragma unroll 1
-        for (int q = 0; q < nq; ++q) {
-            const int qn = q + 1 < nq ? q + 1 : q;
+        for (int q = 0; q < Q; ++q) {
+            const int qn = q + 1 < Q ? q + 1 : q;
             T p1[K];
+            const auto rP = rsrc(A.Phi + (int64_t(lf) * Q + qn) * K * nc, uint64_t(K) * rowT);
 #pragma unroll
-            for (int k = 0; k < K; ++k) p1[k] = pp[(int64_t(qn) * K + k) * nc];
-            T d[5];
+            for (int k = 0; k < K; ++k) p1[k] = bld<T>(rP, cT, uint32_t(k) * rowT);
+            if (q < nq) {
+                T d[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) d[v] = T(0);
-            if (mode != 2) {
+                for (int v = 0; v < 5; ++v) d[v] = T(0);
+                if (mode != 2) {
 #pragma unroll
-                for (int k = 0; k < K; ++k)
+                    for (int k = 0; k < K; ++k)
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) d[v] += p0[k] * a[k][v];
+                        for (int v = 0; v < 5; ++v) d[v] += p0[k] * a[k][v];
+                }
+                T val[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
+                const T p =
+                    A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+                ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
+                const auto rF = rsrc(A.fs + (int64_t(lf) * Q + q) * 5 * nc, uint64_t(5) * rowT);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cT, uint32_t(v) * rowT);
             }
-            T val[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
-            const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-            ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
-            T* out = A.fs + (int64_t(lf * Q + q) * 5) * nc + c;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) out[v * nc] = val[v];
 #pragma unroll
             for (int k = 0; k < K; ++k) p0[k] = p1[k];
         }
@@ -229,19 +270,27 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
         const T o00 = A.O[0 * nc + c], o01 = A.O[1 * nc + c], o02 = A.O[2 * nc + c];
         const T o11 = A.O[int64_t(K) * nc + c], o12 = A.O[int64_t(K + 1) * nc + c];
         const T o22 = A.O[int64_t(2 * K - 1) * nc + c];
-        // all directional members as one pipelined stream t = s * MD + m
-        const int MD = A.MD, total = nd * MD;
-        const int32_t* sp = A.sten_d + c;
-        const T* bp = A.Bd + c;
-        const int64_t kstride = int64_t(MD) * nc;  // between the 3 rows of one stencil
-        int32_t j1 = sp[int64_t(total > 1 ? 1 : 0) * nc];
-        const int32_t j0 = sp[0];
+        // all directional members as one pipelined stream t = s * MD + m over
+        // every stencil slot (a wave-uniform count; the slots past the cell's
+        // nd hold zero operators and are not counted); the id of member t at
+        // sten_d[t][c], its 3 operator rows at Bd[t][k][c]
+        const int MD = A.MD, total = A.ND * MD;
+        const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T));
+        const uint32_t rowU = uint32_t(nc) * 8u;
+        const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
+        const auto rS = rsrc(A.sten_d, uint64_t(total) * rowI);
+        const auto rU = rsrc(A.U, uint64_t(5) * rowU);
+        int32_t j1 = bld<int32_t>(rS, c4, total > 1 ? rowI : 0u);
+        const int32_t j0 = bld<int32_t>(rS, c4, 0u);
         double u0[5];
         T b0[3];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) u0[v] = A.U[v * nc + j0];
+        for (int v = 0; v < 5; ++v) u0[v] = bld<double>(rU, uint32_t(j0) * 8u, uint32_t(v) * rowU);
+        {
+            const auto rB = rsrc(A.Bd, uint64_t(3) * rowT);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) b0[k] = bp[k * kstride];
+            for (int k = 0; k < 3; ++k) b0[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+        }
         T as[3][5];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -250,19 +299,16 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
         int m = 0, s = 0;
 #pragma unroll 1
         for (int t = 0; t < total; ++t) {
-            // element t+1 is (s, m+1) or (s+1, 0); its operator rows sit at
-            // (3 s' + k) MD + m' = t' + 2 s' MD + k MD for t' = s' MD + m'
             const int tn = t + 1 < total ? t + 1 : t;
-            const int sn = (m + 1 < MD) ? s : s + 1;
-            const int sn_c = t + 1 < total ? sn : s;
             const int t2 = t + 2 < total ? t + 2 : tn;
-            const int32_t j2 = sp[int64_t(t2) * nc];
+            const int32_t j2 = bld<int32_t>(rS, c4, uint32_t(t2) * rowI);
             double u1[5];
             T b1[3];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) u1[v] = A.U[v * nc + j1];
+            for (int v = 0; v < 5; ++v) u1[v] = bld<double>(rU, uint32_t(j1) * 8u, uint32_t(v) * rowU);
+            const auto rB = rsrc(A.Bd + int64_t(tn) * 3 * nc, uint64_t(3) * rowT);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) b1[k] = bp[int64_t(tn + 2 * sn_c * MD) * nc + k * kstride];
+            for (int k = 0; k < 3; ++k) b1[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
             T bv[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
@@ -272,24 +318,27 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
                 for (int v = 0; v < 5; ++v) as[k][v] += b0[k] * bv[v];
             if (m + 1 == MD) {
                 // stencil s complete: its indicator and its share of the blend
+                if (s < nd) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    const T x = as[0][v], y = as[1][v], z = as[2][v];
-                    const T SIs = fmax(
-                        x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z,
-                        T(0));
-                    tsum[v] += fabs(SI1[v] - SIs);
-                    const T r = T(1) / (A.eps + SIs);
-                    Lam[v] += lam_s * r;
-                    rmin[v] = fmin(rmin[v], r);
-                    rmax[v] = fmax(rmax[v], r);
-                    const T coef = lam_s * (r - inv1[v]);
+                    for (int v = 0; v < 5; ++v) {
+                        const T x = as[0][v], y = as[1][v], z = as[2][v];
+                        const T SIs = fmax(
+                            x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z,
+                            T(0));
+                        tsum[v] += fabs(SI1[v] - SIs);
+                        const T r = T(1) / (A.eps + SIs);
+                        Lam[v] += lam_s * r;
+                        rmin[v] = fmin(rmin[v], r);
+                        rmax[v] = fmax(rmax[v], r);
+                        const T coef = lam_s * (r - inv1[v]);
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        g[k][v] += coef * as[k][v];
-                        as[k][v] = T(0);
+                        for (int k = 0; k < 3; ++k) g[k][v] += coef * as[k][v];
                     }
                 }
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) as[k][v] = T(0);
                 m = 0;
                 ++s;
             } else {
@@ -374,7 +423,7 @@ __device__ __forceinline__ void dir_sums_wave(const ReconArgs<T>& A, int64_t co,
             for (int v = 0; v < 5; ++v) bv[v] = T(A.U[v * nc + j] - uo[v]);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const T bk = A.Bd[(int64_t(s * 3 + k) * MD + m) * nc + co];
+                const T bk = A.Bd[(int64_t(s * MD + m) * 3 + k) * nc + co];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) as[k][v] = bk * bv[v];
             }

@@ -91,6 +91,7 @@ struct ReconArgs {
     const uint8_t* ndir;
     const int32_t* sten_d;
     const T* Bd;
+    int ND;       // directional stencil slots per cell (cells with fewer pad with zero operators)
     int MD, MDG;  // padded directional stencil size, and rounded up to a power of two
     const T* O;
     const T* Phi;
@@ -549,6 +550,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.ndir = arena_ptr<uint8_t>(ar, ar.ndir);
     A.sten_d = arena_ptr<int32_t>(ar, ar.sten_d);
     A.Bd = arena_ptr<T>(ar, ar.Bd);
+    A.ND = std::max(1, m.nd_max);
     A.MD = std::max(1, m.md_pad);
     A.MDG = 1;
     while (A.MDG < A.MD) A.MDG <<= 1;
