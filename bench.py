@@ -22,6 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# measured HBM bytes per launch of the dominant kernel (rocprofv3 counters)
+TRAFFIC = {"fp32_gate": "traffic_reconstruct_fp32_gate_tgv64.md",
+           "fp64_plain": "traffic_reconstruct_fp64_tgv64.md"}
 METRIC = "cell-stage updates/s, P2 CWENO+HLLC: FP64 plain vs FP32+MLP gate; % HBM peak"
 
 
@@ -178,8 +181,13 @@ def main():
     copy_calibration(torch)
     head = "fp32_gate" if "fp32_gate" in variants else "fp64_plain"
     hv = variants[head]
-    kname = "reconstruct_kernel<float,9,false,true>" if head == "fp32_gate" else "reconstruct_kernel<double,9,false,false>"
+    kname = ("reconstruct_kernel<float, 9, false, true>" if head == "fp32_gate"
+             else "reconstruct_kernel<double, 9, false, false>")
     achieved = hv["recon_GBs"]
+    from paper_2609_07387_amd import prof
+
+    rec = prof.load_traffic(os.path.join(ROOT, "profiles", TRAFFIC[head]))
+    traffic = rec["bytes_per_launch"] if rec and kname in rec["kernel"] else None
     out = {
         "metric": METRIC, "value": hv["value"], "unit": "cell-stage updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -192,7 +200,8 @@ def main():
         "fp64_plain_value": variants["fp64_plain"]["value"],
         "speedup_vs_fp64_plain": hv["value"] / variants["fp64_plain"]["value"],
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,
                      "bytes_per_cell": hv["recon_bytes_per_cell"]},
     }
     if not args.no_cpu_baseline:

@@ -1,0 +1,139 @@
+"""rocprofv3 result helpers: kernel-time summaries and measured HBM traffic.
+
+Measured traffic of a kernel comes from two counter runs of the same command
+(FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is scaled by
+what it reads for a plain device copy of known size in the same run (the
+benchmark issues one 256 MiB copy outside its timed region): the counters
+count fixed-size requests, and the copy tells how many bytes one counted
+unit is.  The stored record (a short markdown file with the figures and a
+JSON block) carries a digest of the kernel sources; once the sources change
+the record no longer applies and the benchmark reports no traffic.
+
+  python -m paper_2609_07387_amd.prof stats KERNEL_STATS_CSV TITLE COMMAND > profiles/NAME.md
+  python -m paper_2609_07387_amd.prof traffic FETCH_CSV WRITE_CSV KERNEL_SUBSTRING COPY_BYTES COMMAND OUT_MD
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_KERNEL = "copyBuffer"
+
+
+def source_digest() -> str:
+    """sha256 over the device and host sources of libucns."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if p.endswith((".hip", ".hpp", ".cpp", ".h")):
+            with open(p, "rb") as f:
+                h.update(os.path.basename(p).encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def _by_kernel(path, counter):
+    vals = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def _mean_by_kernel(path, counter):
+    return {k: (sum(v) / len(v), len(v)) for k, v in _by_kernel(path, counter).items()}
+
+
+def _copy_reading(path, counter):
+    """The calibration copy is the largest copy dispatch of the run (others
+    are small host uploads)."""
+    hits = [v for k, v in _by_kernel(path, counter).items() if COPY_KERNEL in k]
+    if not hits:
+        raise SystemExit(f"no {COPY_KERNEL} dispatch in {path}")
+    return max(max(v) for v in hits)
+
+
+def _pick(d, sub):
+    hits = [k for k in d if sub in k]
+    if len(hits) != 1:
+        raise SystemExit(f"kernel '{sub}': {len(hits)} matches in {sorted(d)}")
+    return hits[0], d[hits[0]]
+
+
+def traffic(fetch_csv, write_csv, kernel, copy_bytes, command):
+    fe = _mean_by_kernel(fetch_csv, "FETCH_SIZE")
+    wr = _mean_by_kernel(write_csv, "WRITE_SIZE")
+    name, (f_kib, nf) = _pick(fe, kernel)
+    _, (w_kib, nw) = _pick(wr, kernel)
+    cf_kib = _copy_reading(fetch_csv, "FETCH_SIZE")
+    cw_kib = _copy_reading(write_csv, "WRITE_SIZE")
+    f_scale = copy_bytes / (cf_kib * 1024.0)
+    w_scale = copy_bytes / (cw_kib * 1024.0)
+    fetch_b = f_kib * 1024.0 * f_scale
+    write_b = w_kib * 1024.0 * w_scale
+    return {"kernel": name, "dispatches": [nf, nw], "fetch_kib": f_kib, "write_kib": w_kib,
+            "copy_bytes": copy_bytes, "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib,
+            "fetch_scale": f_scale, "write_scale": w_scale, "fetch_bytes": fetch_b, "write_bytes": write_b,
+            "bytes_per_launch": fetch_b + write_b, "source_digest": source_digest(), "command": command}
+
+
+def traffic_md(rec):
+    return "\n".join([
+        f"# Measured HBM traffic: `{rec['kernel'][:100]}`", "",
+        "Command (two runs, one counter each):", "", "```", rec["command"], "```", "",
+        "| counter | KiB / dispatch | copy kernel KiB ({:.0f} MiB copied) | scale | bytes / launch |".format(
+            rec["copy_bytes"] / 2**20),
+        "|---|---|---|---|---|",
+        f"| FETCH_SIZE | {rec['fetch_kib']:.1f} | {rec['copy_fetch_kib']:.1f} | {rec['fetch_scale']:.3f} | "
+        f"{rec['fetch_bytes']:.4g} |",
+        f"| WRITE_SIZE | {rec['write_kib']:.1f} | {rec['copy_write_kib']:.1f} | {rec['write_scale']:.3f} | "
+        f"{rec['write_bytes']:.4g} |", "",
+        f"Total per launch: {rec['bytes_per_launch']:.4g} bytes.", "",
+        "```json", json.dumps(rec, indent=1), "```", ""])
+
+
+def load_traffic(path):
+    """The stored record if it was taken on the current kernel sources, else None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        text = f.read()
+    i = text.find("```json")
+    if i < 0:
+        return None
+    rec = json.loads(text[i + 7:text.index("```", i + 7)])
+    return rec if rec.get("source_digest") == source_digest() else None
+
+
+def stats_md(stats_csv, title, command, top=14):
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"# {title}", "", "Command:", "", "```", command, "```", "",
+           "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def main(argv):
+    if len(argv) >= 4 and argv[0] == "stats":
+        sys.stdout.write(stats_md(argv[1], argv[2], argv[3]))
+    elif len(argv) >= 7 and argv[0] == "traffic":
+        rec = traffic(argv[1], argv[2], argv[3], float(argv[4]), argv[5])
+        with open(argv[6], "w") as f:
+            f.write(traffic_md(rec))
+        print(json.dumps(rec))
+    else:
+        sys.stderr.write(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
