@@ -115,13 +115,16 @@ typedef struct {
  * runs inside the reconstruction kernel on each cell's features, smooth when
  * sigmoid(z) < theta); not both.  mask_out (may be NULL) records the
  * network's decisions.  A NULL gate = full CWENOZ everywhere.  With a gate,
- * the cells left for full CWENOZ are taken one at a time by their whole wave
- * (one lane per directional stencil member), so a few troubled cells do not
- * hold a wave in the directional stencils; labels are not produced. */
+ * the cells left for full CWENOZ are listed in work (device int32
+ * [n_cell + 64], required, 256-byte aligned, contents scratch) and
+ * reconstructed by a second pass that gives each of them a whole wave, so
+ * their cost does not depend on how they cluster; calls sharing a work
+ * buffer must not overlap.  Labels are not produced with a gate. */
 typedef struct {
     const uint8_t* mask;  /* device [n_cell] or NULL */
     const float* mlp;     /* device parameter block (UCNS_MLP_NPARAM floats) or NULL */
     uint8_t* mask_out;    /* device [n_cell] or NULL */
+    int32_t* work;        /* device [n_cell + 64], required with mask or mlp */
 } ucns_gate;
 
 /* Gate network parameter block (float32) offsets: mu[16] isig[16]
@@ -213,7 +216,7 @@ int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
 
 /* Face fluxes (Sec. 2.2, eq. fv_update and eq. viscous_gradient_penalty with
  * alpha = 4/3): F_f = |S_f| sum_q w_q (F_c(U_L, U_R; n) - F_v), HLLC or
- * Rusanov convective flux; the Gauss-point sum is a cross-lane reduction.
+ * Rusanov convective flux; one lane per face sums its Gauss points.
  * U (device double [5][n_cell]) supplies the ghost state of transmissive
  * boundary faces (the owner's cell average).  gradW may be NULL for Euler.
  * face_flux [n_face][5]. */

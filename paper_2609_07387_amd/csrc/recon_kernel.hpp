@@ -466,19 +466,15 @@ __device__ __forceinline__ void dir_sums_wave(const ReconArgs<T>& A, int64_t co,
 // GATE: right after the central coefficients (which it needs anyway) each
 // cell forms its features and the wave evaluates the network for its 64
 // cells on the matrix cores (or reads the mask).  Cells taken as smooth keep
-// the linear central polynomial.  The cells left for full CWENOZ, usually a
-// few per wave, do not run the directional stencils in their own lanes, which
-// would hold the whole wave for the length of a directional stream: the wave
-// takes them one after the other, all 64 lanes on one cell's directional
-// members at once (dir_sums_wave, two memory round trips per cell).  Where
-// troubled cells cluster and a wave holds more than kCoopMax of them, their
-// lanes run their own streams instead.
+// the linear central polynomial.  The cells left for full CWENOZ are listed
+// and reconstructed by reconstruct_wave_kernel, one wave per cell, so their
+// cost does not depend on how they cluster (a wave holding a few of them
+// would otherwise run a whole directional stream for them).
 //
 // A cell whose point states violate positivity is marked with bit 7 of its
 // flag for the fallback pass.
 template <class T, int K, bool LABEL, bool GATE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GATE && sizeof(T) == 4 && K == 9 ? 3 : 1)))
-void reconstruct_kernel(ReconArgs<T> A) {
+__global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     const bool valid = c < A.nc;
     double ui[5];
@@ -509,54 +505,23 @@ void reconstruct_kernel(ReconArgs<T> A) {
             central_coeffs<T, K>(A, c, ui, a);
             mode = A.gate[c] ? 0 : 1;
         }
-        const bool full = valid && mode == 1;
-        const int nd = full ? int(A.ndir[c]) : 0;
-        uint64_t bal = __ballot(full && nd > 0);
-        if (__popcll(bal) > kCoopMax) {
-            float lab = 0.f;
-            if (full && nd > 0) dir_blend_lane<T, K, false>(A, c, ui, nd, lab, a);
-            bal = 0;
-        }
-        const T lam_s = T(1) / (A.lam_c + T(nd));
-        const bool mine = bal != 0 && full && nd > 0;  // this lane's cell goes wave-cooperative
-        T SI1[5], inv1[5];
-        if (mine) si_opt<T, K>(A, c, a, SI1);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) inv1[v] = mine ? T(1) / (A.eps + SI1[v]) : T(0);
-        const int lane = int(threadIdx.x & 63);
-        while (bal) {
-            const int o = __ffsll(static_cast<unsigned long long>(bal)) - 1;
-            bal &= bal - 1;
-            const int64_t co = __shfl(int(c), o);
-            const int ndo = __shfl(nd, o);
-            const T lso = __shfl(lam_s, o);
-            double uo[5];
-            T SIo[5], invo[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                uo[v] = __shfl(ui[v], o);
-                SIo[v] = __shfl(SI1[v], o);
-                invo[v] = __shfl(inv1[v], o);
-            }
-            T tsum[5], Lsum[5], Gs[3][5];
-            dir_sums_wave<T, K>(A, co, uo, SIo, invo, ndo, lso, tsum, Lsum, Gs);
-            if (lane == o) {
-                const T lam_1 = A.lam_c * lam_s;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    const T tau = tsum[v] / T(nd);
-                    const T W = T(1) + tau * (lam_1 * inv1[v] + Lsum[v]);
-                    const T s1 = (T(1) + tau * inv1[v]) / W;
-                    const T tw = tau / W;
-#pragma unroll
-                    for (int k = 0; k < K; ++k) a[k][v] = s1 * a[k][v] + (k < 3 ? tw * Gs[k < 3 ? k : 0][v] : T(0));
-                }
-            }
+        // troubled cells go to the work list (one atomic per wave) for
+        // reconstruct_wave_kernel; the others take the linear polynomial here
+        const bool listed = valid && mode == 1;
+        const uint64_t bal = __ballot(listed);
+        if (bal) {
+            const int lane = int(threadIdx.x & 63);
+            const int leader = __ffsll(static_cast<unsigned long long>(bal)) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(A.work, int(__popcll(bal)));
+            base = __shfl(base, leader);
+            if (listed) A.work[kListOff + base + int(__popcll(bal & ((uint64_t(1) << lane) - 1)))] = int32_t(c);
         }
         if (!valid) return;
         if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
+        if (listed) return;
         const bool ok = face_values<T, K>(A, c, ui, 0, a);
-        A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
+        A.flags[c] = uint8_t(1 | (ok ? 0 : 0x80));
     } else {
         if (!valid) return;
 #pragma unroll
@@ -566,6 +531,134 @@ void reconstruct_kernel(ReconArgs<T> A) {
         const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
         A.flags[c] = uint8_t(ok ? 0 : 0x80);
         if constexpr (LABEL) A.label[c] = lab;
+    }
+}
+
+// Full CWENOZ for the listed cells, one wave per cell (a grid-stride loop
+// over the list):
+//  - central coefficients: lane m takes stencil member m, then a butterfly
+//    over the wave sums B_c b into every lane;
+//  - SI_1 = a^T O a: lane e takes upper-triangle entry e of O;
+//  - directional stencils, indicators and weights: dir_sums_wave;
+//  - point values: lane p takes face point p = lf Q + q.
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void reconstruct_wave_kernel(ReconArgs<T> A) {
+    const int lane = int(threadIdx.x & 63);
+    const int64_t nc = A.nc;
+    const int count = A.work[0];
+    const int64_t stride = int64_t(gridDim.x) * (blockDim.x >> 6);
+    for (int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); idx < count; idx += stride) {
+        const int64_t c = A.work[kListOff + idx];
+        double ui[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ui[v] = A.U[v * nc + c];
+        // central coefficients
+        T a[K][5];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) a[k][v] = T(0);
+        if (lane < A.MC) {
+            const int32_t j = A.sten_c[int64_t(lane) * nc + c];
+            T bv[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) bv[v] = T(A.U[v * nc + j] - ui[v]);
+            const T* bp = A.Bc + int64_t(lane) * K * nc + c;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T bk = bp[int64_t(k) * nc];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) a[k][v] = bk * bv[v];
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) a[k][v] += __shfl_xor(a[k][v], off);
+        // SI_1 over the upper triangle of O (off-diagonal entries twice)
+        T SI1[5] = {T(0), T(0), T(0), T(0), T(0)};
+        constexpr int NT = K * (K + 1) / 2;
+        for (int e0 = 0; e0 < NT; e0 += 64) {
+            const int e = e0 + lane;
+            if (e < NT) {
+                int k = 0, rem = e;
+                while (rem >= K - k) {
+                    rem -= K - k;
+                    ++k;
+                }
+                const int l = k + rem;
+                const T o = A.O[int64_t(e) * nc + c] * (l == k ? T(1) : T(2));
+                T ak[5], al[5];
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) {
+                        if (kk == k) ak[v] = a[kk][v];
+                        if (kk == l) al[v] = a[kk][v];
+                    }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) SI1[v] += o * ak[v] * al[v];
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) SI1[v] += __shfl_xor(SI1[v], off);
+        const int nd = A.ndir[c];
+        if (nd > 0) {
+            const T lam_s = T(1) / (A.lam_c + T(nd));
+            const T lam_1 = A.lam_c * lam_s;
+            T inv1[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                SI1[v] = fmax(SI1[v], T(0));
+                inv1[v] = T(1) / (A.eps + SI1[v]);
+            }
+            T tsum[5], Lsum[5], Gs[3][5];
+            dir_sums_wave<T, K>(A, c, ui, SI1, inv1, nd, lam_s, tsum, Lsum, Gs);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T tau = tsum[v] / T(nd);
+                const T W = T(1) + tau * (lam_1 * inv1[v] + Lsum[v]);
+                const T s1 = (T(1) + tau * inv1[v]) / W;
+                const T tw = tau / W;
+#pragma unroll
+                for (int k = 0; k < K; ++k) a[k][v] = s1 * a[k][v] + (k < 3 ? tw * Gs[k < 3 ? k : 0][v] : T(0));
+            }
+        }
+        // point values, one lane per face point
+        bool ok = true;
+        const int Q = A.Q;
+        for (int p0 = 0; p0 < A.NF * Q; p0 += 64) {
+            const int p = p0 + lane;
+            if (p < A.NF * Q) {
+                const int lf = p / Q, q = p - lf * Q;
+                const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
+                if (f2 >= 0 && q < int(A.fnq[f2 >> 1])) {
+                    const T* pp = A.Phi + int64_t(p) * K * nc + c;
+                    T d[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const T ph = pp[int64_t(k) * nc];
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) d[v] += ph * a[k][v];
+                    }
+                    T val[5];
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
+                    const T pr =
+                        A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+                    ok = (val[0] > T(1e-10)) && (pr > T(1e-10));
+                    T* out = A.fs + int64_t(p) * 5 * nc + c;
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) out[int64_t(v) * nc] = val[v];
+                }
+            }
+        }
+        const bool all_ok = __ballot(!ok) == 0;
+        if (lane == 0) A.flags[c] = uint8_t(all_ok ? 0 : 0x80);
     }
 }
 

@@ -30,7 +30,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
-constexpr int kCoopMax = 12;      // gated recon: up to this many full cells per wave go wave-cooperative
+constexpr int kListOff = 64;      // gate work list: counter in [0], cell ids from [64]
+constexpr int kWaveBlocks = 2048; // grid of the one-wave-per-cell pass over the work list
 
 // The dispatcher hands workgroups to the eight XCDs round robin (block b runs
 // on XCD b mod 8).  Renumbered this way, each XCD takes one contiguous range
@@ -106,6 +107,7 @@ struct ReconArgs {
     // troubled-cell gate (network inside the kernel) and its features
     const float* mlp;
     uint8_t* mask_out;
+    int32_t* work;  // counter + list of the cells the gate leaves for full CWENOZ
     const int32_t* nbr;
     const T* ndc;
     const T* hb;
@@ -328,63 +330,66 @@ __device__ void viscous_flux(const PhysT<T>& P, const T* uL, const T* uR, const 
     Fv[4] = e;
 }
 
-// QG lanes per face (QG >= points per face, power of two); the Gauss-point
-// sum is a butterfly over the group's lanes.
-template <class T, int QG>
+// One lane per face; the Gauss-point sum is the lane's own loop.  Adjacent
+// lanes take adjacent faces (numbered by owner), so each point-state load of
+// a wave reads a few contiguous runs of the owners' and neighbours' slots,
+// and the cell gradients and face geometry are read once per face.
+template <class T>
 __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<T> P, BcT<T> B) {
-    const int64_t tid = xcd_block() * blockDim.x + threadIdx.x;
-    const int64_t f = tid / QG;
-    const int q = int(tid % QG);
-    if (f >= A.nf) return;  // whole groups leave together
-    T F[5] = {T(0), T(0), T(0), T(0), T(0)};
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
+    if (f >= A.nf) return;
+    const int64_t nc = A.nc;
+    const int Q = A.Q;
     const int nq = A.fnq[f];
-    if (q < nq) {
-        const T n[3] = {A.fnrm[3 * f], A.fnrm[3 * f + 1], A.fnrm[3 * f + 2]};
-        const int32_t cL = A.fcell[2 * f], cR = A.fcell[2 * f + 1];
-        T uL[5], uR[5];
-        // point states in the cell-fastest slots [lf][q][v][cell] of each side
-        const T* pL = A.fs + int64_t(A.flf[2 * f] * A.Q + q) * 5 * A.nc + cL;
+    const T n[3] = {A.fnrm[3 * f], A.fnrm[3 * f + 1], A.fnrm[3 * f + 2]};
+    const int32_t cL = A.fcell[2 * f], cR = A.fcell[2 * f + 1];
+    // point states in the cell-fastest slots [lf][q][v][cell] of each side
+    const T* pL = A.fs + int64_t(A.flf[2 * f]) * Q * 5 * nc + cL;
+    const T* pR = cR >= 0 ? A.fs + int64_t(A.flf[2 * f + 1]) * Q * 5 * nc + cR : pL;
+    T avg[5];
+    if (cR < 0) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) uL[v] = pL[v * A.nc];
+        for (int v = 0; v < 5; ++v) avg[v] = T(A.U[v * nc + cL]);
+    }
+    T gL[12], gR[12], Lint = T(1);
+    if (P.viscous) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            gL[k] = A.gradW[k * nc + cL];
+            gR[k] = cR >= 0 ? A.gradW[k * nc + cR] : gL[k];
+        }
+        const T dx = A.fdc[3 * f], dy = A.fdc[3 * f + 1], dz = A.fdc[3 * f + 2];
+        Lint = sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    T F[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll 2
+    for (int q = 0; q < nq; ++q) {
+        T uL[5], uR[5], Fq[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) uL[v] = pL[int64_t(q * 5 + v) * nc];
         if (cR >= 0) {
-            const T* pR = A.fs + int64_t(A.flf[2 * f + 1] * A.Q + q) * 5 * A.nc + cR;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) uR[v] = pR[v * A.nc];
+            for (int v = 0; v < 5; ++v) uR[v] = pR[int64_t(q * 5 + v) * nc];
         } else {
-            T avg[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) avg[v] = T(A.U[v * A.nc + cL]);
             ghost(B, -1 - cR, uL, avg, uR);
         }
         if (P.flux == UCNS_HLLC)
-            hllc_flux(P, uL, uR, n, F);
+            hllc_flux(P, uL, uR, n, Fq);
         else
-            rusanov_flux(P, uL, uR, n, F);
+            rusanov_flux(P, uL, uR, n, Fq);
         if (P.viscous) {
-            T gL[12], gR[12], Fv[5];
+            T Fv[5];
+            viscous_flux(P, uL, uR, gL, gR, n, Lint, Fv);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                gL[k] = A.gradW[k * A.nc + cL];
-                gR[k] = cR >= 0 ? A.gradW[k * A.nc + cR] : gL[k];
-            }
-            const T dx = A.fdc[3 * f], dy = A.fdc[3 * f + 1], dz = A.fdc[3 * f + 2];
-            viscous_flux(P, uL, uR, gL, gR, n, sqrt(dx * dx + dy * dy + dz * dz), Fv);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) F[v] -= Fv[v];
+            for (int v = 0; v < 5; ++v) Fq[v] -= Fv[v];
         }
-        const T w = A.fw[f * A.Q + q];
+        const T w = A.fw[f * Q + q];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) F[v] *= w;
+        for (int v = 0; v < 5; ++v) F[v] += w * Fq[v];
     }
+    const T ar = A.farea[f];
 #pragma unroll
-    for (int off = QG / 2; off > 0; off >>= 1)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) F[v] += __shfl_xor(F[v], off, QG);
-    if (q == 0) {
-        const T ar = A.farea[f];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) A.ff[f * 5 + v] = ar * F[v];
-    }
+    for (int v = 0; v < 5; ++v) A.ff[f * 5 + v] = ar * F[v];
 }
 
 // ----------------------------------------------------- residual + RK stage
@@ -563,6 +568,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.gate = gate ? gate->mask : nullptr;
     A.mlp = gate ? gate->mlp : nullptr;
     A.mask_out = gate ? gate->mask_out : nullptr;
+    A.work = gate ? gate->work : nullptr;
     A.nbr = arena_ptr<int32_t>(ar, ar.nbr);
     A.ndc = arena_ptr<T>(ar, ar.ndc);
     A.hb = arena_ptr<T>(ar, ar.hb);
@@ -576,11 +582,16 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     return A;
 }
 
+__global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
+
 template <class T, int K>
 int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
     const dim3 grid(grid_for(A.nc)), block(kBlock);
     if (A.mlp || A.gate) {
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, st, A.work);
         hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
+        const unsigned wb = std::min<unsigned>(kWaveBlocks, unsigned((A.nc + kBlock / 64 - 1) / (kBlock / 64)));
+        hipLaunchKernelGGL((reconstruct_wave_kernel<T, K>), dim3(wb), block, 0, st, A);
     } else {
         if (A.label)
             hipLaunchKernelGGL((reconstruct_kernel<T, K, true, false>), grid, block, 0, st, A);
@@ -767,6 +778,8 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     UCNS_REQUIRE(!(gate && gate->mask && gate->mlp), UCNS_EINVAL, "gate: give a mask or a network, not both");
     UCNS_REQUIRE(!(gate && (gate->mask || gate->mlp) && label), UCNS_EINVAL,
                  "labels are produced by the ungated reconstruction only");
+    UCNS_REQUIRE(!(gate && (gate->mask || gate->mlp)) || (gate->work && aligned(gate->work)), UCNS_EINVAL,
+                 "gate: a 256-byte aligned work buffer of n_cell + 64 int32 is required");
     const double gm1 = phys->gamma - 1.0;
     const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
                                          : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);
@@ -812,20 +825,14 @@ int ucns_face_flux(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
     const Arena& ar = m.arena[precision];
     UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int QG = m.qmax <= 4 ? 4 : 16;
-    const int64_t nthreads = m.nf * QG;
     auto go = [&](auto zero) {
         using T = decltype(zero);
         FluxArgs<T> A{U, static_cast<const T*>(face_state), m.nf, m.nc, m.qmax, arena_ptr<int32_t>(ar, ar.fcell),
                       arena_ptr<uint8_t>(ar, ar.flf), arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<T>(ar, ar.fw),
                       arena_ptr<T>(ar, ar.fdc), arena_ptr<uint8_t>(ar, ar.fnq), static_cast<const T*>(gradW),
                       static_cast<T*>(face_flux)};
-        if (QG == 4)
-            hipLaunchKernelGGL((face_flux_kernel<T, 4>), dim3(grid_for(nthreads)), dim3(kBlock), 0, st, A,
-                               make_phys<T>(phys), make_bc<T>(bc));
-        else
-            hipLaunchKernelGGL((face_flux_kernel<T, 16>), dim3(grid_for(nthreads)), dim3(kBlock), 0, st, A,
-                               make_phys<T>(phys), make_bc<T>(bc));
+        hipLaunchKernelGGL((face_flux_kernel<T>), dim3(grid_for(m.nf)), dim3(kBlock), 0, st, A, make_phys<T>(phys),
+                           make_bc<T>(bc));
     };
     if (precision == UCNS_F64)
         go(double(0));
