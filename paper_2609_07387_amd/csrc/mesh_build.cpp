@@ -649,6 +649,7 @@ int build_operators(Mesh& m, int nt) {
     m.mean.assign(size_t(m.nc) * K, 0);
     m.O.assign(size_t(m.nc) * K * K, 0);
     m.Phi.assign(size_t(m.nc) * NF * Q * K, 0);
+    m.xi.assign(size_t(m.nc) * NF * Q * 3, 0);
     // central operators: stride = largest stencil before rank extension;
     // the rare extended cells go to an overflow map
     int stride0 = 0;
@@ -765,6 +766,7 @@ int build_operators(Mesh& m, int nt) {
                     for (int a = 0; a < 3; ++a)
                         x[a] = m.fqp[(size_t(f) * Q + q) * 3 + a] - (side ? m.fshift[3 * f + a] : 0.0);
                     Vec3 xi = (1.0 / h) * (x - ci);
+                    for (int a = 0; a < 3; ++a) m.xi[((size_t(c) * NF + lf) * Q + q) * 3 + a] = xi[a];
                     double* phi = &m.Phi[((size_t(c) * NF + lf) * Q + q) * K];
                     for (int k = 0; k < K; ++k) {
                         const int* ek = mo.e[k];
@@ -915,7 +917,8 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     auto* sten_d = reinterpret_cast<int32_t*>(base + a.sten_d);
     auto* Bd = reinterpret_cast<T*>(base + a.Bd);
     auto* O = reinterpret_cast<T*>(base + a.O);
-    auto* Phi = reinterpret_cast<T*>(base + a.Phi);
+    auto* xi = reinterpret_cast<T*>(base + a.xi);
+    auto* pmean = reinterpret_cast<T*>(base + a.pmean);
     auto* c2f = reinterpret_cast<int32_t*>(base + a.c2f);
     auto* vol = reinterpret_cast<double*>(base + a.vol);
     auto* hdt = reinterpret_cast<double*>(base + a.hdt);
@@ -976,11 +979,12 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
         int t = 0;
         for (int k = 0; k < K; ++k)
             for (int l = k; l < K; ++l) O[size_t(t++) * nc + c] = T(m.O[(size_t(c) * K + k) * K + l]);
+        for (int k = 0; k < K; ++k) pmean[size_t(k) * nc + c] = T(m.mean[size_t(c) * K + k]);
         for (int lf = 0; lf < NF; ++lf) {
             c2f[size_t(lf) * nc + c] = m.c2f[c * kMaxFaces + lf];
             for (int q = 0; q < Q; ++q)
-                for (int k = 0; k < K; ++k)
-                    Phi[((size_t(lf) * Q + q) * K + k) * nc + c] = T(m.Phi[((size_t(c) * NF + lf) * Q + q) * K + k]);
+                for (int d = 0; d < 3; ++d)
+                    xi[((size_t(lf) * Q + q) * 3 + d) * nc + c] = T(m.xi[((size_t(c) * NF + lf) * Q + q) * 3 + d]);
         }
         vol[c] = m.vol[c];
         hdt[c] = m.hdt[c];
@@ -1017,7 +1021,8 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.sten_d = take(4 * ND * MD * nc);
     a.Bd = take(ts * ND * 3 * MD * nc);
     a.O = take(ts * K * (K + 1) / 2 * nc);
-    a.Phi = take(ts * NF * Q * K * nc);
+    a.xi = take(ts * NF * Q * 3 * nc);
+    a.pmean = take(ts * K * nc);
     a.c2f = take(4 * NF * nc);
     a.vol = take(8 * nc);
     a.hdt = take(8 * nc);

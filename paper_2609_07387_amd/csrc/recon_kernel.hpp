@@ -180,6 +180,38 @@ __device__ __forceinline__ void si_opt(const ReconArgs<T>& A, int64_t c, const T
     for (int v = 0; v < 5; ++v) SI1[v] = fmax(SI1[v], T(0));
 }
 
+// Basis functions at a face point from its offset (x, y, z) in the cell's
+// scaled frame: the monomials of degree 1..r in graded-lex order (x exponent
+// descending, then y) minus their cell means pm.  Recomputing them costs a
+// few multiplies and reads 3 values per point instead of K.
+template <class T, int K>
+__device__ __forceinline__ void basis_at(T x, T y, T z, const T* pm, T* ph) {
+    ph[0] = x - pm[0];
+    ph[1] = y - pm[1];
+    ph[2] = z - pm[2];
+    if constexpr (K >= 9) {
+        ph[3] = x * x - pm[3];
+        ph[4] = x * y - pm[4];
+        ph[5] = x * z - pm[5];
+        ph[6] = y * y - pm[6];
+        ph[7] = y * z - pm[7];
+        ph[8] = z * z - pm[8];
+    }
+    if constexpr (K >= 19) {
+        const T xx = x * x, yy = y * y, zz = z * z;
+        ph[9] = xx * x - pm[9];
+        ph[10] = xx * y - pm[10];
+        ph[11] = xx * z - pm[11];
+        ph[12] = x * yy - pm[12];
+        ph[13] = x * y * z - pm[13];
+        ph[14] = x * zz - pm[14];
+        ph[15] = yy * y - pm[15];
+        ph[16] = yy * z - pm[16];
+        ph[17] = y * zz - pm[17];
+        ph[18] = zz * z - pm[18];
+    }
+}
+
 // Point values at the cell's face quadrature points (step vii) from the
 // coefficients a (first order when mode == 2), stored in the cell-fastest
 // slots [lf][q][v][cell] so that a wave's stores are contiguous; returns
@@ -192,36 +224,44 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
     const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T));
     const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
     const auto rC = rsrc(A.c2f, uint64_t(NF) * rowI);
+    T pm[K];
+    {
+        const auto rM = rsrc(A.pmean, uint64_t(K) * rowT);
+#pragma unroll
+        for (int k = 0; k < K; ++k) pm[k] = bld<T>(rM, cT, uint32_t(k) * rowT);
+    }
     bool ok = true;
     // the loops are wave-uniform (every lane walks all NF x Q slots); a lane
-    // skips the slots its cell does not have.  Phi of point (lf, q) in rows
-    // ((lf Q + q) K + k), the point's state in rows ((lf Q + q) 5 + v).
+    // skips the slots its cell does not have.  The offset of point (lf, q) in
+    // rows ((lf Q + q) 3 + d), the point's state in rows ((lf Q + q) 5 + v).
 #pragma unroll 1
     for (int lf = 0; lf < NF; ++lf) {
         const int32_t f2 = bld<int32_t>(rC, c4, uint32_t(lf) * rowI);
         const int nq = f2 < 0 ? 0 : int(A.fnq[f2 >> 1]);
-        T p0[K];
+        T x0[3];
         {
-            const auto rP = rsrc(A.Phi + int64_t(lf) * Q * K * nc, uint64_t(K) * rowT);
+            const auto rX = rsrc(A.xi + int64_t(lf) * Q * 3 * nc, uint64_t(3) * rowT);
 #pragma unroll
-            for (int k = 0; k < K; ++k) p0[k] = bld<T>(rP, cT, uint32_t(k) * rowT);
+            for (int d = 0; d < 3; ++d) x0[d] = bld<T>(rX, cT, uint32_t(d) * rowT);
         }
 #pragma unroll 1
         for (int q = 0; q < Q; ++q) {
             const int qn = q + 1 < Q ? q + 1 : q;
-            T p1[K];
-            const auto rP = rsrc(A.Phi + (int64_t(lf) * Q + qn) * K * nc, uint64_t(K) * rowT);
+            T x1[3];
+            const auto rX = rsrc(A.xi + (int64_t(lf) * Q + qn) * 3 * nc, uint64_t(3) * rowT);
 #pragma unroll
-            for (int k = 0; k < K; ++k) p1[k] = bld<T>(rP, cT, uint32_t(k) * rowT);
+            for (int d = 0; d < 3; ++d) x1[d] = bld<T>(rX, cT, uint32_t(d) * rowT);
             if (q < nq) {
                 T d[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) d[v] = T(0);
                 if (mode != 2) {
+                    T ph[K];
+                    basis_at<T, K>(x0[0], x0[1], x0[2], pm, ph);
 #pragma unroll
                     for (int k = 0; k < K; ++k)
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) d[v] += p0[k] * a[k][v];
+                        for (int v = 0; v < 5; ++v) d[v] += ph[k] * a[k][v];
                 }
                 T val[5];
 #pragma unroll
@@ -234,7 +274,7 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
                 for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cT, uint32_t(v) * rowT);
             }
 #pragma unroll
-            for (int k = 0; k < K; ++k) p0[k] = p1[k];
+            for (int d = 0; d < 3; ++d) x0[d] = x1[d];
         }
     }
     return ok;
@@ -540,37 +580,51 @@ __global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
 //    over the wave sums B_c b into every lane;
 //  - SI_1 = a^T O a: lane e takes upper-triangle entry e of O;
 //  - directional stencils, indicators and weights: dir_sums_wave;
-//  - point values: lane p takes face point p = lf Q + q.
+//  - point values: lane p takes face point p = lf Q + q (basis recomputed
+//    from the point's offset).
 template <class T, int K>
 __global__ __launch_bounds__(kBlock) void reconstruct_wave_kernel(ReconArgs<T> A) {
     const int lane = int(threadIdx.x & 63);
     const int64_t nc = A.nc;
     const int count = A.work[0];
+    const int Q = A.Q, NP = A.NF * A.Q;
+    constexpr int NT = K * (K + 1) / 2;
     const int64_t stride = int64_t(gridDim.x) * (blockDim.x >> 6);
     for (int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); idx < count; idx += stride) {
         const int64_t c = A.work[kListOff + idx];
+        // every load that needs only c, issued together: the cell state, this
+        // lane's central member and its operator column, its entry of O, its
+        // face point's offset and face
         double ui[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) ui[v] = A.U[v * nc + c];
-        // central coefficients
+        const bool cm = lane < A.MC;
+        const int32_t jc = cm ? A.sten_c[int64_t(lane) * nc + c] : int32_t(c);
+        T bc[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) bc[k] = cm ? A.Bc[(int64_t(lane) * K + k) * nc + c] : T(0);
+        const T o_lane = lane < NT ? A.O[int64_t(lane) * nc + c] : T(0);
+        const bool pt = lane < NP;
+        const int32_t f2 = pt ? A.c2f[int64_t(lane / Q) * nc + c] : -1;
+        T xp[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xp[d] = pt ? A.xi[(int64_t(lane) * 3 + d) * nc + c] : T(0);
+        T pm[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) pm[k] = A.pmean[int64_t(k) * nc + c];
+        const int nd = A.ndir[c];
+        // central coefficients: this lane's member, then a butterfly over the wave
         T a[K][5];
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) a[k][v] = T(0);
-        if (lane < A.MC) {
-            const int32_t j = A.sten_c[int64_t(lane) * nc + c];
+        {
             T bv[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) bv[v] = T(A.U[v * nc + j] - ui[v]);
-            const T* bp = A.Bc + int64_t(lane) * K * nc + c;
+            for (int v = 0; v < 5; ++v) bv[v] = cm ? T(A.U[v * nc + jc] - ui[v]) : T(0);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const T bk = bp[int64_t(k) * nc];
+            for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) a[k][v] = bk * bv[v];
-            }
+                for (int v = 0; v < 5; ++v) a[k][v] = bc[k] * bv[v];
         }
+        const int nq = f2 >= 0 ? int(A.fnq[f2 >> 1]) : 0;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1)
 #pragma unroll
@@ -579,7 +633,6 @@ __global__ __launch_bounds__(kBlock) void reconstruct_wave_kernel(ReconArgs<T> A
                 for (int v = 0; v < 5; ++v) a[k][v] += __shfl_xor(a[k][v], off);
         // SI_1 over the upper triangle of O (off-diagonal entries twice)
         T SI1[5] = {T(0), T(0), T(0), T(0), T(0)};
-        constexpr int NT = K * (K + 1) / 2;
         for (int e0 = 0; e0 < NT; e0 += 64) {
             const int e = e0 + lane;
             if (e < NT) {
@@ -589,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void reconstruct_wave_kernel(ReconArgs<T> A
                     ++k;
                 }
                 const int l = k + rem;
-                const T o = A.O[int64_t(e) * nc + c] * (l == k ? T(1) : T(2));
+                const T o = (e0 == 0 ? o_lane : A.O[int64_t(e) * nc + c]) * (l == k ? T(1) : T(2));
                 T ak[5], al[5];
 #pragma unroll
                 for (int kk = 0; kk < K; ++kk)
@@ -606,7 +659,6 @@ __global__ __launch_bounds__(kBlock) void reconstruct_wave_kernel(ReconArgs<T> A
         for (int off = 1; off < 64; off <<= 1)
 #pragma unroll
             for (int v = 0; v < 5; ++v) SI1[v] += __shfl_xor(SI1[v], off);
-        const int nd = A.ndir[c];
         if (nd > 0) {
             const T lam_s = T(1) / (A.lam_c + T(nd));
             const T lam_1 = A.lam_c * lam_s;
@@ -628,33 +680,37 @@ __global__ __launch_bounds__(kBlock) void reconstruct_wave_kernel(ReconArgs<T> A
                 for (int k = 0; k < K; ++k) a[k][v] = s1 * a[k][v] + (k < 3 ? tw * Gs[k < 3 ? k : 0][v] : T(0));
             }
         }
-        // point values, one lane per face point
+        // point values, one lane per face point (points past the first 64 in a loop)
         bool ok = true;
-        const int Q = A.Q;
-        for (int p0 = 0; p0 < A.NF * Q; p0 += 64) {
+        for (int p0 = 0; p0 < NP; p0 += 64) {
             const int p = p0 + lane;
-            if (p < A.NF * Q) {
-                const int lf = p / Q, q = p - lf * Q;
-                const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
-                if (f2 >= 0 && q < int(A.fnq[f2 >> 1])) {
-                    const T* pp = A.Phi + int64_t(p) * K * nc + c;
-                    T d[5] = {T(0), T(0), T(0), T(0), T(0)};
+            int nqp = nq;
+            int32_t f2p = f2;
+            if (p0 > 0) {
+                f2p = p < NP ? A.c2f[int64_t(p / Q) * nc + c] : -1;
+                nqp = f2p >= 0 ? int(A.fnq[f2p >> 1]) : 0;
+            }
+            if (f2p >= 0 && p - (p / Q) * Q < nqp) {
+                T d[5] = {T(0), T(0), T(0), T(0), T(0)};
+                if (p0 > 0) {
 #pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        const T ph = pp[int64_t(k) * nc];
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) d[v] += ph * a[k][v];
-                    }
-                    T val[5];
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
-                    const T pr =
-                        A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-                    ok = (val[0] > T(1e-10)) && (pr > T(1e-10));
-                    T* out = A.fs + int64_t(p) * 5 * nc + c;
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) out[int64_t(v) * nc] = val[v];
+                    for (int e = 0; e < 3; ++e) xp[e] = A.xi[(int64_t(p) * 3 + e) * nc + c];
                 }
+                T ph[K];
+                basis_at<T, K>(xp[0], xp[1], xp[2], pm, ph);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) d[v] += ph[k] * a[k][v];
+                T val[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
+                const T pr =
+                    A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+                ok = ok && (val[0] > T(1e-10)) && (pr > T(1e-10));
+                T* out = A.fs + int64_t(p) * 5 * nc + c;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) out[int64_t(v) * nc] = val[v];
             }
         }
         const bool all_ok = __ballot(!ok) == 0;

@@ -23,7 +23,7 @@ void set_error(const std::string& msg);
 // Offsets (bytes) of every array inside one precision's device arena.
 struct Arena {
     size_t bytes = 0;
-    size_t sten_c = 0, Bc = 0, ndir = 0, sten_d = 0, Bd = 0, O = 0, Phi = 0, c2f = 0;
+    size_t sten_c = 0, Bc = 0, ndir = 0, sten_d = 0, Bd = 0, O = 0, xi = 0, pmean = 0, c2f = 0;
     size_t vol = 0, hdt = 0, fcell = 0, flf = 0, fnrm = 0, farea = 0, fw = 0, fdc = 0, fnq = 0;
     size_t nbr = 0, ndc = 0, hb = 0, ncen = 0;  // gate features: face neighbours, offsets, basis scale, stencil size
     void* dev = nullptr;  // caller-owned device pointer after upload
@@ -64,6 +64,7 @@ struct Mesh {
     std::vector<double> Bd;       // [nc][nd_max][3][md_pad]
     std::vector<double> O;        // [nc][K][K]
     std::vector<double> Phi;      // [nc][nfmax][qmax][K]
+    std::vector<double> xi;       // [nc][nfmax][qmax][3] face points in the cell's scaled frame
     std::vector<double> mean;     // [nc][K]
     // ---- device arenas
     Arena arena[2];

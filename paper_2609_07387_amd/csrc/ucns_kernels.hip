@@ -95,7 +95,8 @@ struct ReconArgs {
     int ND;       // directional stencil slots per cell (cells with fewer pad with zero operators)
     int MD, MDG;  // padded directional stencil size, and rounded up to a power of two
     const T* O;
-    const T* Phi;
+    const T* xi;     // face points in each cell's scaled frame [lf][q][3][nc]
+    const T* pmean;  // cell means of the scaled monomials [K][nc]
     const int32_t* c2f;
     const uint8_t* fnq;
     int Q, NF;
@@ -560,7 +561,8 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.MDG = 1;
     while (A.MDG < A.MD) A.MDG <<= 1;
     A.O = arena_ptr<T>(ar, ar.O);
-    A.Phi = arena_ptr<T>(ar, ar.Phi);
+    A.xi = arena_ptr<T>(ar, ar.xi);
+    A.pmean = arena_ptr<T>(ar, ar.pmean);
     A.c2f = arena_ptr<int32_t>(ar, ar.c2f);
     A.fnq = arena_ptr<uint8_t>(ar, ar.fnq);
     A.Q = m.qmax;
