@@ -55,32 +55,41 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
 #pragma unroll
         for (int v = 0; v < 5; ++v) a[k][v] = T(0);
     if constexpr (FEAT) js[0] = js[1] = js[2] = js[3] = T(0);
-    // prologue: member 0 operands, index of member 1
-    int32_t j1 = bld<int32_t>(rS, c4, MC > 1 ? rowI : 0u);
-    const int32_t j0 = bld<int32_t>(rS, c4, 0u);
-    double u0[5];
-    T b0[K];
+    // Loads run DEPTH members ahead of the arithmetic (member ids one further):
+    // two in FP32, where a member's operators are half the bytes and the
+    // registers allow it, one in FP64.
+    constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+    auto last = [&](int m) { return m < MC ? m : MC - 1; };
+    double u[DEPTH + 1][5];
+    T b[DEPTH + 1][K];
+    int32_t jn[DEPTH + 1];  // ids of members m+1 .. m+DEPTH+1 (jn[0] unused after the prologue)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) u0[v] = bld<double>(rU, uint32_t(j0) * 8u, uint32_t(v) * rowU);
-    {
-        const auto rB = rsrc(A.Bc, uint64_t(K) * rowT);
+    for (int d = 0; d <= DEPTH; ++d) jn[d] = bld<int32_t>(rS, c4, uint32_t(last(d)) * rowI);
 #pragma unroll
-        for (int k = 0; k < K; ++k) b0[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+    for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
+        const auto rB = rsrc(A.Bc + int64_t(last(d)) * K * nc, uint64_t(K) * rowT);
+#pragma unroll
+        for (int k = 0; k < K; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
     }
-#pragma unroll 2
+    int32_t jnext = jn[DEPTH];  // id of member DEPTH
+#pragma unroll DEPTH + 1
     for (int m = 0; m < MC; ++m) {
-        const int mn = m + 1 < MC ? m + 1 : m;
-        const int32_t j2 = bld<int32_t>(rS, c4, uint32_t(m + 2 < MC ? m + 2 : mn) * rowI);
-        double u1[5];
-        T b1[K];
+        // issue member m+DEPTH (operands) and the id of member m+DEPTH+1
+        const int mf = last(m + DEPTH);
+        const int32_t jf = bld<int32_t>(rS, c4, uint32_t(last(m + DEPTH + 1)) * rowI);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) u1[v] = bld<double>(rU, uint32_t(j1) * 8u, uint32_t(v) * rowU);
-        const auto rB = rsrc(A.Bc + int64_t(mn) * K * nc, uint64_t(K) * rowT);
+        for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
+        {
+            const auto rB = rsrc(A.Bc + int64_t(mf) * K * nc, uint64_t(K) * rowT);
 #pragma unroll
-        for (int k = 0; k < K; ++k) b1[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+            for (int k = 0; k < K; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+        }
+        // member m
         T bv[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
+        for (int v = 0; v < 5; ++v) bv[v] = T(u[0][v] - ui[v]);
         if constexpr (FEAT) {
             js[0] = fmax(js[0], fabs(bv[0]));
             js[1] += fabs(bv[0]);
@@ -90,12 +99,15 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) a[k][v] += b0[k] * bv[v];
+            for (int v = 0; v < 5; ++v) a[k][v] += b[0][k] * bv[v];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) u0[v] = u1[v];
+        for (int d = 0; d < DEPTH; ++d) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) b0[k] = b1[k];
-        j1 = j2;
+            for (int v = 0; v < 5; ++v) u[d][v] = u[d + 1][v];
+#pragma unroll
+            for (int k = 0; k < K; ++k) b[d][k] = b[d + 1][k];
+        }
+        jnext = jf;
     }
 }
 
@@ -320,17 +332,23 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
         const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
         const auto rS = rsrc(A.sten_d, uint64_t(total) * rowI);
         const auto rU = rsrc(A.U, uint64_t(5) * rowU);
-        int32_t j1 = bld<int32_t>(rS, c4, total > 1 ? rowI : 0u);
-        const int32_t j0 = bld<int32_t>(rS, c4, 0u);
-        double u0[5];
-        T b0[3];
+        // loads DEPTH members ahead (ids one further), as in central_coeffs
+        constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+        auto last = [&](int t) { return t < total ? t : total - 1; };
+        double u[DEPTH + 1][5];
+        T b[DEPTH + 1][3];
+        int32_t jn[DEPTH + 1];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) u0[v] = bld<double>(rU, uint32_t(j0) * 8u, uint32_t(v) * rowU);
-        {
-            const auto rB = rsrc(A.Bd, uint64_t(3) * rowT);
+        for (int d = 0; d <= DEPTH; ++d) jn[d] = bld<int32_t>(rS, c4, uint32_t(last(d)) * rowI);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) b0[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+        for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
+            const auto rB = rsrc(A.Bd + int64_t(last(d)) * 3 * nc, uint64_t(3) * rowT);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
         }
+        int32_t jnext = jn[DEPTH];
         T as[3][5];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -339,23 +357,22 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
         int m = 0, s = 0;
 #pragma unroll 1
         for (int t = 0; t < total; ++t) {
-            const int tn = t + 1 < total ? t + 1 : t;
-            const int t2 = t + 2 < total ? t + 2 : tn;
-            const int32_t j2 = bld<int32_t>(rS, c4, uint32_t(t2) * rowI);
-            double u1[5];
-            T b1[3];
+            const int tf = last(t + DEPTH);
+            const int32_t jf = bld<int32_t>(rS, c4, uint32_t(last(t + DEPTH + 1)) * rowI);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) u1[v] = bld<double>(rU, uint32_t(j1) * 8u, uint32_t(v) * rowU);
-            const auto rB = rsrc(A.Bd + int64_t(tn) * 3 * nc, uint64_t(3) * rowT);
+            for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
+            {
+                const auto rB = rsrc(A.Bd + int64_t(tf) * 3 * nc, uint64_t(3) * rowT);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) b1[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+                for (int k = 0; k < 3; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+            }
             T bv[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) bv[v] = T(u0[v] - ui[v]);
+            for (int v = 0; v < 5; ++v) bv[v] = T(u[0][v] - ui[v]);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) as[k][v] += b0[k] * bv[v];
+                for (int v = 0; v < 5; ++v) as[k][v] += b[0][k] * bv[v];
             if (m + 1 == MD) {
                 // stencil s complete: its indicator and its share of the blend
                 if (s < nd) {
@@ -385,10 +402,13 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
                 ++m;
             }
 #pragma unroll
-            for (int v = 0; v < 5; ++v) u0[v] = u1[v];
+            for (int d = 0; d < DEPTH; ++d) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) b0[k] = b1[k];
-            j1 = j2;
+                for (int v = 0; v < 5; ++v) u[d][v] = u[d + 1][v];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b[d][k] = b[d + 1][k];
+            }
+            jnext = jf;
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
