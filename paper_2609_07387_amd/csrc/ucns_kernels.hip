@@ -127,62 +127,76 @@ __device__ __forceinline__ T pressure(const PhysT<T>& P, const T* u) {
     return P.gm1 * (u[4] - T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0]);
 }
 
+// Primitive quantities of one point state, formed once per Gauss point and
+// shared by the convective and viscous fluxes (one reciprocal of the density
+// instead of a division in every formula).
 template <class T>
-__device__ __forceinline__ void euler_flux(const PhysT<T>& P, const T* u, const T* n, T p, T* F) {
-    const T un = (u[1] * n[0] + u[2] * n[1] + u[3] * n[2]) / u[0];
-    F[0] = u[0] * un;
-    F[1] = u[1] * un + p * n[0];
-    F[2] = u[2] * un + p * n[1];
-    F[3] = u[3] * un + p * n[2];
-    F[4] = (u[4] + p) * un;
+struct Prim {
+    T r, ir, u[3], un, p, c, E;
+};
+
+template <class T>
+__device__ __forceinline__ Prim<T> prim(const PhysT<T>& P, const T* U, const T* n) {
+    Prim<T> q;
+    q.r = U[0];
+    q.ir = T(1) / U[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.u[a] = U[1 + a] * q.ir;
+    q.un = q.u[0] * n[0] + q.u[1] * n[1] + q.u[2] * n[2];
+    q.E = U[4];
+    q.p = P.gm1 * (U[4] - T(0.5) * q.r * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]));
+    q.c = sqrt(P.gamma * q.p * q.ir);
+    return q;
+}
+
+// Physical flux F(U) . n
+template <class T>
+__device__ __forceinline__ void euler_flux(const Prim<T>& q, const T* n, T* F) {
+    F[0] = q.r * q.un;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[1 + a] = q.r * q.u[a] * q.un + q.p * n[a];
+    F[4] = (q.E + q.p) * q.un;
 }
 
 // Rusanov: s = max(|u_nL| + c_L, |u_nR| + c_R).
 template <class T>
-__device__ void rusanov_flux(const PhysT<T>& P, const T* L, const T* R, const T* n, T* F) {
-    const T pL = pressure(P, L), pR = pressure(P, R);
+__device__ void rusanov_flux(const Prim<T>& L, const Prim<T>& R, const T* UL, const T* UR, const T* n, T* F) {
     T FL[5], FR[5];
-    euler_flux(P, L, n, pL, FL);
-    euler_flux(P, R, n, pR, FR);
-    const T unL = (L[1] * n[0] + L[2] * n[1] + L[3] * n[2]) / L[0];
-    const T unR = (R[1] * n[0] + R[2] * n[1] + R[3] * n[2]) / R[0];
-    const T s = fmax(fabs(unL) + sqrt(P.gamma * pL / L[0]), fabs(unR) + sqrt(P.gamma * pR / R[0]));
+    euler_flux(L, n, FL);
+    euler_flux(R, n, FR);
+    const T s = fmax(fabs(L.un) + L.c, fabs(R.un) + R.c);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (R[v] - L[v]);
+    for (int v = 0; v < 5; ++v) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (UR[v] - UL[v]);
 }
 
 // HLLC (Toro, Spruce & Speares) with Davis wave speeds; S* >= 0 takes the
 // left star state.
 template <class T>
-__device__ void hllc_flux(const PhysT<T>& P, const T* L, const T* R, const T* n, T* F) {
-    const T rL = L[0], rR = R[0];
-    const T unL = (L[1] * n[0] + L[2] * n[1] + L[3] * n[2]) / rL;
-    const T unR = (R[1] * n[0] + R[2] * n[1] + R[3] * n[2]) / rR;
-    const T pL = pressure(P, L), pR = pressure(P, R);
-    const T cL = sqrt(P.gamma * pL / rL), cR = sqrt(P.gamma * pR / rR);
-    const T SL = fmin(unL - cL, unR - cR), SR = fmax(unL + cL, unR + cR);
+__device__ void hllc_flux(const Prim<T>& L, const Prim<T>& R, const T* UL, const T* UR, const T* n, T* F) {
+    const T SL = fmin(L.un - L.c, R.un - R.c), SR = fmax(L.un + L.c, R.un + R.c);
     if (SL >= T(0)) {
-        euler_flux(P, L, n, pL, F);
+        euler_flux(L, n, F);
         return;
     }
     if (SR <= T(0)) {
-        euler_flux(P, R, n, pR, F);
+        euler_flux(R, n, F);
         return;
     }
-    const T Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR));
+    const T Ss = (R.p - L.p + L.r * L.un * (SL - L.un) - R.r * R.un * (SR - R.un)) /
+                 (L.r * (SL - L.un) - R.r * (SR - R.un));
     const bool left = Ss >= T(0);
-    const T* Kst = left ? L : R;
-    const T SK = left ? SL : SR, unK = left ? unL : unR, pK = left ? pL : pR;
-    euler_flux(P, Kst, n, pK, F);
-    const T chi = (SK - unK) / (SK - Ss);
-    const T rho = Kst[0];
+    const Prim<T>& K = left ? L : R;
+    const T* UK = left ? UL : UR;
+    const T SK = left ? SL : SR;
+    euler_flux(K, n, F);
+    const T rchi = K.r * (SK - K.un) / (SK - Ss);
     T Us[5];
-    Us[0] = rho * chi;
+    Us[0] = rchi;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Us[1 + a] = rho * chi * (Kst[1 + a] / rho + (Ss - unK) * n[a]);
-    Us[4] = rho * chi * (Kst[4] / rho + (Ss - unK) * (Ss + pK / (rho * (SK - unK))));
+    for (int a = 0; a < 3; ++a) Us[1 + a] = rchi * (K.u[a] + (Ss - K.un) * n[a]);
+    Us[4] = rchi * (K.E * K.ir + (Ss - K.un) * (Ss + K.p / (K.r * (SK - K.un))));
 #pragma unroll
-    for (int v = 0; v < 5; ++v) F[v] += SK * (Us[v] - Kst[v]);
+    for (int v = 0; v < 5; ++v) F[v] += SK * (Us[v] - UK[v]);
 }
 
 template <class T>
@@ -301,19 +315,20 @@ struct FluxArgs {
 };
 
 // Viscous flux F_v . n with the penalised interface gradient
-// grad W_f = (grad W_L + grad W_R)/2 + (4/3)/L_int (W_R - W_L) (x) n.
+// grad W_f = (grad W_L + grad W_R)/2 + (4/3)/L_int (W_R - W_L) (x) n on
+// W = (u, v, w, T); G0 is the face's mean cell gradient, pen = (4/3)/L_int.
 template <class T>
-__device__ void viscous_flux(const PhysT<T>& P, const T* uL, const T* uR, const T* gL, const T* gR, const T* n,
-                             T Lint, T* Fv) {
-    T WL[4], WR[4], G[4][3];
-    prim_W(P, uL, WL);
-    prim_W(P, uR, WR);
-    const T pen = T(4.0 / 3.0) / Lint;
+__device__ void viscous_flux(const PhysT<T>& P, const Prim<T>& L, const Prim<T>& R, const T* G0, const T* n, T pen,
+                             T* Fv) {
+    T dW[4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dW[a] = R.u[a] - L.u[a];
+    dW[3] = P.gM2 * (R.p * R.ir - L.p * L.ir);
+    T G[4][3];
 #pragma unroll
     for (int var = 0; var < 4; ++var)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            G[var][a] = T(0.5) * (gL[3 * var + a] + gR[3 * var + a]) + pen * (WR[var] - WL[var]) * n[a];
+        for (int a = 0; a < 3; ++a) G[var][a] = G0[3 * var + a] + pen * dW[var] * n[a];
     const T div = G[0][0] + G[1][1] + G[2][2];
     T e = T(0);
     Fv[0] = T(0);
@@ -324,7 +339,7 @@ __device__ void viscous_flux(const PhysT<T>& P, const T* uL, const T* uR, const 
         for (int j = 0; j < 3; ++j) t += (G[i][j] + G[j][i] - (i == j ? T(2.0 / 3.0) * div : T(0))) * n[j];
         t *= P.mu;
         Fv[1 + i] = t;
-        e += T(0.5) * (WL[i] + WR[i]) * t;
+        e += T(0.5) * (L.u[i] + R.u[i]) * t;
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) e += P.kappa * G[3][j] * n[j];
@@ -352,15 +367,15 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
 #pragma unroll
         for (int v = 0; v < 5; ++v) avg[v] = T(A.U[v * nc + cL]);
     }
-    T gL[12], gR[12], Lint = T(1);
+    T G0[12], pen = T(0);
     if (P.viscous) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            gL[k] = A.gradW[k * nc + cL];
-            gR[k] = cR >= 0 ? A.gradW[k * nc + cR] : gL[k];
+            const T gl = A.gradW[k * nc + cL];
+            G0[k] = T(0.5) * (gl + (cR >= 0 ? A.gradW[k * nc + cR] : gl));
         }
         const T dx = A.fdc[3 * f], dy = A.fdc[3 * f + 1], dz = A.fdc[3 * f + 2];
-        Lint = sqrt(dx * dx + dy * dy + dz * dz);
+        pen = T(4.0 / 3.0) / sqrt(dx * dx + dy * dy + dz * dz);
     }
     T F[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll 2
@@ -374,13 +389,14 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         } else {
             ghost(B, -1 - cR, uL, avg, uR);
         }
+        const Prim<T> qL = prim(P, uL, n), qR = prim(P, uR, n);
         if (P.flux == UCNS_HLLC)
-            hllc_flux(P, uL, uR, n, Fq);
+            hllc_flux(qL, qR, uL, uR, n, Fq);
         else
-            rusanov_flux(P, uL, uR, n, Fq);
+            rusanov_flux(qL, qR, uL, uR, n, Fq);
         if (P.viscous) {
             T Fv[5];
-            viscous_flux(P, uL, uR, gL, gR, n, Lint, Fv);
+            viscous_flux(P, qL, qR, G0, n, pen, Fv);
 #pragma unroll
             for (int v = 0; v < 5; ++v) Fq[v] -= Fv[v];
         }
