@@ -56,9 +56,9 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
         for (int v = 0; v < 5; ++v) a[k][v] = T(0);
     if constexpr (FEAT) js[0] = js[1] = js[2] = js[3] = T(0);
     // Loads run DEPTH members ahead of the arithmetic (member ids one further):
-    // two in FP32, where a member's operators are half the bytes and the
-    // registers allow it, one in FP64.
-    constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+    // three in FP32, two in FP64 (the kernels' register peak is in the
+    // directional phase, so this costs no occupancy).
+    constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
     auto last = [&](int m) { return m < MC ? m : MC - 1; };
     double u[DEPTH + 1][5];
     T b[DEPTH + 1][K];
