@@ -9,8 +9,8 @@ unit is.  The stored record (a short markdown file with the figures and a
 JSON block) carries a digest of the kernel sources; once the sources change
 the record no longer applies and the benchmark reports no traffic.
 
-  python -m paper_2609_07387_amd.prof stats KERNEL_STATS_CSV TITLE COMMAND > profiles/NAME.md
-  python -m paper_2609_07387_amd.prof traffic FETCH_CSV WRITE_CSV KERNEL_SUBSTRING COPY_BYTES COMMAND OUT_MD
+  python -m paper_2609_07387_amd.prof stats KERNEL_STATS_CSV TITLE COMMAND [TRACE_CSV LABEL=K1|K2=N ...] > profiles/NAME.md
+  python -m paper_2609_07387_amd.prof traffic FETCH_CSV WRITE_CSV K1[|K2...] COPY_BYTES COMMAND OUT_MD [N_LAST]
 """
 from __future__ import annotations
 
@@ -37,16 +37,23 @@ def source_digest() -> str:
 
 
 def _by_kernel(path, counter):
+    """Counter values per kernel name, in dispatch order."""
     vals = {}
     with open(path) as f:
-        for r in csv.DictReader(f):
-            if r["Counter_Name"] == counter:
-                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    for r in rows:
+        vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return vals
 
 
-def _mean_by_kernel(path, counter):
-    return {k: (sum(v) / len(v), len(v)) for k, v in _by_kernel(path, counter).items()}
+def _mean_by_kernel(path, counter, n_last=0):
+    """Mean per kernel over all dispatches, or over the last n_last."""
+    out = {}
+    for k, v in _by_kernel(path, counter).items():
+        w = v[-n_last:] if n_last else v
+        out[k] = (sum(w) / len(w), len(w))
+    return out
 
 
 def _copy_reading(path, counter):
@@ -65,11 +72,22 @@ def _pick(d, sub):
     return hits[0], d[hits[0]]
 
 
-def traffic(fetch_csv, write_csv, kernel, copy_bytes, command):
-    fe = _mean_by_kernel(fetch_csv, "FETCH_SIZE")
-    wr = _mean_by_kernel(write_csv, "WRITE_SIZE")
-    name, (f_kib, nf) = _pick(fe, kernel)
-    _, (w_kib, nw) = _pick(wr, kernel)
+def traffic(fetch_csv, write_csv, kernel, copy_bytes, command, n_last=0):
+    """kernel: one name substring, or several joined by '|' (the kernels of
+    one library call; their per-dispatch means are summed).  n_last: average
+    the last n dispatches only (the window a benchmark times)."""
+    fe = _mean_by_kernel(fetch_csv, "FETCH_SIZE", n_last)
+    wr = _mean_by_kernel(write_csv, "WRITE_SIZE", n_last)
+    names, f_kib, w_kib, nf, nw = [], 0.0, 0.0, [], []
+    for sub in kernel.split("|"):
+        name, (fk, n1) = _pick(fe, sub)
+        _, (wk, n2) = _pick(wr, sub)
+        names.append(name)
+        f_kib += fk
+        w_kib += wk
+        nf.append(n1)
+        nw.append(n2)
+    name = " + ".join(names)
     cf_kib = _copy_reading(fetch_csv, "FETCH_SIZE")
     cw_kib = _copy_reading(write_csv, "WRITE_SIZE")
     f_scale = copy_bytes / (cf_kib * 1024.0)
@@ -79,7 +97,8 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes, command):
     return {"kernel": name, "dispatches": [nf, nw], "fetch_kib": f_kib, "write_kib": w_kib,
             "copy_bytes": copy_bytes, "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib,
             "fetch_scale": f_scale, "write_scale": w_scale, "fetch_bytes": fetch_b, "write_bytes": write_b,
-            "bytes_per_launch": fetch_b + write_b, "source_digest": source_digest(), "command": command}
+            "bytes_per_launch": fetch_b + write_b, "window_last_dispatches": n_last,
+            "source_digest": source_digest(), "command": command}
 
 
 def traffic_md(rec):
@@ -93,7 +112,9 @@ def traffic_md(rec):
         f"{rec['fetch_bytes']:.4g} |",
         f"| WRITE_SIZE | {rec['write_kib']:.1f} | {rec['copy_write_kib']:.1f} | {rec['write_scale']:.3f} | "
         f"{rec['write_bytes']:.4g} |", "",
-        f"Total per launch: {rec['bytes_per_launch']:.4g} bytes.", "",
+        f"Total per launch: {rec['bytes_per_launch']:.4g} bytes"
+        + (f" (mean of the last {rec['window_last_dispatches']} dispatches of each kernel)."
+           if rec.get("window_last_dispatches") else " (mean over all dispatches)."), "",
         "```json", json.dumps(rec, indent=1), "```", ""])
 
 
@@ -110,7 +131,21 @@ def load_traffic(path):
     return rec if rec.get("source_digest") == source_digest() else None
 
 
-def stats_md(stats_csv, title, command, top=14):
+def last_calls_us(trace_csv, kernel, n):
+    """Mean duration (us) of the last n dispatches of each kernel in `kernel`
+    ('|'-joined substrings), and their sum: the window a benchmark times."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    parts = []
+    for sub in kernel.split("|"):
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows if sub in r["Kernel_Name"]]
+        if len(d) < n:
+            raise SystemExit(f"kernel '{sub}': {len(d)} dispatches, fewer than {n}")
+        parts.append((sub, sum(d[-n:]) / n))
+    return parts, sum(p[1] for p in parts)
+
+
+def stats_md(stats_csv, title, command, top=14, trace_csv=None, windows=()):
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = [f"# {title}", "", "Command:", "", "```", command, "```", "",
@@ -118,14 +153,22 @@ def stats_md(stats_csv, title, command, top=14):
     for r in rows[:top]:
         out.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    for label, kernel, n in windows:
+        parts, total = last_calls_us(trace_csv, kernel, n)
+        out += ["", f"**{label}** (mean of the last {n} dispatches of each kernel): "
+                + " + ".join(f"`{k}` {t:.1f} us" for k, t in parts) + f" = **{total:.1f} us** per call."]
     return "\n".join(out) + "\n"
 
 
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
-        sys.stdout.write(stats_md(argv[1], argv[2], argv[3]))
+        # optional trailing args: TRACE_CSV then LABEL=KERNELS=N ...
+        trace = argv[4] if len(argv) > 4 else None
+        wins = [tuple(w.split("=")) for w in argv[5:]]
+        wins = [(lab, ker, int(n)) for lab, ker, n in wins]
+        sys.stdout.write(stats_md(argv[1], argv[2], argv[3], trace_csv=trace, windows=wins))
     elif len(argv) >= 7 and argv[0] == "traffic":
-        rec = traffic(argv[1], argv[2], argv[3], float(argv[4]), argv[5])
+        rec = traffic(argv[1], argv[2], argv[3], float(argv[4]), argv[5], int(argv[7]) if len(argv) > 7 else 0)
         with open(argv[6], "w") as f:
             f.write(traffic_md(rec))
         print(json.dumps(rec))
