@@ -26,8 +26,7 @@ HBM_PEAK_GBS = 8000.0
 # as a whole with HIP events; its kernels, and the record of their measured
 # HBM bytes per call (rocprofv3 counters, summed over the call's kernels)
 RECON_KERNELS = {
-    "fp32_gate": "zero_i32_kernel|reconstruct_kernel<float, 9, false, true>|reconstruct_wave_kernel<float, 9>|"
-                 "reconstruct_fallback_kernel<float, 9>",
+    "fp32_gate": "reconstruct_kernel<float, 9, false, true>|reconstruct_fallback_kernel<float, 9>",
     "fp64_plain": "reconstruct_kernel<double, 9, false, false>|reconstruct_fallback_kernel<double, 9>"}
 TRAFFIC = {"fp32_gate": "traffic_reconstruct_fp32_gate_tgv64.md",
            "fp64_plain": "traffic_reconstruct_fp64_tgv64.md"}
@@ -80,17 +79,17 @@ def time_steps(solver, U, steps, warmup, torch):
     return e0.elapsed_time(e1), wall
 
 
-def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns, mlp=None, mask_out=None, work=None):
+def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns, mlp=None, mask_out=None):
     """Mean duration of one reconstruction call (all the kernels it
     launches), HIP events recorded on the stream the kernels are launched on."""
     s = torch.cuda.current_stream()
     for _ in range(3):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out, work=work)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out, work=work)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -171,7 +170,7 @@ def main():
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
         rate = nc * 3 * args.steps / (ms / 1e3)
         rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns, net,
-                         solver.ws.mask_out, solver.ws.work)
+                         solver.ws.mask_out)
         frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
         gate = net is not None
         rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate)

@@ -114,17 +114,12 @@ typedef struct {
  * precomputed mask (1 = smooth) or the network's parameters (the network then
  * runs inside the reconstruction kernel on each cell's features, smooth when
  * sigmoid(z) < theta); not both.  mask_out (may be NULL) records the
- * network's decisions.  A NULL gate = full CWENOZ everywhere.  With a gate,
- * the cells left for full CWENOZ are listed in work (device int32
- * [n_cell + 64], required, 256-byte aligned, contents scratch) and
- * reconstructed by a second pass that gives each of them a whole wave, so
- * their cost does not depend on how they cluster; calls sharing a work
- * buffer must not overlap.  Labels are not produced with a gate. */
+ * network's decisions.  A NULL gate = full CWENOZ everywhere.  Labels are
+ * not produced with a gate. */
 typedef struct {
     const uint8_t* mask;  /* device [n_cell] or NULL */
     const float* mlp;     /* device parameter block (UCNS_MLP_NPARAM floats) or NULL */
     uint8_t* mask_out;    /* device [n_cell] or NULL */
-    int32_t* work;        /* device [n_cell + 64], required with mask or mlp */
 } ucns_gate;
 
 /* Gate network parameter block (float32) offsets: mu[16] isig[16]

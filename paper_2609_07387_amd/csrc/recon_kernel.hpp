@@ -444,97 +444,24 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
     return face_values<T, K>(A, c, ui, mode, a);
 }
 
-// Steps (iii)-(v) of one cell co taken by the whole wave: lane l handles
-// member l mod G of stencil l / G (G = MD rounded up to a power of two; 64/G
-// stencils per pass).  The stencil sums a_s are butterflies over each group
-// of G lanes, then every stencil's share of the blend is summed over the
-// groups, so every lane returns
-//   tsum = sum_s |SI_1 - SI_s|, Lsum = sum_s lambda_s / (eps + SI_s),
-//   Gs   = sum_s lambda_s (1/(eps+SI_s) - 1/(eps+SI_1)) a_s.
-// All 64 lanes must call it together.
-template <class T, int K>
-__device__ __forceinline__ void dir_sums_wave(const ReconArgs<T>& A, int64_t co, const double* uo, const T* SI1,
-                                              const T* inv1, int nd, T lam_s, T tsum[5], T Lsum[5], T Gs[3][5]) {
-    const int64_t nc = A.nc;
-    const int MD = A.MD, G = A.MDG, per = 64 / A.MDG;
-    const int lane = int(threadIdx.x & 63);
-    const int m = lane & (G - 1);
-    const T o00 = A.O[0 * nc + co], o01 = A.O[1 * nc + co], o02 = A.O[2 * nc + co];
-    const T o11 = A.O[int64_t(K) * nc + co], o12 = A.O[int64_t(K + 1) * nc + co];
-    const T o22 = A.O[int64_t(2 * K - 1) * nc + co];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        tsum[v] = Lsum[v] = T(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) Gs[k][v] = T(0);
-    }
-#pragma unroll 1
-    for (int s0 = 0; s0 < nd; s0 += per) {
-        const int s = s0 + lane / G;
-        T as[3][5];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
-        if (s < nd && m < MD) {
-            const int32_t j = A.sten_d[int64_t(s * MD + m) * nc + co];
-            T bv[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) bv[v] = T(A.U[v * nc + j] - uo[v]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const T bk = A.Bd[(int64_t(s * MD + m) * 3 + k) * nc + co];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) as[k][v] = bk * bv[v];
-            }
-        }
-        for (int off = 1; off < G; off <<= 1)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) as[k][v] += __shfl_xor(as[k][v], off);
-        // every lane of a group now holds its stencil's a_s; add its share
-        if (s < nd) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const T x = as[0][v], y = as[1][v], z = as[2][v];
-                const T SIs = fmax(
-                    x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z, T(0));
-                const T r = T(1) / (A.eps + SIs);
-                tsum[v] += fabs(SI1[v] - SIs);
-                Lsum[v] += lam_s * r;
-                const T coef = lam_s * (r - inv1[v]);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) Gs[k][v] += coef * as[k][v];
-            }
-        }
-    }
-    // sum over the groups: lanes with equal (lane mod G) hold one copy each
-    for (int off = G; off < 64; off <<= 1)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            tsum[v] += __shfl_xor(tsum[v], off);
-            Lsum[v] += __shfl_xor(Lsum[v], off);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) Gs[k][v] += __shfl_xor(Gs[k][v], off);
-        }
-}
-
 // Main pass without a gate (full CWENOZ everywhere), or with a gate (a mask,
 // or the troubled-cell network run inside this kernel).
 //
 // GATE: right after the central coefficients (which it needs anyway) each
 // cell forms its features and the wave evaluates the network for its 64
 // cells on the matrix cores (or reads the mask).  Cells taken as smooth keep
-// the linear central polynomial.  The cells left for full CWENOZ are listed
-// and reconstructed by reconstruct_wave_kernel, one wave per cell, so their
-// cost does not depend on how they cluster (a wave holding a few of them
-// would otherwise run a whole directional stream for them).
+// the linear central polynomial; the others run the directional stencils,
+// indicators and weights in their own lanes.  (Moving the troubled cells to
+// a separate pass, a wave or a quad of lanes per cell, was measured slower:
+// an isolated troubled cell then reads a cache line per operator value,
+// while here its central and face data stream with its neighbours'.)  The
+// FP32 P2 variant is held to 3 waves per SIMD, which its LDS already imposes.
 //
 // A cell whose point states violate positivity is marked with bit 7 of its
 // flag for the fallback pass.
 template <class T, int K, bool LABEL, bool GATE>
-__global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GATE && sizeof(T) == 4 && K == 9 ? 3 : 1)))
+void reconstruct_kernel(ReconArgs<T> A) {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     const bool valid = c < A.nc;
     double ui[5];
@@ -565,23 +492,16 @@ __global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
             central_coeffs<T, K>(A, c, ui, a);
             mode = A.gate[c] ? 0 : 1;
         }
-        // troubled cells go to the work list (one atomic per wave) for
-        // reconstruct_wave_kernel; the others take the linear polynomial here
-        const bool listed = valid && mode == 1;
-        const uint64_t bal = __ballot(listed);
-        if (bal) {
-            const int lane = int(threadIdx.x & 63);
-            const int leader = __ffsll(static_cast<unsigned long long>(bal)) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(A.work, int(__popcll(bal)));
-            base = __shfl(base, leader);
-            if (listed) A.work[kListOff + base + int(__popcll(bal & ((uint64_t(1) << lane) - 1)))] = int32_t(c);
-        }
+        // troubled cells run their directional streams in place
         if (!valid) return;
         if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
-        if (listed) return;
+        if (mode == 1) {
+            const int nd = A.ndir[c];
+            float lab = 0.f;
+            if (nd > 0) dir_blend_lane<T, K, false>(A, c, ui, nd, lab, a);
+        }
         const bool ok = face_values<T, K>(A, c, ui, 0, a);
-        A.flags[c] = uint8_t(1 | (ok ? 0 : 0x80));
+        A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
     } else {
         if (!valid) return;
 #pragma unroll
@@ -591,150 +511,6 @@ __global__ __launch_bounds__(kBlock) void reconstruct_kernel(ReconArgs<T> A) {
         const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
         A.flags[c] = uint8_t(ok ? 0 : 0x80);
         if constexpr (LABEL) A.label[c] = lab;
-    }
-}
-
-// Full CWENOZ for the listed cells, one wave per cell (a grid-stride loop
-// over the list):
-//  - central coefficients: lane m takes stencil member m, then a butterfly
-//    over the wave sums B_c b into every lane;
-//  - SI_1 = a^T O a: lane e takes upper-triangle entry e of O;
-//  - directional stencils, indicators and weights: dir_sums_wave;
-//  - point values: lane p takes face point p = lf Q + q (basis recomputed
-//    from the point's offset).
-template <class T, int K>
-__global__ __launch_bounds__(kBlock) void reconstruct_wave_kernel(ReconArgs<T> A) {
-    const int lane = int(threadIdx.x & 63);
-    const int64_t nc = A.nc;
-    const int count = A.work[0];
-    const int Q = A.Q, NP = A.NF * A.Q;
-    constexpr int NT = K * (K + 1) / 2;
-    const int64_t stride = int64_t(gridDim.x) * (blockDim.x >> 6);
-    for (int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); idx < count; idx += stride) {
-        const int64_t c = A.work[kListOff + idx];
-        // every load that needs only c, issued together: the cell state, this
-        // lane's central member and its operator column, its entry of O, its
-        // face point's offset and face
-        double ui[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) ui[v] = A.U[v * nc + c];
-        const bool cm = lane < A.MC;
-        const int32_t jc = cm ? A.sten_c[int64_t(lane) * nc + c] : int32_t(c);
-        T bc[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) bc[k] = cm ? A.Bc[(int64_t(lane) * K + k) * nc + c] : T(0);
-        const T o_lane = lane < NT ? A.O[int64_t(lane) * nc + c] : T(0);
-        const bool pt = lane < NP;
-        const int32_t f2 = pt ? A.c2f[int64_t(lane / Q) * nc + c] : -1;
-        T xp[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xp[d] = pt ? A.xi[(int64_t(lane) * 3 + d) * nc + c] : T(0);
-        T pm[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) pm[k] = A.pmean[int64_t(k) * nc + c];
-        const int nd = A.ndir[c];
-        // central coefficients: this lane's member, then a butterfly over the wave
-        T a[K][5];
-        {
-            T bv[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) bv[v] = cm ? T(A.U[v * nc + jc] - ui[v]) : T(0);
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) a[k][v] = bc[k] * bv[v];
-        }
-        const int nq = f2 >= 0 ? int(A.fnq[f2 >> 1]) : 0;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1)
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) a[k][v] += __shfl_xor(a[k][v], off);
-        // SI_1 over the upper triangle of O (off-diagonal entries twice)
-        T SI1[5] = {T(0), T(0), T(0), T(0), T(0)};
-        for (int e0 = 0; e0 < NT; e0 += 64) {
-            const int e = e0 + lane;
-            if (e < NT) {
-                int k = 0, rem = e;
-                while (rem >= K - k) {
-                    rem -= K - k;
-                    ++k;
-                }
-                const int l = k + rem;
-                const T o = (e0 == 0 ? o_lane : A.O[int64_t(e) * nc + c]) * (l == k ? T(1) : T(2));
-                T ak[5], al[5];
-#pragma unroll
-                for (int kk = 0; kk < K; ++kk)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) {
-                        if (kk == k) ak[v] = a[kk][v];
-                        if (kk == l) al[v] = a[kk][v];
-                    }
-#pragma unroll
-                for (int v = 0; v < 5; ++v) SI1[v] += o * ak[v] * al[v];
-            }
-        }
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) SI1[v] += __shfl_xor(SI1[v], off);
-        if (nd > 0) {
-            const T lam_s = T(1) / (A.lam_c + T(nd));
-            const T lam_1 = A.lam_c * lam_s;
-            T inv1[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                SI1[v] = fmax(SI1[v], T(0));
-                inv1[v] = T(1) / (A.eps + SI1[v]);
-            }
-            T tsum[5], Lsum[5], Gs[3][5];
-            dir_sums_wave<T, K>(A, c, ui, SI1, inv1, nd, lam_s, tsum, Lsum, Gs);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const T tau = tsum[v] / T(nd);
-                const T W = T(1) + tau * (lam_1 * inv1[v] + Lsum[v]);
-                const T s1 = (T(1) + tau * inv1[v]) / W;
-                const T tw = tau / W;
-#pragma unroll
-                for (int k = 0; k < K; ++k) a[k][v] = s1 * a[k][v] + (k < 3 ? tw * Gs[k < 3 ? k : 0][v] : T(0));
-            }
-        }
-        // point values, one lane per face point (points past the first 64 in a loop)
-        bool ok = true;
-        for (int p0 = 0; p0 < NP; p0 += 64) {
-            const int p = p0 + lane;
-            int nqp = nq;
-            int32_t f2p = f2;
-            if (p0 > 0) {
-                f2p = p < NP ? A.c2f[int64_t(p / Q) * nc + c] : -1;
-                nqp = f2p >= 0 ? int(A.fnq[f2p >> 1]) : 0;
-            }
-            if (f2p >= 0 && p - (p / Q) * Q < nqp) {
-                T d[5] = {T(0), T(0), T(0), T(0), T(0)};
-                if (p0 > 0) {
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) xp[e] = A.xi[(int64_t(p) * 3 + e) * nc + c];
-                }
-                T ph[K];
-                basis_at<T, K>(xp[0], xp[1], xp[2], pm, ph);
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) d[v] += ph[k] * a[k][v];
-                T val[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
-                const T pr =
-                    A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-                ok = ok && (val[0] > T(1e-10)) && (pr > T(1e-10));
-                T* out = A.fs + int64_t(p) * 5 * nc + c;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) out[int64_t(v) * nc] = val[v];
-            }
-        }
-        const bool all_ok = __ballot(!ok) == 0;
-        if (lane == 0) A.flags[c] = uint8_t(all_ok ? 0 : 0x80);
     }
 }
 

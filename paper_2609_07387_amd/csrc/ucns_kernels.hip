@@ -30,8 +30,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
-constexpr int kListOff = 64;      // gate work list: counter in [0], cell ids from [64]
-constexpr int kWaveBlocks = 2048; // grid of the one-wave-per-cell pass over the work list
 
 // The dispatcher hands workgroups to the eight XCDs round robin (block b runs
 // on XCD b mod 8).  Renumbered this way, each XCD takes one contiguous range
@@ -93,7 +91,7 @@ struct ReconArgs {
     const int32_t* sten_d;
     const T* Bd;
     int ND;       // directional stencil slots per cell (cells with fewer pad with zero operators)
-    int MD, MDG;  // padded directional stencil size, and rounded up to a power of two
+    int MD;       // padded directional stencil size
     const T* O;
     const T* xi;     // face points in each cell's scaled frame [lf][q][3][nc]
     const T* pmean;  // cell means of the scaled monomials [K][nc]
@@ -108,7 +106,6 @@ struct ReconArgs {
     // troubled-cell gate (network inside the kernel) and its features
     const float* mlp;
     uint8_t* mask_out;
-    int32_t* work;  // counter + list of the cells the gate leaves for full CWENOZ
     const int32_t* nbr;
     const T* ndc;
     const T* hb;
@@ -574,8 +571,6 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.Bd = arena_ptr<T>(ar, ar.Bd);
     A.ND = std::max(1, m.nd_max);
     A.MD = std::max(1, m.md_pad);
-    A.MDG = 1;
-    while (A.MDG < A.MD) A.MDG <<= 1;
     A.O = arena_ptr<T>(ar, ar.O);
     A.xi = arena_ptr<T>(ar, ar.xi);
     A.pmean = arena_ptr<T>(ar, ar.pmean);
@@ -586,7 +581,6 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.gate = gate ? gate->mask : nullptr;
     A.mlp = gate ? gate->mlp : nullptr;
     A.mask_out = gate ? gate->mask_out : nullptr;
-    A.work = gate ? gate->work : nullptr;
     A.nbr = arena_ptr<int32_t>(ar, ar.nbr);
     A.ndc = arena_ptr<T>(ar, ar.ndc);
     A.hb = arena_ptr<T>(ar, ar.hb);
@@ -600,16 +594,11 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     return A;
 }
 
-__global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
-
 template <class T, int K>
 int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
     const dim3 grid(grid_for(A.nc)), block(kBlock);
     if (A.mlp || A.gate) {
-        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, st, A.work);
         hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
-        const unsigned wb = std::min<unsigned>(kWaveBlocks, unsigned((A.nc + kBlock / 64 - 1) / (kBlock / 64)));
-        hipLaunchKernelGGL((reconstruct_wave_kernel<T, K>), dim3(wb), block, 0, st, A);
     } else {
         if (A.label)
             hipLaunchKernelGGL((reconstruct_kernel<T, K, true, false>), grid, block, 0, st, A);
@@ -796,8 +785,7 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     UCNS_REQUIRE(!(gate && gate->mask && gate->mlp), UCNS_EINVAL, "gate: give a mask or a network, not both");
     UCNS_REQUIRE(!(gate && (gate->mask || gate->mlp) && label), UCNS_EINVAL,
                  "labels are produced by the ungated reconstruction only");
-    UCNS_REQUIRE(!(gate && (gate->mask || gate->mlp)) || (gate->work && aligned(gate->work)), UCNS_EINVAL,
-                 "gate: a 256-byte aligned work buffer of n_cell + 64 int32 is required");
+
     const double gm1 = phys->gamma - 1.0;
     const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
                                          : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);

@@ -53,7 +53,7 @@ class BC(C.Structure):
 
 
 class Gate(C.Structure):
-    _fields_ = [("mask", C.c_void_p), ("mlp", C.c_void_p), ("mask_out", C.c_void_p), ("work", C.c_void_p)]
+    _fields_ = [("mask", C.c_void_p), ("mlp", C.c_void_p), ("mask_out", C.c_void_p)]
 
 
 # gate network parameter block (float32) offsets, as in include/ucns.h
@@ -254,25 +254,14 @@ def dt(mesh, ph, U, cfl, scratch, dt_dev, stream=None):
     check(lib().ucns_dt(mesh.h, C.byref(ph), _dp(U), float(cfl), _dp(scratch), _dp(dt_dev), _stream(stream)))
 
 
-def gate_work(mesh, device="cuda"):
-    """Work-list buffer for a gated reconstruction (int32 [n_cell + 64])."""
-    import torch
-
-    return torch.zeros(mesh.n_cell + 64, dtype=torch.int32, device=device)
-
-
 def reconstruct(mesh, ph, U, precision, face_state, gate_mask=None, flags=None, label=None, stream=None, mlp=None,
-                mask_out=None, work=None):
-    """gate_mask (uint8, 1 = smooth) or mlp (float32 parameter block) selects
-    the gate; a gate needs work (see gate_work)."""
+                mask_out=None):
+    """gate_mask (uint8, 1 = smooth) or mlp (float32 parameter block) selects the gate."""
     g = None
     if gate_mask is not None or mlp is not None:
-        if work is None:
-            raise ValueError("a gated reconstruction needs a work buffer (ucns.gate_work)")
         g = Gate(None if gate_mask is None else C.c_void_p(gate_mask.data_ptr()),
                  None if mlp is None else C.c_void_p(mlp.data_ptr()),
-                 None if mask_out is None else C.c_void_p(mask_out.data_ptr()),
-                 C.c_void_p(work.data_ptr()))
+                 None if mask_out is None else C.c_void_p(mask_out.data_ptr()))
     check(lib().ucns_reconstruct(mesh.h, C.byref(ph), _dp(U), precision, None if g is None else C.byref(g),
                                  _dp(face_state), _dp(flags), _dp(label), _stream(stream)))
 
@@ -338,8 +327,6 @@ class Solver:
         self.ws = Workspace(mesh, precision, bool(ph.viscous), device)
         self.ws.label = torch.zeros(mesh.n_cell, dtype=torch.float32, device=device) if label else None
         self.ws.mask_out = torch.zeros(mesh.n_cell, dtype=torch.uint8, device=device) if mlp is not None else None
-        gated = mlp is not None or gate_mask is not None
-        self.ws.work = gate_work(mesh, device) if gated else None
         self.U0 = torch.empty((5, mesh.n_cell), dtype=torch.float64, device=device)
         self.gate_mask = gate_mask
         self.mlp = mlp
@@ -347,7 +334,7 @@ class Solver:
     def rhs_stage(self, U):
         ws = self.ws
         reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags, ws.label,
-                    mlp=self.mlp, mask_out=ws.mask_out, work=ws.work)
+                    mlp=self.mlp, mask_out=ws.mask_out)
         if self.ph.viscous:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
         face_flux(self.mesh, self.ph, self.bcs, U, ws.face_state, ws.gradW, self.precision, ws.face_flux)

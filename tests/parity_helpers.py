@@ -64,8 +64,7 @@ def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
     fs, ff, gw, R = lib_arrays(lm, precision, device)
     flags = torch.zeros(lm.n_cell, dtype=torch.uint8, device=device)
     gm = None if gate_mask is None else torch.tensor(gate_mask, dtype=torch.uint8, device=device)
-    work = None if gate_mask is None else ucns.gate_work(lm, device)
-    ucns.reconstruct(lm, ph, U, precision, fs, gm, flags, work=work)
+    ucns.reconstruct(lm, ph, U, precision, fs, gm, flags)
     if ph.viscous:
         ucns.gradients(lm, ph, bcs, U, precision, gw)
     ucns.face_flux(lm, ph, bcs, U, fs, gw if ph.viscous else None, precision, ff)
