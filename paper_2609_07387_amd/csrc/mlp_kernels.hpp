@@ -43,19 +43,20 @@ __device__ __forceinline__ ucns_bf16x8 zero8() {
 
 // Block-shared copy of the network (bf16 matrices, fp32 vectors).
 struct MlpWeights {
-    uint16_t W1t[64 * mlp::kXS];  // [n][k], k < 16
-    uint16_t W2t[64 * mlp::kHS];  // [n_out][k_in]
+    alignas(16) uint16_t W1t[64 * mlp::kXS];  // [n][k], k < 16
+    alignas(16) uint16_t W2t[64 * mlp::kHS];  // [n_out][k_in]
     float b1[64], b2[64], w3[64], mu[16], isig[16];
     float b3, theta;
 };
 
 __device__ void mlp_stage(const float* __restrict__ P, MlpWeights& S, int tid, int nthr) {
+    // consecutive threads read consecutive n (coalesced), write transposed to LDS
     for (int i = tid; i < 64 * 16; i += nthr) {
-        const int n = i >> 4, k = i & 15;
+        const int k = i >> 6, n = i & 63;
         S.W1t[n * mlp::kXS + k] = f2bf(P[mlp::kOffW1 + k * 64 + n]);
     }
     for (int i = tid; i < 64 * 64; i += nthr) {
-        const int n = i >> 6, k = i & 63;
+        const int k = i >> 6, n = i & 63;
         S.W2t[n * mlp::kHS + k] = f2bf(P[mlp::kOffW2 + k * 64 + n]);
     }
     for (int i = tid; i < 64; i += nthr) {
@@ -75,77 +76,91 @@ __device__ void mlp_stage(const float* __restrict__ P, MlpWeights& S, int tid, i
 
 // Per-wave scratch: rows of 64 cells (the X rows share the H buffer's start).
 struct MlpWaveLds {
-    uint16_t H[64 * mlp::kHS];
-    float z[64];
+    alignas(16) uint16_t H[64 * mlp::kHS];
 };
 
 // Standardised inputs x[16] of this lane's cell -> logit z.  All 64 lanes of
 // the wave must call it together (lanes without a cell pass zeros).
+//
+// Both layers are computed transposed (weights as the A operand, the cells'
+// rows as B), so that a lane's output fragment holds four consecutive hidden
+// units of one cell: the hidden layer is stored with one 8-byte LDS write per
+// tile, and the output row sum needs only the four lane groups (two
+// shuffles), after which lane l holds cell l's sum.
 __device__ float mlp_wave_forward(const MlpWeights& S, MlpWaveLds& W, const float* f12) {
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     uint16_t* X = W.H;  // 64 rows x kXS, overwritten by the first hidden layer below
+    {
+        uint32_t w[8];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) X[lane * mlp::kXS + k] = f2bf(k < 12 ? (f12[k] - S.mu[k]) * S.isig[k] : 0.f);
+        for (int k = 0; k < 8; ++k) {
+            const float x0 = 2 * k < 12 ? (f12[2 * k] - S.mu[2 * k]) * S.isig[2 * k] : 0.f;
+            const float x1 = 2 * k + 1 < 12 ? (f12[2 * k + 1] - S.mu[2 * k + 1]) * S.isig[2 * k + 1] : 0.f;
+            w[k] = uint32_t(f2bf(x0)) | (uint32_t(f2bf(x1)) << 16);
+        }
+        uint4* xr = reinterpret_cast<uint4*>(&X[lane * mlp::kXS]);
+        xr[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        xr[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    }
     __builtin_amdgcn_wave_barrier();
-    ucns_bf16x8 ax[4];
+    ucns_bf16x8 bx[4];  // B fragments: cells 16 mt + r, inputs 8 g .. 8 g + 7
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) ax[mt] = g < 2 ? lds8(&X[(16 * mt + r) * mlp::kXS + 8 * g]) : zero8();
-    // The X rows now sit in registers (ax); the wave's LDS operations run in
+    for (int mt = 0; mt < 4; ++mt) bx[mt] = g < 2 ? lds8(&X[(16 * mt + r) * mlp::kXS + 8 * g]) : zero8();
+    // The X rows now sit in registers (bx); the wave's LDS operations run in
     // issue order, so the hidden layer may overwrite them tile by tile.
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const ucns_bf16x8 bw = g < 2 ? lds8(&S.W1t[(16 * nt + r) * mlp::kXS + 8 * g]) : zero8();
-        const int n = 16 * nt + r;
-        const float bias = S.b1[n];
+        const ucns_bf16x8 aw = g < 2 ? lds8(&S.W1t[(16 * nt + r) * mlp::kXS + 8 * g]) : zero8();
+        const int n0 = 16 * nt + 4 * g;  // this lane's hidden units n0 .. n0 + 3
+        float bias[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bias[j] = S.b1[n0 + j];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            const ucns_f32x4 h1 = mfma16(ax[mt], bw, ucns_f32x4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int j = 0; j < 4; ++j) W.H[(16 * mt + 4 * g + j) * mlp::kHS + n] = f2bf(fmaxf(h1[j] + bias, 0.f));
+            const ucns_f32x4 h = mfma16(aw, bx[mt], ucns_f32x4{0.f, 0.f, 0.f, 0.f});
+            const uint32_t lo = uint32_t(f2bf(fmaxf(h[0] + bias[0], 0.f))) |
+                                (uint32_t(f2bf(fmaxf(h[1] + bias[1], 0.f))) << 16);
+            const uint32_t hi = uint32_t(f2bf(fmaxf(h[2] + bias[2], 0.f))) |
+                                (uint32_t(f2bf(fmaxf(h[3] + bias[3], 0.f))) << 16);
+            *reinterpret_cast<uint2*>(&W.H[(16 * mt + r) * mlp::kHS + n0]) = make_uint2(lo, hi);
         }
     }
     __builtin_amdgcn_wave_barrier();
-    float part[4][4];
+    ucns_bf16x8 bh0[4], bh1[4];  // B fragments: cells 16 mt + r, hidden 8 g .. and 32 + 8 g ..
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) part[mt][j] = 0.f;
+    for (int mt = 0; mt < 4; ++mt) {
+        bh0[mt] = lds8(&W.H[(16 * mt + r) * mlp::kHS + 8 * g]);
+        bh1[mt] = lds8(&W.H[(16 * mt + r) * mlp::kHS + 32 + 8 * g]);
+    }
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const ucns_bf16x8 b0 = lds8(&S.W2t[(16 * nt + r) * mlp::kHS + 8 * g]);
-        const ucns_bf16x8 b1 = lds8(&S.W2t[(16 * nt + r) * mlp::kHS + 32 + 8 * g]);
-        const int n = 16 * nt + r;
-        const float bias = S.b2[n], w = S.w3[n];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const ucns_bf16x8 a0 = lds8(&W.H[(16 * mt + r) * mlp::kHS + 8 * g]);
-            const ucns_bf16x8 a1 = lds8(&W.H[(16 * mt + r) * mlp::kHS + 32 + 8 * g]);
-            ucns_f32x4 acc = mfma16(a0, b0, ucns_f32x4{0.f, 0.f, 0.f, 0.f});
-            acc = mfma16(a1, b1, acc);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) part[mt][j] += fmaxf(acc[j] + bias, 0.f) * w;
-        }
-    }
-    // sum over the 16 columns held by the 16 lanes of each group
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+        const ucns_bf16x8 a0 = lds8(&S.W2t[(16 * nt + r) * mlp::kHS + 8 * g]);
+        const ucns_bf16x8 a1 = lds8(&S.W2t[(16 * nt + r) * mlp::kHS + 32 + 8 * g]);
+        const int n0 = 16 * nt + 4 * g;
+        float bias[4], w[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            float v = part[mt][j];
-            v += __shfl_xor(v, 1, 16);
-            v += __shfl_xor(v, 2, 16);
-            v += __shfl_xor(v, 4, 16);
-            v += __shfl_xor(v, 8, 16);
-            part[mt][j] = v;
+            bias[j] = S.b2[n0 + j];
+            w[j] = S.w3[n0 + j];
         }
-    if (r == 0) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < 4; ++mt) {
+            ucns_f32x4 acc = mfma16(a0, bh0[mt], ucns_f32x4{0.f, 0.f, 0.f, 0.f});
+            acc = mfma16(a1, bh1[mt], acc);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) W.z[16 * mt + 4 * g + j] = part[mt][j] + S.b3;
+            for (int j = 0; j < 4; ++j) part[mt] += fmaxf(acc[j] + bias[j], 0.f) * w[j];
+        }
     }
-    __builtin_amdgcn_wave_barrier();
-    return W.z[lane];
+    // sum over the four lane groups (output units 4 g .. 4 g + 3 of each tile)
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        part[mt] += __shfl_xor(part[mt], 16);
+        part[mt] += __shfl_xor(part[mt], 32);
+    }
+    // lane l = 16 g + r holds cell 16 mt + r in part[mt]; its own cell is mt = g
+    const float z = g == 0 ? part[0] : g == 1 ? part[1] : g == 2 ? part[2] : part[3];
+    return z + S.b3;
 }
 
 // prob[i] = sigmoid(z) (mode 0) or mask[i] = sigmoid(z) < theta (mode 1)

@@ -117,39 +117,60 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
 //      centroid is a_lin / h),
 //  (4-6) max, mean and min over the face neighbours j of
 //      |v_j - v_i - grad p_opt . (c_j - c_i)| / (|v_j - v_i| + h |grad p_opt| + 1e-12 |v_i|).
+template <class T>
+__device__ __forceinline__ T feat_log(T x) {
+    // the features feed a BF16 network: FP32 takes the hardware logarithm
+    if constexpr (sizeof(T) == 4)
+        return __logf(x);
+    else
+        return log(x);
+}
+
 template <class T, int K>
 __device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, const double* ui, const T a[K][5],
                                               const T* js, float* f) {
     const int64_t nc = A.nc;
     const T h = A.hb[c], ninv = T(1) / T(A.ncen[c]);
+    T au[2], g[2][3], gn[2], dmax[2], dsum[2], dmin[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int v = t ? 4 : 0;
-        const T au = fabs(T(ui[v]));
-        const T gx = a[0][v], gy = a[1][v], gz = a[2][v];
-        const T gn = sqrt(gx * gx + gy * gy + gz * gz);
-        T dmax = T(0), dsum = T(0), dmin = T(INFINITY);
-        int cnt = 0;
-        for (int lf = 0; lf < A.NF; ++lf) {
-            const int32_t j = A.nbr[int64_t(lf) * nc + c];
-            if (j < 0) continue;
-            const T dx = A.ndc[(int64_t(lf) * 3 + 0) * nc + c];
-            const T dy = A.ndc[(int64_t(lf) * 3 + 1) * nc + c];
-            const T dz = A.ndc[(int64_t(lf) * 3 + 2) * nc + c];
+        au[t] = fabs(T(ui[v]));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[t][d] = a[d][v];
+        gn[t] = sqrt(g[t][0] * g[t][0] + g[t][1] * g[t][1] + g[t][2] * g[t][2]);
+        dmax[t] = dsum[t] = T(0);
+        dmin[t] = T(INFINITY);
+    }
+    // one pass over the face neighbours for both variables
+    int cnt = 0;
+    for (int lf = 0; lf < A.NF; ++lf) {
+        const int32_t j = A.nbr[int64_t(lf) * nc + c];
+        if (j < 0) continue;
+        const T dx = A.ndc[(int64_t(lf) * 3 + 0) * nc + c];
+        const T dy = A.ndc[(int64_t(lf) * 3 + 1) * nc + c];
+        const T dz = A.ndc[(int64_t(lf) * 3 + 2) * nc + c];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int v = t ? 4 : 0;
             const T du = T(A.U[v * nc + j] - ui[v]);
-            const T rr = fabs(du - (gx * dx + gy * dy + gz * dz) / h) / (fabs(du) + gn + T(1e-12) * au);
-            dmax = fmax(dmax, rr);
-            dmin = fmin(dmin, rr);
-            dsum += rr;
-            ++cnt;
+            const T rr = fabs(du - (g[t][0] * dx + g[t][1] * dy + g[t][2] * dz) / h) /
+                         (fabs(du) + gn[t] + T(1e-12) * au[t]);
+            dmax[t] = fmax(dmax[t], rr);
+            dmin[t] = fmin(dmin[t], rr);
+            dsum[t] += rr;
         }
+        ++cnt;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
         float* o = f + 6 * t;
-        o[0] = float(log(T(1e-12) + js[2 * t] / au));
-        o[1] = float(log(T(1e-12) + js[2 * t + 1] * ninv / au));
-        o[2] = float(log(T(1e-12) + gn / au));
-        o[3] = float(log(T(1e-12) + dmax));
-        o[4] = float(log(T(1e-12) + dsum / T(cnt > 0 ? cnt : 1)));
-        o[5] = float(log(T(1e-12) + (cnt > 0 ? dmin : T(0))));
+        o[0] = float(feat_log(T(1e-12) + js[2 * t] / au[t]));
+        o[1] = float(feat_log(T(1e-12) + js[2 * t + 1] * ninv / au[t]));
+        o[2] = float(feat_log(T(1e-12) + gn[t] / au[t]));
+        o[3] = float(feat_log(T(1e-12) + dmax[t]));
+        o[4] = float(feat_log(T(1e-12) + dsum[t] / T(cnt > 0 ? cnt : 1)));
+        o[5] = float(feat_log(T(1e-12) + (cnt > 0 ? dmin[t] : T(0))));
     }
 }
 
