@@ -79,17 +79,17 @@ def time_steps(solver, U, steps, warmup, torch):
     return e0.elapsed_time(e1), wall
 
 
-def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns, mlp=None, mask_out=None):
+def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns, mlp_image=None, mask_out=None):
     """Mean duration of one reconstruction call (all the kernels it
     launches), HIP events recorded on the stream the kernels are launched on."""
     s = torch.cuda.current_stream()
     for _ in range(3):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp_image=mlp_image, mask_out=mask_out)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp=mlp, mask_out=mask_out)
+        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp_image=mlp_image, mask_out=mask_out)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -169,7 +169,7 @@ def main():
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
         rate = nc * 3 * args.steps / (ms / 1e3)
-        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns, net,
+        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns, solver.mlp_image,
                          solver.ws.mask_out)
         frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
         gate = net is not None

@@ -117,9 +117,9 @@ typedef struct {
  * network's decisions.  A NULL gate = full CWENOZ everywhere.  Labels are
  * not produced with a gate. */
 typedef struct {
-    const uint8_t* mask;  /* device [n_cell] or NULL */
-    const float* mlp;     /* device parameter block (UCNS_MLP_NPARAM floats) or NULL */
-    uint8_t* mask_out;    /* device [n_cell] or NULL */
+    const uint8_t* mask;    /* device [n_cell] or NULL */
+    const void* mlp_image;  /* device image written by ucns_mlp_pack, or NULL */
+    uint8_t* mask_out;      /* device [n_cell] or NULL */
 } ucns_gate;
 
 /* Gate network parameter block (float32) offsets: mu[16] isig[16]
@@ -128,7 +128,8 @@ typedef struct {
  * unit n, W2[i][n] hidden i to hidden n. */
 enum {
     UCNS_MLP_MU = 0, UCNS_MLP_ISIG = 16, UCNS_MLP_W1 = 32, UCNS_MLP_B1 = 1056, UCNS_MLP_W2 = 1120,
-    UCNS_MLP_B2 = 5216, UCNS_MLP_W3 = 5280, UCNS_MLP_B3 = 5344, UCNS_MLP_THETA = 5345, UCNS_MLP_NPARAM = 5348
+    UCNS_MLP_B2 = 5216, UCNS_MLP_W3 = 5280, UCNS_MLP_B3 = 5344, UCNS_MLP_THETA = 5345, UCNS_MLP_NPARAM = 5348,
+    UCNS_MLP_IMAGE_BYTES = 13312
 };
 
 const char* ucns_last_error(void);
@@ -255,6 +256,13 @@ int ucns_gate_features(const ucns_mesh* mesh, const double* U, int precision, fl
  * with FP32 accumulation, on n feature rows: prob = sigmoid(z); ucns_gate_mask
  * writes mask = (prob < theta), 1 = smooth. */
 int ucns_mlp_forward(const float* params, const float* features, int64_t n, float* prob, ucns_stream stream);
+
+/* Packs a parameter block into the image the fused gate of ucns_reconstruct
+ * reads (UCNS_MLP_IMAGE_BYTES bytes of device memory, 256-byte aligned, owned
+ * by the caller): the BF16 weights already in the matrix-core operand layout
+ * (so each wave loads its fragments directly, with no per-block conversion)
+ * and the FP32 vectors.  Call again whenever the parameters change. */
+int ucns_mlp_pack(const float* params, void* image, ucns_stream stream);
 int ucns_gate_mask(const float* params, const float* features, int64_t n, uint8_t* mask, ucns_stream stream);
 
 /* One training step on a batch of n rows (labels 0/1 as float): forward,

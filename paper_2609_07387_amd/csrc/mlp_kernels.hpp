@@ -163,6 +163,137 @@ __device__ float mlp_wave_forward(const MlpWeights& S, MlpWaveLds& W, const floa
     return z + S.b3;
 }
 
+// ------------------------------------------------------------ packed image
+//
+// Bytes [0, 4096): layer-1 A fragments, (nt, lane) at 16 (64 nt + lane):
+// W1t[16 nt + r][8 g .. 8 g + 7] (zero for g >= 2); [4096, 12288): layer-2
+// A fragments, (nt, half, lane) at 4096 + 16 (64 (2 nt + half) + lane):
+// W2t[16 nt + r][32 half + 8 g .. + 7]; then float32 mu[16] isig[16] b1[64]
+// b2[64] w3[64] b3 theta.
+namespace mlpimg {
+constexpr int kW1 = 0, kW2 = 4096, kF = 12288;
+constexpr int kMu = 0, kIsig = 16, kB1 = 32, kB2 = 96, kW3 = 160, kB3 = 224, kTheta = 225, kNF = 226;
+}  // namespace mlpimg
+
+__global__ __launch_bounds__(256) void mlp_pack_kernel(const float* __restrict__ P, unsigned char* img) {
+    for (int fr = threadIdx.x; fr < 4 * 64 + 8 * 64; fr += blockDim.x) {
+        const int lane = fr & 63, g = lane >> 4, r = lane & 15;
+        uint32_t w[4];
+        if (fr < 256) {  // layer 1
+            const int nt = fr >> 6, n = 16 * nt + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k0 = 8 * g + 2 * i;
+                const uint32_t lo = g < 2 ? f2bf(P[mlp::kOffW1 + k0 * 64 + n]) : 0u;
+                const uint32_t hi = g < 2 ? f2bf(P[mlp::kOffW1 + (k0 + 1) * 64 + n]) : 0u;
+                w[i] = lo | (hi << 16);
+            }
+            *reinterpret_cast<uint4*>(img + mlpimg::kW1 + 16 * fr) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {  // layer 2
+            const int q = (fr - 256) >> 6, nt = q >> 1, half = q & 1, n = 16 * nt + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k0 = 32 * half + 8 * g + 2 * i;
+                const uint32_t lo = f2bf(P[mlp::kOffW2 + k0 * 64 + n]);
+                const uint32_t hi = f2bf(P[mlp::kOffW2 + (k0 + 1) * 64 + n]);
+                w[i] = lo | (hi << 16);
+            }
+            *reinterpret_cast<uint4*>(img + mlpimg::kW2 + 16 * (fr - 256)) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+    float* fv = reinterpret_cast<float*>(img + mlpimg::kF);
+    for (int i = threadIdx.x; i < mlpimg::kNF; i += blockDim.x) {
+        float x;
+        if (i < mlpimg::kIsig) x = P[mlp::kOffMu + i];
+        else if (i < mlpimg::kB1) x = P[mlp::kOffIsig + i - mlpimg::kIsig];
+        else if (i < mlpimg::kB2) x = P[mlp::kOffB1 + i - mlpimg::kB1];
+        else if (i < mlpimg::kW3) x = P[mlp::kOffB2 + i - mlpimg::kB2];
+        else if (i < mlpimg::kB3) x = P[mlp::kOffW3 + i - mlpimg::kW3];
+        else if (i == mlpimg::kB3) x = P[mlp::kOffB3];
+        else x = P[mlp::kOffTheta];
+        fv[i] = x;
+    }
+}
+
+__device__ __forceinline__ ucns_bf16x8 gld8(const unsigned char* p) {
+    return __builtin_bit_cast(ucns_bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+// As mlp_wave_forward, with the weights read from the packed image (each
+// lane loads its own 16-byte fragments; the vectors are small, cached reads).
+__device__ float mlp_wave_forward_packed(const unsigned char* __restrict__ img, MlpWaveLds& W, const float* f12) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const float* fv = reinterpret_cast<const float*>(img + mlpimg::kF);
+    uint16_t* X = W.H;
+    {
+        uint32_t w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int k0 = 2 * k, k1 = 2 * k + 1;
+            const float x0 = k0 < 12 ? (f12[k0] - fv[mlpimg::kMu + k0]) * fv[mlpimg::kIsig + k0] : 0.f;
+            const float x1 = k1 < 12 ? (f12[k1] - fv[mlpimg::kMu + k1]) * fv[mlpimg::kIsig + k1] : 0.f;
+            w[k] = uint32_t(f2bf(x0)) | (uint32_t(f2bf(x1)) << 16);
+        }
+        uint4* xr = reinterpret_cast<uint4*>(&X[lane * mlp::kXS]);
+        xr[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        xr[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    }
+    ucns_bf16x8 aw[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) aw[nt] = gld8(img + mlpimg::kW1 + 16 * (64 * nt + lane));
+    __builtin_amdgcn_wave_barrier();
+    ucns_bf16x8 bx[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) bx[mt] = g < 2 ? lds8(&X[(16 * mt + r) * mlp::kXS + 8 * g]) : zero8();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int n0 = 16 * nt + 4 * g;
+        const float4 bias = *reinterpret_cast<const float4*>(fv + mlpimg::kB1 + n0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const ucns_f32x4 h = mfma16(aw[nt], bx[mt], ucns_f32x4{0.f, 0.f, 0.f, 0.f});
+            const uint32_t lo = uint32_t(f2bf(fmaxf(h[0] + bias.x, 0.f))) |
+                                (uint32_t(f2bf(fmaxf(h[1] + bias.y, 0.f))) << 16);
+            const uint32_t hi = uint32_t(f2bf(fmaxf(h[2] + bias.z, 0.f))) |
+                                (uint32_t(f2bf(fmaxf(h[3] + bias.w, 0.f))) << 16);
+            *reinterpret_cast<uint2*>(&W.H[(16 * mt + r) * mlp::kHS + n0]) = make_uint2(lo, hi);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    ucns_bf16x8 bh0[4], bh1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        bh0[mt] = lds8(&W.H[(16 * mt + r) * mlp::kHS + 8 * g]);
+        bh1[mt] = lds8(&W.H[(16 * mt + r) * mlp::kHS + 32 + 8 * g]);
+    }
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const ucns_bf16x8 a0 = gld8(img + mlpimg::kW2 + 16 * (64 * (2 * nt) + lane));
+        const ucns_bf16x8 a1 = gld8(img + mlpimg::kW2 + 16 * (64 * (2 * nt + 1) + lane));
+        const int n0 = 16 * nt + 4 * g;
+        const float4 bias = *reinterpret_cast<const float4*>(fv + mlpimg::kB2 + n0);
+        const float4 w = *reinterpret_cast<const float4*>(fv + mlpimg::kW3 + n0);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            ucns_f32x4 acc = mfma16(a0, bh0[mt], ucns_f32x4{0.f, 0.f, 0.f, 0.f});
+            acc = mfma16(a1, bh1[mt], acc);
+            // same summation order as mlp_wave_forward (identical decisions)
+            part[mt] += fmaxf(acc[0] + bias.x, 0.f) * w.x;
+            part[mt] += fmaxf(acc[1] + bias.y, 0.f) * w.y;
+            part[mt] += fmaxf(acc[2] + bias.z, 0.f) * w.z;
+            part[mt] += fmaxf(acc[3] + bias.w, 0.f) * w.w;
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        part[mt] += __shfl_xor(part[mt], 16);
+        part[mt] += __shfl_xor(part[mt], 32);
+    }
+    const float z = g == 0 ? part[0] : g == 1 ? part[1] : g == 2 ? part[2] : part[3];
+    return z + fv[mlpimg::kB3];
+}
+
 // prob[i] = sigmoid(z) (mode 0) or mask[i] = sigmoid(z) < theta (mode 1)
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restrict__ P, const float* __restrict__ feat,
                                                           int64_t n, float* prob, uint8_t* mask) {

@@ -470,7 +470,8 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 //
 // GATE: right after the central coefficients (which it needs anyway) each
 // cell forms its features and the wave evaluates the network for its 64
-// cells on the matrix cores (or reads the mask).  Cells taken as smooth keep
+// cells on the matrix cores, its weights read from the packed image (or it
+// reads the mask).  Cells taken as smooth keep
 // the linear central polynomial; the others run the directional stencils,
 // indicators and weights in their own lanes.  (Moving the troubled cells to
 // a separate pass, a wave or a quad of lanes per cell, was measured slower:
@@ -490,10 +491,8 @@ void reconstruct_kernel(ReconArgs<T> A) {
     if constexpr (GATE) {
         int mode = 0;
         if (A.mlp) {
-            __shared__ MlpWeights S;
             __shared__ MlpWaveLds Wv[kBlock / 64];
-            mlp_stage(A.mlp, S, threadIdx.x, blockDim.x);
-            __syncthreads();
+            const float* fv = reinterpret_cast<const float*>(A.mlp + mlpimg::kF);
             float f[12];
             if (valid) {
 #pragma unroll
@@ -503,10 +502,10 @@ void reconstruct_kernel(ReconArgs<T> A) {
                 gate_features<T, K>(A, c, ui, a, js, f);
             } else {
 #pragma unroll
-                for (int k = 0; k < 12; ++k) f[k] = S.mu[k];
+                for (int k = 0; k < 12; ++k) f[k] = fv[mlpimg::kMu + k];
             }
-            const float z = mlp_wave_forward(S, Wv[threadIdx.x >> 6], f);  // all lanes of the wave
-            mode = 1.f / (1.f + __expf(-z)) < S.theta ? 0 : 1;
+            const float z = mlp_wave_forward_packed(A.mlp, Wv[threadIdx.x >> 6], f);  // all lanes of the wave
+            mode = 1.f / (1.f + __expf(-z)) < fv[mlpimg::kTheta] ? 0 : 1;
         } else if (valid) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];

@@ -104,7 +104,7 @@ struct ReconArgs {
     float* label;
     T lam_c, eps, gm1;
     // troubled-cell gate (network inside the kernel) and its features
-    const float* mlp;
+    const unsigned char* mlp;  // packed network image (ucns_mlp_pack)
     uint8_t* mask_out;
     const int32_t* nbr;
     const T* ndc;
@@ -579,7 +579,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.Q = m.qmax;
     A.NF = m.nfmax;
     A.gate = gate ? gate->mask : nullptr;
-    A.mlp = gate ? gate->mlp : nullptr;
+    A.mlp = gate ? static_cast<const unsigned char*>(gate->mlp_image) : nullptr;
     A.mask_out = gate ? gate->mask_out : nullptr;
     A.nbr = arena_ptr<int32_t>(ar, ar.nbr);
     A.ndc = arena_ptr<T>(ar, ar.ndc);
@@ -782,8 +782,10 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     const Arena& ar = m.arena[precision];
     UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    UCNS_REQUIRE(!(gate && gate->mask && gate->mlp), UCNS_EINVAL, "gate: give a mask or a network, not both");
-    UCNS_REQUIRE(!(gate && (gate->mask || gate->mlp) && label), UCNS_EINVAL,
+    UCNS_REQUIRE(!(gate && gate->mask && gate->mlp_image), UCNS_EINVAL, "gate: give a mask or a network, not both");
+    UCNS_REQUIRE(!(gate && gate->mlp_image) || aligned(gate->mlp_image), UCNS_EINVAL,
+                 "gate: the network image must be 256-byte aligned");
+    UCNS_REQUIRE(!(gate && (gate->mask || gate->mlp_image) && label), UCNS_EINVAL,
                  "labels are produced by the ungated reconstruction only");
 
     const double gm1 = phys->gamma - 1.0;
@@ -939,6 +941,14 @@ int ucns_mlp_forward(const float* params, const float* features, int64_t n, floa
     hipLaunchKernelGGL(mlp_forward_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), params, features, n, prob, nullptr);
     return hip_check("ucns_mlp_forward");
+}
+
+int ucns_mlp_pack(const float* params, void* image, ucns_stream stream) {
+    UCNS_REQUIRE(params && image, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(aligned(image), UCNS_EINVAL, "the image must be 256-byte aligned");
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), params,
+                       static_cast<unsigned char*>(image));
+    return hip_check("ucns_mlp_pack");
 }
 
 int ucns_gate_mask(const float* params, const float* features, int64_t n, uint8_t* mask, ucns_stream stream) {

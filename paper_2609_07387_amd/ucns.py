@@ -27,7 +27,7 @@ EXPORTS = [
     "ucns_mesh_upload", "ucns_mesh_faces", "ucns_mesh_cell_geometry", "ucns_mesh_stencil", "ucns_mesh_operators",
     "ucns_workspace_elems", "ucns_dt", "ucns_reconstruct", "ucns_gradients", "ucns_face_flux", "ucns_residual",
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
-    "ucns_gate_mask", "ucns_mlp_train_step",
+    "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack",
 ]
 
 
@@ -53,12 +53,13 @@ class BC(C.Structure):
 
 
 class Gate(C.Structure):
-    _fields_ = [("mask", C.c_void_p), ("mlp", C.c_void_p), ("mask_out", C.c_void_p)]
+    _fields_ = [("mask", C.c_void_p), ("mlp_image", C.c_void_p), ("mask_out", C.c_void_p)]
 
 
 # gate network parameter block (float32) offsets, as in include/ucns.h
 MLP_OFF = {"mu": 0, "isig": 16, "W1": 32, "b1": 1056, "W2": 1120, "b2": 5216, "w3": 5280, "b3": 5344, "theta": 5345}
 MLP_NPARAM = 5348
+MLP_IMAGE_BYTES = 13312
 
 
 _lib = None
@@ -95,6 +96,7 @@ def lib():
         L.ucns_gate_features.argtypes = [vp, vp, i32, vp, vp]
         L.ucns_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.ucns_gate_mask.argtypes = [vp, vp, i64, vp, vp]
+        L.ucns_mlp_pack.argtypes = [vp, vp, vp]
         L.ucns_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i64, flt, flt, i32, vp, vp]
         _lib = L
     return _lib
@@ -254,13 +256,23 @@ def dt(mesh, ph, U, cfl, scratch, dt_dev, stream=None):
     check(lib().ucns_dt(mesh.h, C.byref(ph), _dp(U), float(cfl), _dp(scratch), _dp(dt_dev), _stream(stream)))
 
 
-def reconstruct(mesh, ph, U, precision, face_state, gate_mask=None, flags=None, label=None, stream=None, mlp=None,
-                mask_out=None):
-    """gate_mask (uint8, 1 = smooth) or mlp (float32 parameter block) selects the gate."""
+def mlp_pack(params, image=None, stream=None):
+    """Packed network image (uint8 [MLP_IMAGE_BYTES]) of a parameter block."""
+    import torch
+
+    if image is None:
+        image = torch.empty(MLP_IMAGE_BYTES, dtype=torch.uint8, device=params.device)
+    check(lib().ucns_mlp_pack(_dp(params), _dp(image), _stream(stream)))
+    return image
+
+
+def reconstruct(mesh, ph, U, precision, face_state, gate_mask=None, flags=None, label=None, stream=None,
+                mlp_image=None, mask_out=None):
+    """gate_mask (uint8, 1 = smooth) or mlp_image (see mlp_pack) selects the gate."""
     g = None
-    if gate_mask is not None or mlp is not None:
+    if gate_mask is not None or mlp_image is not None:
         g = Gate(None if gate_mask is None else C.c_void_p(gate_mask.data_ptr()),
-                 None if mlp is None else C.c_void_p(mlp.data_ptr()),
+                 None if mlp_image is None else C.c_void_p(mlp_image.data_ptr()),
                  None if mask_out is None else C.c_void_p(mask_out.data_ptr()))
     check(lib().ucns_reconstruct(mesh.h, C.byref(ph), _dp(U), precision, None if g is None else C.byref(g),
                                  _dp(face_state), _dp(flags), _dp(label), _stream(stream)))
@@ -330,11 +342,12 @@ class Solver:
         self.U0 = torch.empty((5, mesh.n_cell), dtype=torch.float64, device=device)
         self.gate_mask = gate_mask
         self.mlp = mlp
+        self.mlp_image = mlp_pack(mlp) if mlp is not None else None
 
     def rhs_stage(self, U):
         ws = self.ws
         reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags, ws.label,
-                    mlp=self.mlp, mask_out=ws.mask_out)
+                    mlp_image=self.mlp_image, mask_out=ws.mask_out)
         if self.ph.viscous:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
         face_flux(self.mesh, self.ph, self.bcs, U, ws.face_state, ws.gradW, self.precision, ws.face_flux)

@@ -139,7 +139,7 @@ def test_fused_gate_matches_standalone(torch_cuda):
         flags = torch.zeros(lm.n_cell, dtype=torch.uint8, device="cuda")
         flagsB = torch.zeros_like(flags)
         mask_out = torch.zeros(lm.n_cell, dtype=torch.uint8, device="cuda")
-        ucns.reconstruct(lm, ph, U, prec, fsA, None, flags, mlp=P, mask_out=mask_out)
+        ucns.reconstruct(lm, ph, U, prec, fsA, None, flags, mlp_image=ucns.mlp_pack(P), mask_out=mask_out)
         feats = torch.empty((lm.n_cell, 12), dtype=torch.float32, device="cuda")
         ucns.gate_features(lm, U, prec, feats)
         mask = torch.empty(lm.n_cell, dtype=torch.uint8, device="cuda")
