@@ -171,3 +171,17 @@ def test_gate_end_to_end_small(torch_cuda):
           f"rel L1 {ev['rel_L1_gated_vs_full']:.2e}", flush=True)
     assert ev["gated"]["fraction_gated"] > 0.5
     assert ev["rel_L1_gated_vs_full"] < 1e-3
+
+
+def test_trained_gate_shock_box_500_steps(torch_cuda):
+    """The committed trained network on the full shocked box (seed 6, not
+    used in training): gated FP32 solver against full CWENOZ FP32 over 500
+    steps within 1e-3 relative L1, with most cells gated."""
+    if not __import__("os").path.exists(gate.WEIGHTS):
+        pytest.skip("no trained network")
+    P = np.load(gate.WEIGHTS).astype(np.float32)
+    ev = gate.evaluate(P, seed=6, steps=500, log=lambda *a: None)
+    print(f"[gpu] trained gate, shocked box 500 steps: rel L1 {ev['rel_L1_gated_vs_full']:.2e}, "
+          f"gated {ev['gated']['fraction_gated']:.3f}", flush=True)
+    assert ev["rel_L1_gated_vs_full"] < 1e-3
+    assert ev["gated"]["fraction_gated"] > 0.5
