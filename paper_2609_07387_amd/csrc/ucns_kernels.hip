@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         pen = T(4.0 / 3.0) / sqrt(dx * dx + dy * dy + dz * dz);
     }
     T F[5] = {T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll 2
+#pragma unroll 1  // unrolling doubles the live registers (FP64: 3 waves per SIMD instead of 2)
     for (int q = 0; q < nq; ++q) {
         T uL[5], uR[5], Fq[5];
 #pragma unroll
