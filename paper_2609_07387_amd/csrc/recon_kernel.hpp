@@ -245,6 +245,11 @@ __device__ __forceinline__ void basis_at(T x, T y, T z, const T* pm, T* ph) {
     }
 }
 
+// Most Gauss points on one face for a basis of K terms (order p: p*p on a
+// quadrilateral, 3 on a triangle); the launcher rejects meshes beyond it.
+template <int K>
+constexpr int face_qmax() { return K <= 9 ? 4 : 9; }
+
 // Point values at the cell's face quadrature points (step vii) from the
 // coefficients a (first order when mode == 2), stored in the cell-fastest
 // slots [lf][q][v][cell] so that a wave's stores are contiguous; returns
@@ -267,47 +272,41 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
     // the loops are wave-uniform (every lane walks all NF x Q slots); a lane
     // skips the slots its cell does not have.  The offset of point (lf, q) in
     // rows ((lf Q + q) 3 + d), the point's state in rows ((lf Q + q) 5 + v).
+    // all of a face's point offsets are loaded together (one latency per
+    // face, not per point)
+    constexpr int QM = face_qmax<K>();
 #pragma unroll 1
     for (int lf = 0; lf < NF; ++lf) {
         const int32_t f2 = bld<int32_t>(rC, c4, uint32_t(lf) * rowI);
+        T x[QM][3];
+        const auto rX = rsrc(A.xi + int64_t(lf) * Q * 3 * nc, uint64_t(Q) * 3 * rowT);
+#pragma unroll
+        for (int q = 0; q < QM; ++q)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) x[q][d] = q < Q ? bld<T>(rX, cT, uint32_t(q * 3 + d) * rowT) : T(0);
         const int nq = f2 < 0 ? 0 : int(A.fnq[f2 >> 1]);
-        T x0[3];
-        {
-            const auto rX = rsrc(A.xi + int64_t(lf) * Q * 3 * nc, uint64_t(3) * rowT);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) x0[d] = bld<T>(rX, cT, uint32_t(d) * rowT);
-        }
-#pragma unroll 1
-        for (int q = 0; q < Q; ++q) {
-            const int qn = q + 1 < Q ? q + 1 : q;
-            T x1[3];
-            const auto rX = rsrc(A.xi + (int64_t(lf) * Q + qn) * 3 * nc, uint64_t(3) * rowT);
+        for (int q = 0; q < QM; ++q) {
+            if (q >= nq) continue;
+            T d[5];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) x1[d] = bld<T>(rX, cT, uint32_t(d) * rowT);
-            if (q < nq) {
-                T d[5];
+            for (int v = 0; v < 5; ++v) d[v] = T(0);
+            if (mode != 2) {
+                T ph[K];
+                basis_at<T, K>(x[q][0], x[q][1], x[q][2], pm, ph);
 #pragma unroll
-                for (int v = 0; v < 5; ++v) d[v] = T(0);
-                if (mode != 2) {
-                    T ph[K];
-                    basis_at<T, K>(x0[0], x0[1], x0[2], pm, ph);
+                for (int k = 0; k < K; ++k)
 #pragma unroll
-                    for (int k = 0; k < K; ++k)
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) d[v] += ph[k] * a[k][v];
-                }
-                T val[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
-                const T p =
-                    A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-                ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
-                const auto rF = rsrc(A.fs + (int64_t(lf) * Q + q) * 5 * nc, uint64_t(5) * rowT);
-#pragma unroll
-                for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cT, uint32_t(v) * rowT);
+                    for (int v = 0; v < 5; ++v) d[v] += ph[k] * a[k][v];
             }
+            T val[5];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) x0[d] = x1[d];
+            for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
+            const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+            ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
+            const auto rF = rsrc(A.fs + (int64_t(lf) * Q + q) * 5 * nc, uint64_t(5) * rowT);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cT, uint32_t(v) * rowT);
         }
     }
     return ok;

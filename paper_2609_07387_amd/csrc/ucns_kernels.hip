@@ -596,6 +596,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
 
 template <class T, int K>
 int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
+    if (A.Q > face_qmax<K>()) return UCNS_EINVAL;
     const dim3 grid(grid_for(A.nc)), block(kBlock);
     if (A.mlp || A.gate) {
         hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
