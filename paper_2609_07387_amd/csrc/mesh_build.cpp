@@ -920,6 +920,7 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     auto* xi = reinterpret_cast<T*>(base + a.xi);
     auto* pmean = reinterpret_cast<T*>(base + a.pmean);
     auto* c2f = reinterpret_cast<int32_t*>(base + a.c2f);
+    auto* cnq = reinterpret_cast<uint8_t*>(base + a.cnq);
     auto* vol = reinterpret_cast<double*>(base + a.vol);
     auto* hdt = reinterpret_cast<double*>(base + a.hdt);
     auto* fcell = reinterpret_cast<int32_t*>(base + a.fcell);
@@ -981,7 +982,9 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
             for (int l = k; l < K; ++l) O[size_t(t++) * nc + c] = T(m.O[(size_t(c) * K + k) * K + l]);
         for (int k = 0; k < K; ++k) pmean[size_t(k) * nc + c] = T(m.mean[size_t(c) * K + k]);
         for (int lf = 0; lf < NF; ++lf) {
-            c2f[size_t(lf) * nc + c] = m.c2f[c * kMaxFaces + lf];
+            const int32_t fs = m.c2f[c * kMaxFaces + lf];
+            c2f[size_t(lf) * nc + c] = fs;
+            cnq[size_t(lf) * nc + c] = fs >= 0 ? uint8_t(m.fnq[fs >> 1]) : 0;
             for (int q = 0; q < Q; ++q)
                 for (int d = 0; d < 3; ++d)
                     xi[((size_t(lf) * Q + q) * 3 + d) * nc + c] = T(m.xi[((size_t(c) * NF + lf) * Q + q) * 3 + d]);
@@ -1024,6 +1027,7 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.xi = take(ts * NF * Q * 3 * nc);
     a.pmean = take(ts * K * nc);
     a.c2f = take(4 * NF * nc);
+    a.cnq = take(NF * nc);
     a.vol = take(8 * nc);
     a.hdt = take(8 * nc);
     a.fcell = take(8 * nf);

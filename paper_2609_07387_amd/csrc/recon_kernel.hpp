@@ -142,18 +142,37 @@ __device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, 
         dmax[t] = dsum[t] = T(0);
         dmin[t] = T(INFINITY);
     }
-    // one pass over the face neighbours for both variables
+    // one pass over the face neighbours for both variables; all their ids,
+    // offsets and states are loaded up front (two memory round trips in all)
+    const int NF = A.NF;
+    const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
+    const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
+    const auto rN = rsrc(A.nbr, uint64_t(NF) * rowI);
+    const auto rD = rsrc(A.ndc, uint64_t(NF) * 3 * rowT);
+    const auto rU = rsrc(A.U, uint64_t(5) * rowU);
+    int32_t jn[kMaxFaces];
+    T dn[kMaxFaces][3];
+    double un[kMaxFaces][2];
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf) {
+        jn[lf] = lf < NF ? bld<int32_t>(rN, c4, uint32_t(lf) * rowI) : -1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dn[lf][d] = lf < NF ? bld<T>(rD, cT, uint32_t(lf * 3 + d) * rowT) : T(0);
+    }
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            un[lf][t] = jn[lf] >= 0 ? bld<double>(rU, uint32_t(jn[lf]) * 8u, uint32_t(t ? 4 : 0) * rowU) : 0.0;
     int cnt = 0;
-    for (int lf = 0; lf < A.NF; ++lf) {
-        const int32_t j = A.nbr[int64_t(lf) * nc + c];
-        if (j < 0) continue;
-        const T dx = A.ndc[(int64_t(lf) * 3 + 0) * nc + c];
-        const T dy = A.ndc[(int64_t(lf) * 3 + 1) * nc + c];
-        const T dz = A.ndc[(int64_t(lf) * 3 + 2) * nc + c];
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf) {
+        if (jn[lf] < 0) continue;
+        const T dx = dn[lf][0], dy = dn[lf][1], dz = dn[lf][2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int v = t ? 4 : 0;
-            const T du = T(A.U[v * nc + j] - ui[v]);
+            const T du = T(un[lf][t] - ui[v]);
             const T rr = fabs(du - (g[t][0] * dx + g[t][1] * dy + g[t][2] * dz) / h) /
                          (fabs(du) + gn[t] + T(1e-12) * au[t]);
             dmax[t] = fmax(dmax[t], rr);
@@ -259,9 +278,8 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
                                             const T a[K][5]) {
     const int64_t nc = A.nc;
     const int NF = A.NF, Q = A.Q;
-    const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T));
-    const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
-    const auto rC = rsrc(A.c2f, uint64_t(NF) * rowI);
+    const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T));
+    const uint32_t cT = uint32_t(c) * uint32_t(sizeof(T));
     T pm[K];
     {
         const auto rM = rsrc(A.pmean, uint64_t(K) * rowT);
@@ -269,22 +287,27 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
         for (int k = 0; k < K; ++k) pm[k] = bld<T>(rM, cT, uint32_t(k) * rowT);
     }
     bool ok = true;
-    // the loops are wave-uniform (every lane walks all NF x Q slots); a lane
-    // skips the slots its cell does not have.  The offset of point (lf, q) in
-    // rows ((lf Q + q) 3 + d), the point's state in rows ((lf Q + q) 5 + v).
-    // all of a face's point offsets are loaded together (one latency per
-    // face, not per point)
+    // The loops are wave-uniform (every lane walks all NF x Q slots); a lane
+    // skips the points its cell does not have (nq of the slot).  The offset
+    // of point (lf, q) in rows ((lf Q + q) 3 + d), its state in rows
+    // ((lf Q + q) 5 + v).  The next face's offsets and point count load while
+    // this face's points are formed, so only the first face waits on memory.
     constexpr int QM = face_qmax<K>();
-#pragma unroll 1
-    for (int lf = 0; lf < NF; ++lf) {
-        const int32_t f2 = bld<int32_t>(rC, c4, uint32_t(lf) * rowI);
-        T x[QM][3];
-        const auto rX = rsrc(A.xi + int64_t(lf) * Q * 3 * nc, uint64_t(Q) * 3 * rowT);
+    const auto rX = rsrc(A.xi, uint64_t(NF) * Q * 3 * rowT);
+    const auto rQ = rsrc(A.cnq, uint64_t(NF) * uint64_t(nc));
+    auto load_face = [&](int lf, T (&x)[QM][3]) {
 #pragma unroll
         for (int q = 0; q < QM; ++q)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) x[q][d] = q < Q ? bld<T>(rX, cT, uint32_t(q * 3 + d) * rowT) : T(0);
-        const int nq = f2 < 0 ? 0 : int(A.fnq[f2 >> 1]);
+            for (int d = 0; d < 3; ++d)
+                x[q][d] = q < Q ? bld<T>(rX, cT, uint32_t((lf * Q + q) * 3 + d) * rowT) : T(0);
+        return int(__builtin_amdgcn_raw_buffer_load_b8(rQ, int(uint32_t(c)), int(uint32_t(lf) * uint32_t(nc)), 0));
+    };
+    T x[QM][3], xn[QM][3];
+    int nq = load_face(0, x);
+#pragma unroll 1
+    for (int lf = 0; lf < NF; ++lf) {
+        const int nqn = lf + 1 < NF ? load_face(lf + 1, xn) : 0;
 #pragma unroll
         for (int q = 0; q < QM; ++q) {
             if (q >= nq) continue;
@@ -308,8 +331,95 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
 #pragma unroll
             for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cT, uint32_t(v) * rowT);
         }
+#pragma unroll
+        for (int q = 0; q < QM; ++q)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) x[q][d] = xn[q][d];
+        nq = nqn;
     }
     return ok;
+}
+
+// Running state of the blend (steps iv-vi) of one cell: the central
+// indicator, the sums over its directional stencils and the linear-mode
+// correction G, so that stencils can be added one at a time.
+template <class T>
+struct Blend {
+    T lam_s, lam_1;
+    T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5], g[3][5];
+    T o00, o01, o02, o11, o12, o22;  // the linear block of O
+};
+
+template <class T, int K>
+__device__ __forceinline__ void blend_init(const ReconArgs<T>& A, int64_t c, int nd, const T a[K][5], Blend<T>& B) {
+    const int64_t nc = A.nc;
+    B.lam_s = T(1) / (A.lam_c + T(nd));
+    B.lam_1 = A.lam_c * B.lam_s;
+    si_opt<T, K>(A, c, a, B.SI1);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        B.tsum[v] = T(0);
+        B.inv1[v] = T(1) / (A.eps + B.SI1[v]);
+        B.Lam[v] = B.lam_1 * B.inv1[v];
+        B.rmin[v] = B.inv1[v];
+        B.rmax[v] = B.inv1[v];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) B.g[k][v] = T(0);
+    }
+    B.o00 = A.O[0 * nc + c];
+    B.o01 = A.O[1 * nc + c];
+    B.o02 = A.O[2 * nc + c];
+    B.o11 = A.O[int64_t(K) * nc + c];
+    B.o12 = A.O[int64_t(K + 1) * nc + c];
+    B.o22 = A.O[int64_t(2 * K - 1) * nc + c];
+}
+
+// One directional stencil with linear coefficients as: its indicator and its
+// share of the blend.
+template <class T>
+__device__ __forceinline__ void blend_add(const ReconArgs<T>& A, Blend<T>& B, const T as[3][5]) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const T x = as[0][v], y = as[1][v], z = as[2][v];
+        const T SIs = fmax(x * (B.o00 * x + T(2) * (B.o01 * y + B.o02 * z)) + y * (B.o11 * y + T(2) * B.o12 * z) +
+                               z * B.o22 * z,
+                           T(0));
+        B.tsum[v] += fabs(B.SI1[v] - SIs);
+        const T r = T(1) / (A.eps + SIs);
+        B.Lam[v] += B.lam_s * r;
+        B.rmin[v] = fmin(B.rmin[v], r);
+        B.rmax[v] = fmax(B.rmax[v], r);
+        const T coef = B.lam_s * (r - B.inv1[v]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) B.g[k][v] += coef * as[k][v];
+    }
+}
+
+// The blended coefficients (overwriting the central ones in a) and, with
+// LABEL, max |omega - lambda| over variables and stencils.
+template <class T, int K, bool LABEL>
+__device__ __forceinline__ void blend_finish(Blend<T>& B, int nd, float& lab, T a[K][5]) {
+    T s1[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const T tau = B.tsum[v] / T(nd);
+        const T W = T(1) + tau * B.Lam[v];
+        s1[v] = (T(1) + tau * B.inv1[v]) / W;
+        const T tw = tau / W;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) B.g[k][v] *= tw;
+        if constexpr (LABEL) {
+            // |omega_s - lambda_s| = lambda_s |(1 + tau r_s)/W - 1|: extreme at rmin or rmax
+            const float d1 = float(fabs(B.lam_1 * (s1[v] - T(1))));
+            const float d2 = float(fabs(B.lam_s * ((T(1) + tau * B.rmin[v]) / W - T(1))));
+            const float d3 = float(fabs(B.lam_s * ((T(1) + tau * B.rmax[v]) / W - T(1))));
+            lab = fmaxf(lab, fmaxf(d1, fmaxf(d2, d3)));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) a[k][v] = s1[v] * a[k][v] + (k < 3 ? B.g[k < 3 ? k : 0][v] : T(0));
 }
 
 // One lane per cell: steps (iii)-(vi) for a cell with nd > 0 directional
@@ -319,138 +429,174 @@ template <class T, int K, bool LABEL>
 __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c, const double* ui, int nd, float& lab,
                                                T a[K][5]) {
     const int64_t nc = A.nc;
-    T s1[5], g[3][5];
+    Blend<T> B;
+    blend_init<T, K>(A, c, nd, a, B);
+    // all directional members as one pipelined stream t = s * MD + m over
+    // every stencil slot (a wave-uniform count; the slots past the cell's
+    // nd hold zero operators and are not counted); the id of member t at
+    // sten_d[t][c], its 3 operator rows at Bd[t][k][c]
+    const int MD = A.MD, total = A.ND * MD;
+    const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T));
+    const uint32_t rowU = uint32_t(nc) * 8u;
+    const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
+    const auto rS = rsrc(A.sten_d, uint64_t(total) * rowI);
+    const auto rU = rsrc(A.U, uint64_t(5) * rowU);
+    // loads DEPTH members ahead (ids one further), as in central_coeffs
+    constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+    auto last = [&](int t) { return t < total ? t : total - 1; };
+    double u[DEPTH + 1][5];
+    T b[DEPTH + 1][3];
+    int32_t jn[DEPTH + 1];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        s1[v] = T(1);
+    for (int d = 0; d <= DEPTH; ++d) jn[d] = bld<int32_t>(rS, c4, uint32_t(last(d)) * rowI);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g[k][v] = T(0);
+    for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
+        const auto rB = rsrc(A.Bd + int64_t(last(d)) * 3 * nc, uint64_t(3) * rowT);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
     }
-    {
-        const T lam_s = T(1) / (A.lam_c + T(nd));
-        const T lam_1 = A.lam_c * lam_s;
-        T SI1[5], inv1[5], tsum[5], Lam[5], rmin[5], rmax[5];
-        si_opt<T, K>(A, c, a, SI1);
+    int32_t jnext = jn[DEPTH];
+    T as[3][5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            tsum[v] = T(0);
-            inv1[v] = T(1) / (A.eps + SI1[v]);
-            Lam[v] = lam_1 * inv1[v];
-            rmin[v] = inv1[v];
-            rmax[v] = inv1[v];
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+    int m = 0, s = 0;
+#pragma unroll 1
+    for (int t = 0; t < total; ++t) {
+        const int tf = last(t + DEPTH);
+        const int32_t jf = bld<int32_t>(rS, c4, uint32_t(last(t + DEPTH + 1)) * rowI);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
+        {
+            const auto rB = rsrc(A.Bd + int64_t(tf) * 3 * nc, uint64_t(3) * rowT);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
         }
-        const T o00 = A.O[0 * nc + c], o01 = A.O[1 * nc + c], o02 = A.O[2 * nc + c];
-        const T o11 = A.O[int64_t(K) * nc + c], o12 = A.O[int64_t(K + 1) * nc + c];
-        const T o22 = A.O[int64_t(2 * K - 1) * nc + c];
-        // all directional members as one pipelined stream t = s * MD + m over
-        // every stencil slot (a wave-uniform count; the slots past the cell's
-        // nd hold zero operators and are not counted); the id of member t at
-        // sten_d[t][c], its 3 operator rows at Bd[t][k][c]
-        const int MD = A.MD, total = A.ND * MD;
-        const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T));
-        const uint32_t rowU = uint32_t(nc) * 8u;
-        const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
-        const auto rS = rsrc(A.sten_d, uint64_t(total) * rowI);
-        const auto rU = rsrc(A.U, uint64_t(5) * rowU);
-        // loads DEPTH members ahead (ids one further), as in central_coeffs
-        constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
-        auto last = [&](int t) { return t < total ? t : total - 1; };
-        double u[DEPTH + 1][5];
-        T b[DEPTH + 1][3];
-        int32_t jn[DEPTH + 1];
+        T bv[5];
 #pragma unroll
-        for (int d = 0; d <= DEPTH; ++d) jn[d] = bld<int32_t>(rS, c4, uint32_t(last(d)) * rowI);
-#pragma unroll
-        for (int d = 0; d < DEPTH; ++d) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
-            const auto rB = rsrc(A.Bd + int64_t(last(d)) * 3 * nc, uint64_t(3) * rowT);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
-        }
-        int32_t jnext = jn[DEPTH];
-        T as[3][5];
+        for (int v = 0; v < 5; ++v) bv[v] = T(u[0][v] - ui[v]);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
-        int m = 0, s = 0;
-#pragma unroll 1
-        for (int t = 0; t < total; ++t) {
-            const int tf = last(t + DEPTH);
-            const int32_t jf = bld<int32_t>(rS, c4, uint32_t(last(t + DEPTH + 1)) * rowI);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
-            {
-                const auto rB = rsrc(A.Bd + int64_t(tf) * 3 * nc, uint64_t(3) * rowT);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
-            }
-            T bv[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) bv[v] = T(u[0][v] - ui[v]);
+            for (int v = 0; v < 5; ++v) as[k][v] += b[0][k] * bv[v];
+        if (m + 1 == MD) {
+            // stencil s complete
+            if (s < nd) blend_add<T>(A, B, as);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) as[k][v] += b[0][k] * bv[v];
-            if (m + 1 == MD) {
-                // stencil s complete: its indicator and its share of the blend
-                if (s < nd) {
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) {
-                        const T x = as[0][v], y = as[1][v], z = as[2][v];
-                        const T SIs = fmax(
-                            x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) + z * o22 * z,
-                            T(0));
-                        tsum[v] += fabs(SI1[v] - SIs);
-                        const T r = T(1) / (A.eps + SIs);
-                        Lam[v] += lam_s * r;
-                        rmin[v] = fmin(rmin[v], r);
-                        rmax[v] = fmax(rmax[v], r);
-                        const T coef = lam_s * (r - inv1[v]);
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) g[k][v] += coef * as[k][v];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) as[k][v] = T(0);
-                m = 0;
-                ++s;
-            } else {
-                ++m;
-            }
-#pragma unroll
-            for (int d = 0; d < DEPTH; ++d) {
-#pragma unroll
-                for (int v = 0; v < 5; ++v) u[d][v] = u[d + 1][v];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) b[d][k] = b[d + 1][k];
-            }
-            jnext = jf;
+                for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+            m = 0;
+            ++s;
+        } else {
+            ++m;
         }
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const T tau = tsum[v] / T(nd);
-            const T W = T(1) + tau * Lam[v];
-            s1[v] = (T(1) + tau * inv1[v]) / W;
-            const T tw = tau / W;
+        for (int d = 0; d < DEPTH; ++d) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) g[k][v] *= tw;
-            if constexpr (LABEL) {
-                // |omega_s - lambda_s| = lambda_s |(1 + tau r_s)/W - 1|: extreme at rmin or rmax
-                const float d1 = float(fabs(lam_1 * (s1[v] - T(1))));
-                const float d2 = float(fabs(lam_s * ((T(1) + tau * rmin[v]) / W - T(1))));
-                const float d3 = float(fabs(lam_s * ((T(1) + tau * rmax[v]) / W - T(1))));
-                lab = fmaxf(lab, fmaxf(d1, fmaxf(d2, d3)));
-            }
+            for (int v = 0; v < 5; ++v) u[d][v] = u[d + 1][v];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[d][k] = b[d + 1][k];
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) a[k][v] = s1[v] * a[k][v] + (k < 3 ? g[k < 3 ? k : 0][v] : T(0));
+        jnext = jf;
     }
+    blend_finish<T, K, LABEL>(B, nd, lab, a);
+}
+
+template <class T>
+__device__ __forceinline__ T lane_read(T x, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), lane));
+        const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), lane));
+        return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+    }
+}
+
+// value of lane (this lane + d), any lane of the wave (wraps past 63)
+template <class T>
+__device__ __forceinline__ T lane_down(T x, int lane, int d) {
+    const int addr = ((lane + d) & 63) << 2;
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, x)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u))));
+        const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u >> 32))));
+        return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+    }
+}
+
+// Waves with at most this many troubled cells take them one at a time with
+// the whole wave (dir_blend_wave); busier waves run one lane per cell.
+constexpr int kWaveBlendMax = 8;
+
+// Steps (iii)-(vi) for the troubled cells of a wave that has few of them
+// (the lanes set in todo; every lane of the wave calls this).  One at a
+// time, lane t loads directional slot t of the cell (stencil t / MD, member
+// t % MD; ND * MD <= 64), the member products are summed per stencil across
+// the lanes, and each stencil's coefficients are read by the cell's own lane,
+// which forms the blend exactly as the one-lane path does.  A lone troubled
+// cell thus waits for one round of loads instead of ND * MD of them.  Only
+// the products' summation order differs from dir_blend_lane.
+template <class T, int K>
+__device__ __forceinline__ void dir_blend_wave(const ReconArgs<T>& A, uint64_t todo, int64_t c, const double* ui,
+                                               int nd, T a[K][5]) {
+    const int64_t nc = A.nc;
+    const int lane = int(threadIdx.x & 63u);
+    const int MD = A.MD, total = A.ND * MD, m = lane % MD;
+    const bool mine = (todo >> lane) & 1u;
+    Blend<T> B;
+    if (mine) blend_init<T, K>(A, c, nd, a, B);
+    while (todo) {
+        const int L = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int64_t cL = __builtin_amdgcn_readlane(int(c), L);
+        const int ndL = __builtin_amdgcn_readlane(nd, L);
+        T x[3][5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) x[k][v] = T(0);
+        if (lane < total) {
+            const int32_t j = A.sten_d[int64_t(lane) * nc + cL];
+            T b[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[k] = A.Bd[(int64_t(lane) * 3 + k) * nc + cL];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T bv = T(A.U[v * nc + j] - lane_read(ui[v], L));
+#pragma unroll
+                for (int k = 0; k < 3; ++k) x[k][v] = b[k] * bv;
+            }
+        }
+        // sums over the members of each stencil: after the step with d,
+        // lane s MD + m holds the sum over members m .. min(m + 2d, MD) - 1
+        for (int d = 1; d < MD; d <<= 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    const T y = lane_down(x[k][v], lane, d);
+                    if (m + d < MD) x[k][v] += y;
+                }
+        }
+        for (int s = 0; s < ndL; ++s) {
+            T as[3][5];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) as[k][v] = lane_read(x[k][v], s * MD);
+            if (lane == L) blend_add<T>(A, B, as);
+        }
+    }
+    float lab = 0.f;
+    if (mine) blend_finish<T, K, false>(B, nd, lab, a);
 }
 
 // One lane per cell: steps (iii)-(vi) for mode 1, then (vii) for any mode.
@@ -511,14 +657,18 @@ void reconstruct_kernel(ReconArgs<T> A) {
             central_coeffs<T, K>(A, c, ui, a);
             mode = A.gate[c] ? 0 : 1;
         }
-        // troubled cells run their directional streams in place
+        // troubled cells: with the whole wave one at a time when the wave has
+        // few, else each in its own lane
+        const int nd = valid && mode == 1 ? int(A.ndir[c]) : 0;
+        const uint64_t todo = __builtin_amdgcn_ballot_w64(nd > 0);
+        if (todo != 0 && __builtin_popcountll(todo) <= kWaveBlendMax && A.ND * A.MD <= 64) {
+            dir_blend_wave<T, K>(A, todo, c, ui, nd, a);
+        } else if (nd > 0) {
+            float lab = 0.f;
+            dir_blend_lane<T, K, false>(A, c, ui, nd, lab, a);
+        }
         if (!valid) return;
         if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
-        if (mode == 1) {
-            const int nd = A.ndir[c];
-            float lab = 0.f;
-            if (nd > 0) dir_blend_lane<T, K, false>(A, c, ui, nd, lab, a);
-        }
         const bool ok = face_values<T, K>(A, c, ui, 0, a);
         A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
     } else {

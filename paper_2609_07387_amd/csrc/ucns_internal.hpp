@@ -24,6 +24,7 @@ void set_error(const std::string& msg);
 struct Arena {
     size_t bytes = 0;
     size_t sten_c = 0, Bc = 0, ndir = 0, sten_d = 0, Bd = 0, O = 0, xi = 0, pmean = 0, c2f = 0;
+    size_t cnq = 0;  // [nfmax][nc] Gauss points of each of a cell's face slots (0: no face)
     size_t vol = 0, hdt = 0, fcell = 0, flf = 0, fnrm = 0, farea = 0, fw = 0, fdc = 0, fnq = 0;
     size_t nbr = 0, ndc = 0, hb = 0, ncen = 0;  // gate features: face neighbours, offsets, basis scale, stencil size
     void* dev = nullptr;  // caller-owned device pointer after upload

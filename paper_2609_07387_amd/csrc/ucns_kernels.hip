@@ -95,8 +95,7 @@ struct ReconArgs {
     const T* O;
     const T* xi;     // face points in each cell's scaled frame [lf][q][3][nc]
     const T* pmean;  // cell means of the scaled monomials [K][nc]
-    const int32_t* c2f;
-    const uint8_t* fnq;
+    const uint8_t* cnq;  // Gauss points of each face slot [lf][nc] (0: no face)
     int Q, NF;
     const uint8_t* gate;
     T* fs;
@@ -574,8 +573,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.O = arena_ptr<T>(ar, ar.O);
     A.xi = arena_ptr<T>(ar, ar.xi);
     A.pmean = arena_ptr<T>(ar, ar.pmean);
-    A.c2f = arena_ptr<int32_t>(ar, ar.c2f);
-    A.fnq = arena_ptr<uint8_t>(ar, ar.fnq);
+    A.cnq = arena_ptr<uint8_t>(ar, ar.cnq);
     A.Q = m.qmax;
     A.NF = m.nfmax;
     A.gate = gate ? gate->mask : nullptr;
