@@ -534,7 +534,7 @@ __device__ __forceinline__ T lane_down(T x, int lane, int d) {
 
 // Waves with at most this many troubled cells take them one at a time with
 // the whole wave (dir_blend_wave); busier waves run one lane per cell.
-constexpr int kWaveBlendMax = 8;
+constexpr int kWaveBlendMax = 2;
 
 // Steps (iii)-(vi) for the troubled cells of a wave that has few of them
 // (the lanes set in todo; every lane of the wave calls this).  One at a
@@ -599,6 +599,188 @@ __device__ __forceinline__ void dir_blend_wave(const ReconArgs<T>& A, uint64_t t
     if (mine) blend_finish<T, K, false>(B, nd, lab, a);
 }
 
+// Busier waves (up to this many troubled cells) take their troubled cells
+// with one lane per (cell, directional stencil); FP32 P2 only, where the
+// central coefficients of a wave fit in its LDS.
+constexpr int kStencilLanesMax = 30;
+
+template <class T>
+__device__ __forceinline__ T lane_from(T x, int src) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, x)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src << 2, int(uint32_t(u))));
+        const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src << 2, int(uint32_t(u >> 32))));
+        return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+    }
+}
+
+// Steps (iii)-(vi) for the troubled cells of a wave (the lanes set in todo;
+// every lane of the wave calls this) with one lane per (cell, stencil): each
+// pass gives the next 64 / ND troubled cells ND lanes each; lane s of a cell
+// streams the MD members of the cell's stencil s and forms that stencil's
+// indicator and blend terms, the terms are summed over the cell's lanes, and
+// the cell's own lane adds them to its blend.  A troubled cell thus waits
+// for MD member loads instead of ND * MD.  The lanes' central coefficients
+// wait in LDS (stash, K * 5 * 64 floats) meanwhile, freeing their registers
+// for the streams.  Only the summation order of the blend terms differs from
+// dir_blend_lane.
+template <int K, int SDEPTH = 2>
+__device__ __forceinline__ void dir_blend_stencils(const ReconArgs<float>& A, uint64_t todo, int64_t c,
+                                                   const double* ui, int nd, float a[K][5], float* stash) {
+    using T = float;
+    const int64_t nc = A.nc;
+    const int lane = int(threadIdx.x & 63u);
+    const int ND = A.ND, MD = A.MD, per = 64 / ND;
+    const int p = lane / ND, s = lane - p * ND;  // this lane's cell (within the pass) and stencil
+    const bool mine = (todo >> lane) & 1u;
+    Blend<T> B;
+    if (mine) blend_init<T, K>(A, c, nd, a, B);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) stash[(k * 5 + v) * 64 + lane] = a[k][v];
+    while (todo) {
+        // the next `per` troubled cells, and this lane's cell among them
+        uint64_t pass = 0, rest = todo;
+        int src = -1;
+        for (int k = 0; k < per && rest; ++k) {
+            const int L = __builtin_ctzll(rest);
+            pass |= 1ull << L;
+            rest &= rest - 1;
+            if (k == p) src = L;
+        }
+        todo = rest;
+        const int sl = src >= 0 ? src : lane;
+        const int cp = lane_from(int(c), sl);
+        const int ndp = lane_from(nd, sl);
+        const bool work = src >= 0 && s < ndp;
+        double up[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) up[v] = lane_from(ui[v], sl);
+        const int64_t cq = cp;
+        T as[3][5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+        if (work) {
+            // members of stencil s, loads SDEPTH members ahead (ids one further)
+            const int64_t r0 = int64_t(s) * MD;
+            auto row = [&](int m) { return r0 + (m < MD ? m : MD - 1); };
+            double u[SDEPTH + 1][5];
+            T b[SDEPTH + 1][3];
+            int32_t jn[SDEPTH + 1];
+#pragma unroll
+            for (int d = 0; d <= SDEPTH; ++d) jn[d] = A.sten_d[row(d) * nc + cq];
+#pragma unroll
+            for (int d = 0; d < SDEPTH; ++d) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) u[d][v] = A.U[v * nc + jn[d]];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b[d][k] = A.Bd[(row(d) * 3 + k) * nc + cq];
+            }
+            int32_t jnext = jn[SDEPTH];
+#pragma unroll 1
+            for (int m = 0; m < MD; ++m) {
+                const int32_t jf = A.sten_d[row(m + SDEPTH + 1) * nc + cq];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) u[SDEPTH][v] = A.U[v * nc + jnext];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b[SDEPTH][k] = A.Bd[(row(m + SDEPTH) * 3 + k) * nc + cq];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    const T bv = T(u[0][v] - up[v]);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) as[k][v] += b[0][k] * bv;
+                }
+#pragma unroll
+                for (int d = 0; d < SDEPTH; ++d) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) u[d][v] = u[d + 1][v];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) b[d][k] = b[d + 1][k];
+                }
+                jnext = jf;
+            }
+        }
+        // the stencil's indicator and blend terms (zero on idle lanes)
+        T SI1p[5], inv1p[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            SI1p[v] = lane_from(B.SI1[v], sl);
+            inv1p[v] = lane_from(B.inv1[v], sl);
+        }
+        T ts[5], lm[5], gg[3][5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            ts[v] = lm[v] = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gg[k][v] = T(0);
+        }
+        if (work) {
+            const T o00 = A.O[0 * nc + cq], o01 = A.O[1 * nc + cq], o02 = A.O[2 * nc + cq];
+            const T o11 = A.O[int64_t(K) * nc + cq], o12 = A.O[int64_t(K + 1) * nc + cq];
+            const T o22 = A.O[int64_t(2 * K - 1) * nc + cq];
+            const T lam_s = T(1) / (A.lam_c + T(ndp));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T x = as[0][v], y = as[1][v], z = as[2][v];
+                const T SIs = fmax(x * (o00 * x + T(2) * (o01 * y + o02 * z)) + y * (o11 * y + T(2) * o12 * z) +
+                                       z * o22 * z,
+                                   T(0));
+                ts[v] = fabs(SI1p[v] - SIs);
+                const T r = T(1) / (A.eps + SIs);
+                lm[v] = lam_s * r;
+                const T coef = lam_s * (r - inv1p[v]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gg[k][v] = coef * as[k][v];
+            }
+        }
+        // sums over the ND lanes of each cell: after the step with d, lane
+        // p ND + s holds the sum over stencils s .. min(s + 2d, ND) - 1
+        for (int d = 1; d < ND; d <<= 1) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const T y0 = lane_down(ts[v], lane, d), y1 = lane_down(lm[v], lane, d);
+                if (s + d < ND) {
+                    ts[v] += y0;
+                    lm[v] += y1;
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const T y = lane_down(gg[k][v], lane, d);
+                    if (s + d < ND) gg[k][v] += y;
+                }
+            }
+        }
+        // each cell's lane takes its sums from lane rank * ND
+        const bool inpass = (pass >> lane) & 1u;
+        const int rank = int(__builtin_amdgcn_mbcnt_hi(uint32_t(pass >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(pass), 0u)));
+        const int from = inpass ? rank * ND : lane;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const T x0 = lane_from(ts[v], from), x1 = lane_from(lm[v], from);
+            if (inpass) {
+                B.tsum[v] += x0;
+                B.Lam[v] += x1;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T x = lane_from(gg[k][v], from);
+                if (inpass) B.g[k][v] += x;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) a[k][v] = stash[(k * 5 + v) * 64 + lane];
+    float lab = 0.f;
+    if (mine) blend_finish<T, K, false>(B, nd, lab, a);
+}
+
 // One lane per cell: steps (iii)-(vi) for mode 1, then (vii) for any mode.
 template <class T, int K, bool LABEL>
 __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab,
@@ -635,8 +817,13 @@ void reconstruct_kernel(ReconArgs<T> A) {
     T a[K][5];
     if constexpr (GATE) {
         int mode = 0;
+        // per wave: the network's scratch, then (FP32 P2) the stash of
+        // dir_blend_stencils
+        constexpr int kStash = sizeof(T) == 4 && K == 9 ? K * 5 * 64 * 4 : 0;
+        constexpr int kWaveLds = sizeof(MlpWaveLds) > kStash ? int(sizeof(MlpWaveLds)) : kStash;
+        __shared__ __attribute__((aligned(16))) unsigned char lds[kBlock / 64][kWaveLds];
+        unsigned char* wl = lds[threadIdx.x >> 6];
         if (A.mlp) {
-            __shared__ MlpWaveLds Wv[kBlock / 64];
             const float* fv = reinterpret_cast<const float*>(A.mlp + mlpimg::kF);
             float f[12];
             if (valid) {
@@ -649,7 +836,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) f[k] = fv[mlpimg::kMu + k];
             }
-            const float z = mlp_wave_forward_packed(A.mlp, Wv[threadIdx.x >> 6], f);  // all lanes of the wave
+            const float z = mlp_wave_forward_packed(A.mlp, *reinterpret_cast<MlpWaveLds*>(wl), f);  // all lanes
             mode = 1.f / (1.f + __expf(-z)) < fv[mlpimg::kTheta] ? 0 : 1;
         } else if (valid) {
 #pragma unroll
@@ -661,9 +848,19 @@ void reconstruct_kernel(ReconArgs<T> A) {
         // few, else each in its own lane
         const int nd = valid && mode == 1 ? int(A.ndir[c]) : 0;
         const uint64_t todo = __builtin_amdgcn_ballot_w64(nd > 0);
-        if (todo != 0 && __builtin_popcountll(todo) <= kWaveBlendMax && A.ND * A.MD <= 64) {
+        const int nt = __builtin_popcountll(todo);
+        bool done = todo == 0;
+        if (!done && nt <= kWaveBlendMax && A.ND * A.MD <= 64) {
             dir_blend_wave<T, K>(A, todo, c, ui, nd, a);
-        } else if (nd > 0) {
+            done = true;
+        }
+        if constexpr (kStash > 0) {
+            if (!done && nt <= kStencilLanesMax) {
+                dir_blend_stencils<K>(A, todo, c, ui, nd, a, reinterpret_cast<float*>(wl));
+                done = true;
+            }
+        }
+        if (!done && nd > 0) {
             float lab = 0.f;
             dir_blend_lane<T, K, false>(A, c, ui, nd, lab, a);
         }
