@@ -235,6 +235,16 @@ int ucns_rk_stage(const ucns_mesh* mesh, int stage, const double* dt_dev, double
 int ucns_residual_rk_stage(const ucns_mesh* mesh, const void* face_flux, int precision, int stage,
                            const double* dt_dev, double* U0, double* U, ucns_stream stream);
 
+/* The last SSP-RK3 stage (ucns_residual_rk_stage with stage 2) fused with the
+ * two reductions a step ends with, taken on the new U while it is in
+ * registers: the time step of the next step (as ucns_dt with cfl) into
+ * *dt_next_dev and the kinetic energy (as ucns_diag_ke) into *ke_dev, each a
+ * deterministic two-pass reduction (per-block partials in reduce_scratch,
+ * then one small kernel).  dt_next_dev may equal dt_dev. */
+int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux, int precision,
+                           const double* dt_dev, double* U0, double* U, double cfl, double* reduce_scratch,
+                           double* dt_next_dev, double* ke_dev, ucns_stream stream);
+
 /* Kinetic energy sum |V| |m|^2 / (2 rho) / sum |V| (deterministic two-pass
  * sum in a fixed order); writes *ke_dev. */
 int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* reduce_scratch, double* ke_dev,

@@ -403,6 +403,8 @@ void cell_geometry(Mesh& m, int nt) {
             m.hdt[c] = 6.0 * V / S;
         }
     });
+    m.total_vol = 0;
+    for (int64_t c = 0; c < m.nc; ++c) m.total_vol += m.vol[c];
 }
 
 // ----------------------------------------------------------------- stencils

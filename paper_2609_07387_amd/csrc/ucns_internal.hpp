@@ -50,6 +50,7 @@ struct Mesh {
     std::vector<int32_t> c2f;     // [nc][kMaxFaces] = 2 f + side, -1 unused
     // ---- cells
     std::vector<double> vol, cen, hb, hdt;
+    double total_vol = 0;  // sum of vol, in cell order
     std::vector<double> moments;  // [nc][nmom] central moments
     int mom_deg = 0, nmom = 0;
     // ---- stencils

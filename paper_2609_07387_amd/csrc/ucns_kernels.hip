@@ -420,12 +420,82 @@ struct ResArgs {
     const double* dt;
     double a, b;
     int stage;
+    // with FINAL: per-block time-step and kinetic-energy partials of the new U
+    const double* hdt;
+    PhysT<double> P;
+    double* part;  // [2][gridDim]
 };
 
+// Fixed-shape block reduction (deterministic for a fixed launch shape).
+template <bool MIN>
+__device__ double block_reduce(double x) {
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = MIN ? fmin(sh[threadIdx.x], sh[threadIdx.x + s]) : sh[threadIdx.x] + sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Shu-Osher stage update a U0 + b (U + dt R), one explicit rounding order
+// for every kernel that applies it.
+__device__ __forceinline__ double rk_combine(double a, double b, double u0, double u, double dt, double r) {
+    return fma(a, u0, b * fma(dt, r, u));
+}
+
+// Admissible time step of one cell (Sec. 2.3 reading; cfl applied by the
+// caller): h / (|u| + c), and with viscosity rho h^2 / (2 mu max(4/3, gamma/Pr)).
+// NaN or a non-positive value returns -inf, which poisons the minimum.
+__device__ __forceinline__ double cell_dt(const PhysT<double>& P, const double* u, double h) {
+    const double sp = sqrt(u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+    const double cs = sqrt(P.gamma * pressure(P, u) / u[0]);
+    double t = h / (sp + cs);
+    if (P.viscous) t = fmin(t, u[0] * h * h / (2.0 * P.mu * fmax(4.0 / 3.0, P.gamma / P.pr)));
+    return t > 0.0 ? t : -INFINITY;
+}
+
 // R_i = -(1/|V_i|) sum_f s_if F_f over the cell's faces in local order.
-template <class T, bool RK>
+// FINAL (last RK stage): also the block's minimum time step and kinetic-energy
+// sum of the new state, into part[blk] and part[nblocks + blk].
+template <class T, bool RK, bool FINAL = false>
 __global__ __launch_bounds__(kBlock) void residual_kernel(ResArgs<T> A) {
-    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t blk = xcd_block();
+    const int64_t c = blk * blockDim.x + threadIdx.x;
+    if constexpr (FINAL) {
+        double tdt = INFINITY, tke = 0.0;
+        if (c < A.nc) {
+            double acc[5] = {0, 0, 0, 0, 0};
+            for (int lf = 0; lf < A.NF; ++lf) {
+                const int32_t f2 = A.c2f[int64_t(lf) * A.nc + c];
+                if (f2 < 0) continue;
+                const int64_t f = f2 >> 1;
+                const double s = (f2 & 1) ? -1.0 : 1.0;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] += s * double(A.ff[f * 5 + v]);
+            }
+            const double vol = A.vol[c];
+            const double iv = -1.0 / vol;
+            const double dt = *A.dt;
+            double un[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const int64_t i = v * A.nc + c;
+                un[v] = rk_combine(A.a, A.b, A.U0[i], A.U[i], dt, acc[v] * iv);
+                A.U[i] = un[v];
+            }
+            tdt = cell_dt(A.P, un, A.hdt[c]);
+            tke = vol * 0.5 * (un[1] * un[1] + un[2] * un[2] + un[3] * un[3]) / un[0];
+        }
+        const double rdt = block_reduce<true>(tdt);
+        const double rke = block_reduce<false>(tke);
+        if (threadIdx.x == 0) {
+            A.part[blk] = rdt;
+            A.part[gridDim.x + blk] = rke;
+        }
+        return;
+    }
     if (c >= A.nc) return;
     double acc[5] = {0, 0, 0, 0, 0};
     for (int lf = 0; lf < A.NF; ++lf) {
@@ -445,9 +515,9 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(ResArgs<T> A) {
             const double u = A.U[i];
             if (A.stage == 0) {
                 A.U0[i] = u;
-                A.U[i] = u + dt * (acc[v] * iv);
+                A.U[i] = fma(dt, acc[v] * iv, u);
             } else {
-                A.U[i] = A.a * A.U0[i] + A.b * (u + dt * (acc[v] * iv));
+                A.U[i] = rk_combine(A.a, A.b, A.U0[i], u, dt, acc[v] * iv);
             }
         }
     } else {
@@ -463,26 +533,13 @@ __global__ __launch_bounds__(kBlock) void rk_stage_kernel(int64_t n, double* U0,
     const double u = U[i];
     if (stage == 0) {
         U0[i] = u;
-        U[i] = u + *dt * R[i];
+        U[i] = fma(*dt, R[i], u);
     } else {
-        U[i] = a * U0[i] + b * (u + *dt * R[i]);
+        U[i] = rk_combine(a, b, U0[i], u, *dt, R[i]);
     }
 }
 
 // ----------------------------------------------------------------- reductions
-
-// Fixed-shape block reduction (deterministic for a fixed launch shape).
-template <bool MIN>
-__device__ double block_reduce(double x) {
-    __shared__ double sh[kBlock];
-    sh[threadIdx.x] = x;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] = MIN ? fmin(sh[threadIdx.x], sh[threadIdx.x + s]) : sh[threadIdx.x] + sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    return sh[0];
-}
 
 __global__ __launch_bounds__(kBlock) void dt_partial_kernel(int64_t nc, const double* U, const double* hdt,
                                                             PhysT<double> P, double* part) {
@@ -491,13 +548,7 @@ __global__ __launch_bounds__(kBlock) void dt_partial_kernel(int64_t nc, const do
         double u[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) u[v] = U[v * nc + c];
-        const double sp = sqrt(u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
-        const double cs = sqrt(P.gamma * pressure(P, u) / u[0]);
-        const double h = hdt[c];
-        double t = h / (sp + cs);
-        if (P.viscous) t = fmin(t, u[0] * h * h / (2.0 * P.mu * fmax(4.0 / 3.0, P.gamma / P.pr)));
-        if (!(t > 0.0)) t = -INFINITY;  // NaN or non-positive: poisons the minimum
-        best = fmin(best, t);
+        best = fmin(best, cell_dt(P, u, hdt[c]));
     }
     const double r = block_reduce<true>(best);
     if (threadIdx.x == 0) part[blockIdx.x] = r;
@@ -518,6 +569,22 @@ __global__ __launch_bounds__(kBlock) void ke_partial_kernel(int64_t nc, const do
     }
     const double t = block_reduce<false>(s);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// dt_final and ke_final of the fused last stage in one launch.
+__global__ __launch_bounds__(kBlock) void rk_final_kernel(int nb, const double* part, double cfl, double inv_vol,
+                                                          double* dt, double* ke) {
+    double best = INFINITY, sum = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        best = fmin(best, part[i]);
+        sum += part[nb + i];
+    }
+    const double r = block_reduce<true>(best);
+    const double t = block_reduce<false>(sum);
+    if (threadIdx.x == 0) {
+        *dt = (r > 0.0 && r < INFINITY) ? cfl * r : NAN;
+        *ke = t * inv_vol;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void ke_final_kernel(int nb, const double* part, double inv_vol, double* out) {
@@ -753,7 +820,7 @@ int ucns_workspace_elems(const ucns_mesh* mesh, int64_t* face_state, int64_t* fa
     if (face_state) *face_state = int64_t(m.nfmax) * m.qmax * 5 * m.nc;
     if (face_flux) *face_flux = m.nf * 5;
     if (gradW) *gradW = 12 * m.nc;
-    if (reduce_scratch) *reduce_scratch = kRedBlocks;
+    if (reduce_scratch) *reduce_scratch = std::max<int64_t>(kRedBlocks, 2 * int64_t(grid_for(m.nc)));
     return UCNS_OK;
 }
 
@@ -903,13 +970,41 @@ int ucns_rk_stage(const ucns_mesh* mesh, int stage, const double* dt_dev, double
     return hip_check("ucns_rk_stage");
 }
 
+int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux, int precision,
+                           const double* dt_dev, double* U0, double* U, double cfl, double* scratch,
+                           double* dt_next_dev, double* ke_dev, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && face_flux && dt_dev && U0 && U && scratch && dt_next_dev && ke_dev, UCNS_EINVAL,
+                 "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(cfl > 0, UCNS_EINVAL, "cfl must be positive");
+    UCNS_REQUIRE(aligned(face_flux) && aligned(U0) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    const Mesh& m = *mesh->m;
+    const Arena& ar = m.arena[precision];
+    UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const unsigned nb = grid_for(m.nc);
+    auto go = [&](auto zero) {
+        using T = decltype(zero);
+        ResArgs<T> A{static_cast<const T*>(face_flux), m.nc, arena_ptr<int32_t>(ar, ar.c2f), m.nfmax,
+                     arena_ptr<double>(ar, ar.vol), nullptr, U0, U, dt_dev, 1.0 / 3.0, 2.0 / 3.0, 2,
+                     arena_ptr<double>(ar, ar.hdt), make_phys<double>(phys), scratch};
+        hipLaunchKernelGGL((residual_kernel<T, true, true>), dim3(nb), dim3(kBlock), 0, st, A);
+    };
+    if (precision == UCNS_F64)
+        go(double(0));
+    else
+        go(float(0));
+    hipLaunchKernelGGL(rk_final_kernel, dim3(1), dim3(kBlock), 0, st, int(nb), scratch, cfl, 1.0 / m.total_vol,
+                       dt_next_dev, ke_dev);
+    return hip_check("ucns_residual_rk_final");
+}
+
 int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* scratch, double* ke_dev, ucns_stream stream) {
     UCNS_REQUIRE(mesh && U && scratch && ke_dev, UCNS_EINVAL, "null argument");
     const Mesh& m = *mesh->m;
     const Arena& a = m.arena[UCNS_F64].dev ? m.arena[UCNS_F64] : m.arena[UCNS_F32];
     UCNS_REQUIRE(a.dev, UCNS_ESTATE, "mesh not uploaded");
-    double tv = 0;
-    for (int64_t c = 0; c < m.nc; ++c) tv += m.vol[c];
+    const double tv = m.total_vol;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     unsigned nb = std::min<unsigned>(kRedBlocks, grid_for(m.nc));
     hipLaunchKernelGGL(ke_partial_kernel, dim3(nb), dim3(kBlock), 0, st, m.nc, U, arena_ptr<double>(a, a.vol), scratch);

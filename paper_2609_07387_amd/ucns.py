@@ -27,7 +27,7 @@ EXPORTS = [
     "ucns_mesh_upload", "ucns_mesh_faces", "ucns_mesh_cell_geometry", "ucns_mesh_stencil", "ucns_mesh_operators",
     "ucns_workspace_elems", "ucns_dt", "ucns_reconstruct", "ucns_gradients", "ucns_face_flux", "ucns_residual",
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
-    "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack",
+    "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
 ]
 
 
@@ -93,6 +93,7 @@ def lib():
         L.ucns_rk_stage.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ucns_residual_rk_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
         L.ucns_diag_ke.argtypes = [vp, vp, vp, vp, vp]
+        L.ucns_residual_rk_final.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.ucns_gate_features.argtypes = [vp, vp, i32, vp, vp]
         L.ucns_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.ucns_gate_mask.argtypes = [vp, vp, i64, vp, vp]
@@ -319,6 +320,12 @@ def residual_rk_stage(mesh, ff, precision, stage, dt_dev, U0, U, stream=None):
                                        _stream(stream)))
 
 
+def residual_rk_final(mesh, ph, ff, precision, dt_dev, U0, U, cfl, scratch, dt_next, ke_dev, stream=None):
+    """Last RK stage with the next step's dt and the new state's kinetic energy."""
+    check(lib().ucns_residual_rk_final(mesh.h, C.byref(ph), _dp(ff), precision, _dp(dt_dev), _dp(U0), _dp(U),
+                                       float(cfl), _dp(scratch), _dp(dt_next), _dp(ke_dev), _stream(stream)))
+
+
 def diag_ke(mesh, U, scratch, ke_dev, stream=None):
     check(lib().ucns_diag_ke(mesh.h, _dp(U), _dp(scratch), _dp(ke_dev), _stream(stream)))
 
@@ -343,6 +350,7 @@ class Solver:
         self.gate_mask = gate_mask
         self.mlp = mlp
         self.mlp_image = mlp_pack(mlp) if mlp is not None else None
+        self._dt_key = None  # (data pointer, version) of the U whose dt ws.dt holds
 
     def rhs_stage(self, U):
         ws = self.ws
@@ -352,14 +360,27 @@ class Solver:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
         face_flux(self.mesh, self.ph, self.bcs, U, ws.face_state, ws.gradW, self.precision, ws.face_flux)
 
+    def ensure_dt(self, U):
+        """ws.dt = the time step of U (kept from the previous step when valid)."""
+        if self._dt_key != (U.data_ptr(), U._version):
+            dt(self.mesh, self.ph, U, self.cfl, self.ws.reduce, self.ws.dt)
+            self._dt_key = (U.data_ptr(), U._version)
+
     def step(self, U, ke=False):
+        """One SSP-RK3 step of U in place.  The last stage also leaves the
+        next step's dt in ws.dt and the kinetic energy of the new U in ws.ke
+        (whatever ke says), so a step that follows on the same, unmodified U
+        skips its own dt pass (a change to U through torch bumps its version
+        and forces one)."""
         ws = self.ws
-        dt(self.mesh, self.ph, U, self.cfl, ws.reduce, ws.dt)
-        for s in range(3):  # stage 0 stores U^n into U0
+        self.ensure_dt(U)
+        for s in range(2):  # stage 0 stores U^n into U0
             self.rhs_stage(U)
             residual_rk_stage(self.mesh, ws.face_flux, self.precision, s, ws.dt, self.U0, U)
-        if ke:
-            diag_ke(self.mesh, U, ws.reduce, ws.ke)
+        self.rhs_stage(U)
+        residual_rk_final(self.mesh, self.ph, ws.face_flux, self.precision, ws.dt, self.U0, U, self.cfl, ws.reduce,
+                          ws.dt, ws.ke)
+        self._dt_key = (U.data_ptr(), U._version)
 
     def run(self, U, n_steps, ke_history=False):
         import torch
@@ -369,10 +390,12 @@ class Solver:
             diag_ke(self.mesh, U, self.ws.reduce, self.ws.ke)
             hist.append(self.ws.ke.clone())
         for _ in range(n_steps):
-            self.step(U, ke=ke_history)
+            if ke_history:
+                self.ensure_dt(U)
+                dts.append(self.ws.dt.clone())
+            self.step(U)
             if ke_history:
                 hist.append(self.ws.ke.clone())
-                dts.append(self.ws.dt.clone())
         if ke_history:
             return torch.cat(hist).cpu().numpy(), torch.cat(dts).cpu().numpy()
         return None

@@ -162,6 +162,35 @@ def test_determinism_bitwise(torch_cuda):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", [ucns.F64, ucns.F32])
+def test_fused_last_stage(torch_cuda, prec):
+    """ucns_residual_rk_final equals ucns_residual_rk_stage(2) followed by
+    ucns_dt and ucns_diag_ke: the new state bitwise, the next time step
+    bitwise (a minimum), the kinetic energy to rounding of the summation order."""
+    torch = torch_cuda
+    m, order, ph, U0, bcs = _setup("hex7_p2_hllc_ns")
+    lm = ucns.Mesh(m, order=order)
+    s = ucns.Solver(lm, ph, prec, bcs, 0.5)
+    U = torch.tensor(U0, device="cuda")
+    ws = s.ws
+    ucns.dt(lm, ph, U, 0.5, ws.reduce, ws.dt)
+    for st in range(2):
+        s.rhs_stage(U)
+        ucns.residual_rk_stage(lm, ws.face_flux, prec, st, ws.dt, s.U0, U)
+    s.rhs_stage(U)
+    Ua, Ub = U.clone(), U.clone()
+    ucns.residual_rk_stage(lm, ws.face_flux, prec, 2, ws.dt, s.U0, Ua)
+    dta, kea = torch.zeros_like(ws.dt), torch.zeros_like(ws.ke)
+    ucns.dt(lm, ph, Ua, 0.5, ws.reduce, dta)
+    ucns.diag_ke(lm, Ua, ws.reduce, kea)
+    dtb, keb = ws.dt.clone(), torch.zeros_like(ws.ke)
+    ucns.residual_rk_final(lm, ph, ws.face_flux, prec, ws.dt, s.U0, Ub, 0.5, ws.reduce, dtb, keb)
+    torch.cuda.synchronize()
+    assert torch.equal(Ua, Ub)
+    assert torch.equal(dta, dtb)
+    assert abs(float(kea) - float(keb)) <= 1e-13 * abs(float(kea))
+
+
 def test_positivity_fallback(torch_cuda):
     """A near-vacuum cell next to a strong jump forces the fallback; the GPU
     takes the same branch as the oracle and the same point states."""
