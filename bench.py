@@ -36,18 +36,19 @@ METRIC = "cell-stage updates/s, P2 CWENO+HLLC: FP64 plain vs FP32+MLP gate; % HB
 def recon_bytes_per_cell(lm, precision, linear=False, gate=False):
     """Algorithmic HBM bytes of one reconstruction of one cell: every operator
     value and index read once (the basis at a face point is recomputed from
-    the point's 3 scaled coordinates and the cell's K basis means), the
+    the point's 3 scaled coordinates and the cell's K basis means; one byte
+    per face slot gives its point count), the directional-stencil count, the
     cell's own state read once, its face-point states and flag written once
-    (neighbour states are re-reads of resident data).  linear: the cell takes the central polynomial only (no
-    directional operators or indices).  gate: the in-kernel network's
-    per-cell inputs (face-neighbour ids and offsets, basis scale, stencil
-    size) and its mask output."""
+    (neighbour states are re-reads of resident data).  linear: the cell
+    takes the central polynomial only (no directional operators or
+    indices).  gate: the in-kernel network's per-cell inputs (face-neighbour
+    ids and offsets, basis scale, stencil size) and its mask output."""
     t = 8 if precision == 0 else 4
     K, MC, MD, ND, NF, Q = lm.K, lm.mc_pad, max(1, lm.md_pad), max(1, lm.nd_max), lm.nfmax, lm.qmax
     ops = K * MC + NF * Q * 3 + K + (0 if linear else K * (K + 1) // 2 + ND * 3 * MD)
-    idx = MC + NF + (0 if linear else ND * MD)
-    extra = (4 * NF + 3 * NF * t + t + 4 + 1) if gate else 0
-    return t * ops + 4 * idx + 1 + 40 + t * 5 * NF * Q + NF + extra
+    idx = MC + (0 if linear else ND * MD)
+    extra = (4 * NF + 3 * NF * t + t + 1 + 1) if gate else 0
+    return t * ops + 4 * idx + NF + 1 + 40 + t * 5 * NF * Q + 1 + extra
 
 
 def step_bytes_per_cell(lm, precision, viscous=True, recon=None):

@@ -7,11 +7,11 @@
 //
 // One thread per cell, all five conserved variables, so every operator value
 // is loaded once and used five times.  Every stream of loads (stencil
-// members, directional members, face points) is software-pipelined one
-// element ahead: while element i is accumulated, the index of element i+2
-// and the state and operator values of element i+1 are already in flight,
-// so a wave keeps two elements' worth of loads outstanding instead of
-// waiting a full memory round trip per stencil member.
+// members, directional members, face points) is software-pipelined: while
+// member i is accumulated, the state and operator values of the next DEPTH
+// members and the index of the one after are already in flight, so a wave
+// keeps several members' worth of loads outstanding instead of waiting a
+// full memory round trip per stencil member.
 
 // Buffer loads: the array's base and size sit in a resource descriptor in
 // scalar registers, a row offset (wave-uniform) in a scalar register and the
@@ -798,13 +798,15 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 // GATE: right after the central coefficients (which it needs anyway) each
 // cell forms its features and the wave evaluates the network for its 64
 // cells on the matrix cores, its weights read from the packed image (or it
-// reads the mask).  Cells taken as smooth keep
-// the linear central polynomial; the others run the directional stencils,
-// indicators and weights in their own lanes.  (Moving the troubled cells to
-// a separate pass, a wave or a quad of lanes per cell, was measured slower:
-// an isolated troubled cell then reads a cache line per operator value,
-// while here its central and face data stream with its neighbours'.)  The
-// FP32 P2 variant is held to 3 waves per SIMD, which its LDS already imposes.
+// reads the mask).  Cells taken as smooth keep the linear central
+// polynomial; the wave then finishes its troubled cells in this pass, by the
+// whole wave one cell at a time (a few), one lane per (cell, stencil) (up to
+// kStencilLanesMax, FP32 P2), or one lane per cell.  (Moving the troubled
+// cells to a separate pass, a wave or a quad of lanes per cell, was measured
+// slower: an isolated troubled cell then reads a cache line per operator
+// value, while here its central and face data stream with its neighbours'.)
+// The FP32 P2 variant is held to 3 waves per SIMD, which its LDS already
+// imposes.
 //
 // A cell whose point states violate positivity is marked with bit 7 of its
 // flag for the fallback pass.
@@ -844,8 +846,8 @@ void reconstruct_kernel(ReconArgs<T> A) {
             central_coeffs<T, K>(A, c, ui, a);
             mode = A.gate[c] ? 0 : 1;
         }
-        // troubled cells: with the whole wave one at a time when the wave has
-        // few, else each in its own lane
+        // troubled cells: the whole wave per cell when the wave has few, one
+        // lane per (cell, stencil) when it has more, else one lane per cell
         const int nd = valid && mode == 1 ? int(A.ndir[c]) : 0;
         const uint64_t todo = __builtin_amdgcn_ballot_w64(nd > 0);
         const int nt = __builtin_popcountll(todo);

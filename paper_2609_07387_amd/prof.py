@@ -25,14 +25,40 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_KERNEL = "copyBuffer"
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space, so that a record stays
+    valid across edits that change no code.  String and character literals
+    are kept whole."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        ch = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif ch in "\"'":
+            j = i + 1
+            while j < n and text[j] != ch:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(ch)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_digest() -> str:
-    """sha256 over the device and host sources of libucns."""
+    """sha256 over the code (comments and spacing removed) of the device and
+    host sources of libucns."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
         if p.endswith((".hip", ".hpp", ".cpp", ".h")):
-            with open(p, "rb") as f:
+            with open(p, encoding="utf-8") as f:
                 h.update(os.path.basename(p).encode())
-                h.update(f.read())
+                h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
