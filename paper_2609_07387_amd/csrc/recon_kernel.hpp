@@ -163,7 +163,7 @@ __device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, 
     for (int lf = 0; lf < kMaxFaces; ++lf)
 #pragma unroll
         for (int t = 0; t < 2; ++t)
-            un[lf][t] = jn[lf] >= 0 ? bld<double>(rU, uint32_t(jn[lf]) * 8u, uint32_t(t ? 4 : 0) * rowU) : 0.0;
+            un[lf][t] = bld<double>(rU, uint32_t(jn[lf] >= 0 ? jn[lf] : 0) * 8u, uint32_t(t ? 4 : 0) * rowU);
     int cnt = 0;
 #pragma unroll
     for (int lf = 0; lf < kMaxFaces; ++lf) {

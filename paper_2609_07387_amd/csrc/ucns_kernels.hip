@@ -264,26 +264,47 @@ __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<
     prim_W(P, ui, Wi);
 #pragma unroll
     for (int k = 0; k < 12; ++k) g[k] = T(0);
-    for (int lf = 0; lf < A.NF; ++lf) {
-        const int32_t f2 = A.c2f[int64_t(lf) * nc + c];
-        if (f2 < 0) continue;
-        const int64_t f = f2 >> 1;
-        const int side = f2 & 1;
-        const int32_t other = A.fcell[2 * f + (1 - side)];
-        T uo[5], Wo[4];
-        if (other >= 0) {
+    // faces in groups of G: the group's ids, then its geometry and
+    // neighbours, then the neighbours' states (three memory waits per group
+    // instead of three per face; FP64 takes two groups to stay at 3 waves)
+    constexpr int G = sizeof(T) == 4 ? kMaxFaces : kMaxFaces / 2;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) uo[v] = T(A.U[v * nc + other]);
-        } else {
-            ghost(B, -1 - other, ui, ui, uo);
+    for (int g0 = 0; g0 < kMaxFaces; g0 += G) {
+        int32_t f2[G], other[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) f2[i] = g0 + i < A.NF ? A.c2f[int64_t(g0 + i) * nc + c] : -1;
+        // absent slots read face 0 and boundary sides cell 0, and are
+        // skipped or replaced below: every load is unconditional (a load
+        // under a lane condition would be a branch that waits for it)
+        T sa[G], nr[G][3];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int64_t f = f2[i] >= 0 ? f2[i] >> 1 : 0;
+            const int side = f2[i] & 1;
+            other[i] = A.fcell[2 * f + (1 - side)];
+            sa[i] = (side ? T(-0.5) : T(0.5)) * A.farea[f];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nr[i][a] = A.fnrm[3 * f + a];
         }
-        prim_W(P, uo, Wo);
-        const T s = (side ? T(-0.5) : T(0.5)) * A.farea[f];
+        T uo[G][5];
 #pragma unroll
-        for (int var = 0; var < 4; ++var) {
-            const T wf = (Wi[var] + Wo[var]) * s;
+        for (int i = 0; i < G; ++i) {
+            const int64_t j = other[i] >= 0 ? other[i] : 0;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) g[3 * var + a] += wf * A.fnrm[3 * f + a];
+            for (int v = 0; v < 5; ++v) uo[i][v] = T(A.U[v * nc + j]);
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (f2[i] < 0) continue;
+            if (other[i] < 0) ghost(B, -1 - other[i], ui, ui, uo[i]);
+            T Wo[4];
+            prim_W(P, uo[i], Wo);
+#pragma unroll
+            for (int var = 0; var < 4; ++var) {
+                const T wf = (Wi[var] + Wo[var]) * sa[i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) g[3 * var + a] += wf * nr[i][a];
+            }
         }
     }
     const T iv = T(1.0 / A.vol[c]);
@@ -374,17 +395,33 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         pen = T(4.0 / 3.0) / sqrt(dx * dx + dy * dy + dz * dz);
     }
     T F[5] = {T(0), T(0), T(0), T(0), T(0)};
+    // FP32 loads the next point's two states while it evaluates this one's
+    // flux (FP64 has no registers to spare: 158, three waves per SIMD)
+    constexpr bool kAhead = sizeof(T) == 4;
+    // (on a boundary face pR = pL and the ghost replaces uR)
+    auto load_point = [&](int q, T* uL, T* uR) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            uL[v] = pL[int64_t(q * 5 + v) * nc];
+            uR[v] = pR[int64_t(q * 5 + v) * nc];
+        }
+    };
+    T uLn[5], uRn[5];
+    if (kAhead && nq > 0) load_point(0, uLn, uRn);
 #pragma unroll 1  // unrolling doubles the live registers (FP64: 3 waves per SIMD instead of 2)
     for (int q = 0; q < nq; ++q) {
         T uL[5], uR[5], Fq[5];
+        if constexpr (kAhead) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) uL[v] = pL[int64_t(q * 5 + v) * nc];
-        if (cR >= 0) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) uR[v] = pR[int64_t(q * 5 + v) * nc];
+            for (int v = 0; v < 5; ++v) {
+                uL[v] = uLn[v];
+                uR[v] = uRn[v];
+            }
+            if (q + 1 < nq) load_point(q + 1, uLn, uRn);
         } else {
-            ghost(B, -1 - cR, uL, avg, uR);
+            load_point(q, uL, uR);
         }
+        if (cR < 0) ghost(B, -1 - cR, uL, avg, uR);
         const Prim<T> qL = prim(P, uL, n), qR = prim(P, uR, n);
         if (P.flux == UCNS_HLLC)
             hllc_flux(qL, qR, uL, uR, n, Fq);
@@ -439,6 +476,31 @@ __device__ double block_reduce(double x) {
     return sh[0];
 }
 
+// sum_f s_if F_f over the cell's faces in local order; all face ids first,
+// then all face fluxes (two memory waits instead of two per face).
+template <class T>
+__device__ __forceinline__ void face_sum(const ResArgs<T>& A, int64_t c, double acc[5]) {
+    int32_t f2[kMaxFaces];
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf) f2[lf] = lf < A.NF ? A.c2f[int64_t(lf) * A.nc + c] : -1;
+    // absent slots load face 0 and are skipped below (a load under a lane
+    // condition would be a branch that waits for it)
+    T fl[kMaxFaces][5];
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fl[lf][v] = A.ff[int64_t(f2[lf] >= 0 ? f2[lf] >> 1 : 0) * 5 + v];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf) {
+        if (f2[lf] < 0) continue;
+        const double s = (f2[lf] & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] += s * double(fl[lf][v]);
+    }
+}
+
 // Shu-Osher stage update a U0 + b (U + dt R), one explicit rounding order
 // for every kernel that applies it.
 __device__ __forceinline__ double rk_combine(double a, double b, double u0, double u, double dt, double r) {
@@ -466,15 +528,8 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(ResArgs<T> A) {
     if constexpr (FINAL) {
         double tdt = INFINITY, tke = 0.0;
         if (c < A.nc) {
-            double acc[5] = {0, 0, 0, 0, 0};
-            for (int lf = 0; lf < A.NF; ++lf) {
-                const int32_t f2 = A.c2f[int64_t(lf) * A.nc + c];
-                if (f2 < 0) continue;
-                const int64_t f = f2 >> 1;
-                const double s = (f2 & 1) ? -1.0 : 1.0;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) acc[v] += s * double(A.ff[f * 5 + v]);
-            }
+            double acc[5];
+            face_sum<T>(A, c, acc);
             const double vol = A.vol[c];
             const double iv = -1.0 / vol;
             const double dt = *A.dt;
@@ -497,15 +552,8 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(ResArgs<T> A) {
         return;
     }
     if (c >= A.nc) return;
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int lf = 0; lf < A.NF; ++lf) {
-        const int32_t f2 = A.c2f[int64_t(lf) * A.nc + c];
-        if (f2 < 0) continue;
-        const int64_t f = f2 >> 1;
-        const double s = (f2 & 1) ? -1.0 : 1.0;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) acc[v] += s * double(A.ff[f * 5 + v]);
-    }
+    double acc[5];
+    face_sum<T>(A, c, acc);
     const double iv = -1.0 / A.vol[c];
     if (RK) {
         const double dt = *A.dt;
