@@ -377,8 +377,13 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
     const T n[3] = {A.fnrm[3 * f], A.fnrm[3 * f + 1], A.fnrm[3 * f + 2]};
     const int32_t cL = A.fcell[2 * f], cR = A.fcell[2 * f + 1];
     // point states in the cell-fastest slots [lf][q][v][cell] of each side
-    const T* pL = A.fs + int64_t(A.flf[2 * f]) * Q * 5 * nc + cL;
-    const T* pR = cR >= 0 ? A.fs + int64_t(A.flf[2 * f + 1]) * Q * 5 * nc + cR : pL;
+    // both sides' local face indices in one 16-bit load (the right one is
+    // needed only off the boundary, and a load under that lane condition
+    // would wait)
+    const uint32_t lf2 = *reinterpret_cast<const uint16_t*>(A.flf + 2 * f);
+    const int lfL = int(lf2 & 0xffu), lfR = int(lf2 >> 8);
+    const T* pL = A.fs + int64_t(lfL) * Q * 5 * nc + cL;
+    const T* pR = cR >= 0 ? A.fs + int64_t(lfR) * Q * 5 * nc + cR : pL;
     T avg[5];
     if (cR < 0) {
 #pragma unroll
@@ -386,11 +391,11 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
     }
     T G0[12], pen = T(0);
     if (P.viscous) {
+        // a boundary face takes its own cell's gradient on both sides; both
+        // loads are unconditional (a load under a lane condition would wait)
+        const int64_t cRg = cR >= 0 ? cR : cL;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const T gl = A.gradW[k * nc + cL];
-            G0[k] = T(0.5) * (gl + (cR >= 0 ? A.gradW[k * nc + cR] : gl));
-        }
+        for (int k = 0; k < 12; ++k) G0[k] = T(0.5) * (A.gradW[k * nc + cL] + A.gradW[k * nc + cRg]);
         const T dx = A.fdc[3 * f], dy = A.fdc[3 * f + 1], dz = A.fdc[3 * f + 2];
         pen = T(4.0 / 3.0) / sqrt(dx * dx + dy * dy + dz * dz);
     }
