@@ -14,6 +14,7 @@ the FP64 CPU oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -136,11 +137,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=64, help="cells per side of the periodic hex cube")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("tgv_hex_p2", "tgv_tet_p3"), default="tgv_hex_p2",
+                    help="tgv_hex_p2: the headline (FP64 plain vs FP32 + gate); tgv_tet_p3: the 48^3 x 6 "
+                         "jittered-tet P3 Euler case, FP64 and FP32 throughput")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "tgv_tet_p3":
+        return main_tet_p3(args)
 
     import torch
 
@@ -213,6 +219,60 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def main_tet_p3(args, n=48):
+    """P3 on the tetrahedral TGV (n^3 lattice cubes, 6 jittered tets each,
+    1 % velocity noise), HLLC, Euler: FP64 and FP32 cell-stage updates/s and
+    the reconstruction call against its byte model.  No gate (the network is
+    trained at P2) and no CPU baseline (the oracle takes minutes per step
+    here)."""
+    import torch
+
+    from paper_2609_07387_amd import inputs, ucns
+
+    torch.cuda.set_device(0)
+    m = inputs.kuhn_tet_mesh((n, n, n), (2.0 * math.pi,) * 3, (True,) * 3, 0.15, seed=0)
+    U0 = inputs.tgv_initial(m, noise_seed=1000)
+    ph = ucns.phys(flux="hllc", viscous=False)
+    t0 = time.perf_counter()
+    lm = ucns.Mesh(m, order=3)
+    print(f"[bench] mesh build {time.perf_counter() - t0:.1f} s, {lm.n_cell} cells, {lm.n_face} faces", file=sys.stderr,
+          flush=True)
+    nc = lm.n_cell
+    variants = {}
+    for name, prec in (("fp64", ucns.F64), ("fp32", ucns.F32)):
+        solver = ucns.Solver(lm, ph, prec, cfl=0.5)
+        U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+        ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
+        rate = nc * 3 * args.steps / (ms / 1e3)
+        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 10, torch, ucns)
+        rbc = recon_bytes_per_cell(lm, prec)
+        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall, "recon_ms": rms,
+                          "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
+                          "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, viscous=False),
+                          "path_GBs": step_bytes_per_cell(lm, prec, viscous=False) * rate / 1e9}
+        print(f"[bench] {name}: {rate:.3e} cell-stage/s, {ms / args.steps:.3f} ms/step, recon {rms:.3f} ms",
+              file=sys.stderr, flush=True)
+        del solver
+    hv = variants["fp32"]
+    out = {
+        "metric": "cell-stage updates/s, P3 CWENOZ + HLLC on tets", "value": hv["value"],
+        "unit": "cell-stage updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"TGV {n}^3 x 6 jittered periodic tets (+1 % velocity noise), P3 CWENOZ, HLLC, "
+                               "Euler, SSP-RK3 CFL 0.5, per-step KE", "cells": nc, "faces": lm.n_face,
+                   "variant": "fp32 (FP32 reconstruction/flux, FP64 state/RK/reductions)"},
+        "variants": variants,
+        "fp64_value": variants["fp64"]["value"],
+        "speedup_vs_fp64": hv["value"] / variants["fp64"]["value"],
+        "roofline": {"kernel": "ucns_reconstruct call (FP32, K = 19)", "bound": "hbm", "achieved": hv["recon_GBs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hv["recon_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,
+                     "bytes_per_cell": hv["recon_bytes_per_cell"]},
+    }
     print(json.dumps(out), flush=True)
 
 
