@@ -115,10 +115,10 @@ def test_steps_fp64(torch_cuda, name, steps):
 
 
 def test_gate_mask_semantics(torch_cuda):
-    """mask all ones = linear central path; all zeros = full CWENOZ taken by
-    the wave-cooperative directional evaluation of the gated kernel (equal to
-    the ungated one-lane-per-cell launch up to summation order, bitwise
-    reproducible); both against the oracle."""
+    """mask all ones = linear central path; all zeros = full CWENOZ, each
+    troubled cell in its own lane as in the ungated kernel; a sparse mask
+    (a few troubled cells per wave) takes the whole-wave scheme; all against
+    the oracle, FP64."""
     m, order, ph, U, bcs = _setup("tet4_p2_hllc")
     lm = ucns.Mesh(m, order=order)
     om = oracle.OracleMesh(m, order=order)
@@ -151,6 +151,28 @@ def test_gate_mask_semantics(torch_cuda):
     a, b = fss[fl, sl, :lm.qmax], ofss[fo, sl, :lm.qmax]
     valid = ~np.isnan(b[..., 0])
     assert np.abs(a - b)[valid].max() / np.abs(b[valid]).max() < 1e-12
+
+
+@pytest.mark.parametrize("every", [1, 2, 4, 13, 47])
+def test_gate_schemes_fp32(torch_cuda, every):
+    """FP32 gated reconstruction with every `every`-th cell troubled, so that
+    waves hold 64, 32, 16, 5 or about 1 troubled cells and take the one-lane,
+    (cell, stencil)-lane and whole-wave schemes: decisions equal the oracle's,
+    point states within single-precision error of the FP64 oracle."""
+    m, order, ph, U, bcs = _setup("hex16_p2_rusanov")
+    lm = ucns.Mesh(m, order=order)
+    om = oracle.OracleMesh(m, order=order)
+    mask = np.ones(m.n_cell, np.uint8)
+    mask[::every] = 0
+    fs, _, _, R, fl = gpu_stage(lm, ph, U, ucns.F32, gate_mask=mask)
+    ofs, _, _, oR, ofl, _ = oracle_stage(om, as_oracle_phys(ph), U, None, mask)
+    assert np.array_equal(fl, ofl)
+    f_l, f_o, sl = face_maps(lm, om)
+    a, b = fs[f_l, sl, :lm.qmax], ofs[f_o, sl, :lm.qmax]
+    valid = ~np.isnan(b[..., 0])
+    err = np.abs(a - b)[valid].max() / np.abs(b[valid]).max()
+    print(f"[gpu] fp32 gate every {every}: point-state err {err:.2e}, R err {grouped_rel_linf(R, oR):.2e}", flush=True)
+    assert err < 1e-6
 
 
 def test_determinism_bitwise(torch_cuda):

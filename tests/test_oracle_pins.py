@@ -367,6 +367,132 @@ def test_steady_contact_hllc_vs_rusanov():
     assert np.abs(Ur[0] - U0[0]).max() > 1e-2
 
 
+# ------------------------------------------------------------------ Pi 10
+
+
+def exact_riemann(WL, WR, xi, gamma=1.4):
+    """Exact solution of the 1-D Euler Riemann problem at similarity
+    coordinates xi = x/t (the textbook construction: star pressure from the
+    two wave curves by Newton's method, then sampling the fan).  W = (rho, u,
+    p); returns arrays rho, u, p."""
+    rL, uL, pL = WL
+    rR, uR, pR = WR
+    cL, cR = math.sqrt(gamma * pL / rL), math.sqrt(gamma * pR / rR)
+    g1, g2 = (gamma - 1) / (2 * gamma), (gamma + 1) / (2 * gamma)
+
+    def wave(p, rk, pk, ck):
+        # f_K(p) and its derivative: shock branch for p > p_K, rarefaction otherwise
+        if p > pk:
+            A, B = 2 / ((gamma + 1) * rk), (gamma - 1) / (gamma + 1) * pk
+            q = math.sqrt(A / (p + B))
+            return (p - pk) * q, q * (1 - 0.5 * (p - pk) / (p + B))
+        f = 2 * ck / (gamma - 1) * ((p / pk) ** g1 - 1)
+        return f, (p / pk) ** (-g2) / (rk * ck)
+
+    p = max(1e-8, 0.5 * (pL + pR))
+    for _ in range(100):
+        fL, dL = wave(p, rL, pL, cL)
+        fR, dR = wave(p, rR, pR, cR)
+        dp = (fL + fR + uR - uL) / (dL + dR)
+        p = max(1e-12, p - dp)
+        if abs(dp) < 1e-15 * p:
+            break
+    fL, _ = wave(p, rL, pL, cL)
+    fR, _ = wave(p, rR, pR, cR)
+    us = 0.5 * (uL + uR) + 0.5 * (fR - fL)
+    out = np.zeros((3, len(xi)))
+    for i, s in enumerate(xi):
+        if s <= us:  # left of the contact
+            if p > pL:
+                SL = uL - cL * math.sqrt(g2 * p / pL + g1)
+                w = (rL, uL, pL) if s <= SL else (rL * ((p / pL + (gamma - 1) / (gamma + 1)) /
+                                                        ((gamma - 1) / (gamma + 1) * p / pL + 1)), us, p)
+            else:
+                csL = cL * (p / pL) ** g1
+                if s <= uL - cL:
+                    w = (rL, uL, pL)
+                elif s >= us - csL:
+                    w = (rL * (p / pL) ** (1 / gamma), us, p)
+                else:  # inside the left fan
+                    c = 2 / (gamma + 1) * (cL + (gamma - 1) / 2 * (uL - s))
+                    w = (rL * (c / cL) ** (2 / (gamma - 1)), 2 / (gamma + 1) * (cL + (gamma - 1) / 2 * uL + s),
+                         pL * (c / cL) ** (2 * gamma / (gamma - 1)))
+        else:
+            if p > pR:
+                SR = uR + cR * math.sqrt(g2 * p / pR + g1)
+                w = (rR, uR, pR) if s >= SR else (rR * ((p / pR + (gamma - 1) / (gamma + 1)) /
+                                                        ((gamma - 1) / (gamma + 1) * p / pR + 1)), us, p)
+            else:
+                csR = cR * (p / pR) ** g1
+                if s >= uR + cR:
+                    w = (rR, uR, pR)
+                elif s <= us + csR:
+                    w = (rR * (p / pR) ** (1 / gamma), us, p)
+                else:  # inside the right fan
+                    c = 2 / (gamma + 1) * (cR - (gamma - 1) / 2 * (uR - s))
+                    w = (rR * (c / cR) ** (2 / (gamma - 1)), 2 / (gamma + 1) * (-cR + (gamma - 1) / 2 * uR + s),
+                         pR * (c / cR) ** (2 * gamma / (gamma - 1)))
+        out[:, i] = w
+    return out[0], out[1], out[2]
+
+
+def test_exact_riemann_solver_sod_values():
+    """The textbook values of Sod's problem (star pressure 0.30313, star
+    velocity 0.92745, densities 0.42632 and 0.26557 either side of the
+    contact) and conservation across the shock (Rankine-Hugoniot)."""
+    xi = np.array([0.5, 1.2, 1.8])  # left of contact (in star), right of contact, right of shock
+    r, u, p = exact_riemann((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), xi)
+    assert abs(p[0] - 0.30313) < 5e-5 and abs(u[0] - 0.92745) < 5e-5
+    assert abs(r[0] - 0.42632) < 5e-5 and abs(r[1] - 0.26557) < 5e-5
+    assert r[2] == 0.125 and p[2] == 0.1
+    # the shock speed from mass balance, then momentum balance across it
+    S = (r[1] * u[1] - r[2] * u[2]) / (r[1] - r[2])
+    mom = (r[1] * u[1] ** 2 + p[1] - S * r[1] * u[1]) - (r[2] * u[2] ** 2 + p[2] - S * r[2] * u[2])
+    assert abs(mom) < 1e-6
+
+
+def _sod_errors(nx, t_end=0.2):
+    m = inputs.hex_box_mesh((nx, 3, 3), (1.0, 3.0 / nx, 3.0 / nx), (False, True, True))
+    om = oracle.OracleMesh(m, order=2)
+    vol, cen, _ = om.cell_data()
+    left = cen[:, 0] < 0.5
+    U0 = np.zeros((5, m.n_cell))
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    U0[0] = rho
+    U0[4] = p / 0.4
+    ph = oracle.phys(flux="hllc", mach=1.0)
+    bcs = oracle.bc({1: (2, None), 2: (2, None)})  # transmissive ends
+    nsteps = int(math.ceil(t_end / om.dt(U0, ph, 0.4)))
+    dt = t_end / nsteps
+    U = U0.copy()
+    for _ in range(nsteps):
+        Un = U.copy()
+        for st in range(3):
+            R = om.rhs(U, ph, bcs)
+            om.rk_stage(st, dt, Un, R, U)
+    r_ex, u_ex, p_ex = exact_riemann((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), (cen[:, 0] - 0.5) / t_end)
+    return U, vol, cen, float(np.sum(vol * np.abs(U[0] - r_ex)) / vol.sum())
+
+
+def test_sod_tube_reduces_to_1d_and_converges():
+    """x-only data on a hex slab (3 x 3 cells across, periodic) is a 1-D
+    problem: every cell of an x-column holds the same state, the transverse
+    momenta stay at rounding level, and the density converges to the exact
+    Riemann solution in L1 (first order at the discontinuities)."""
+    errs = []
+    for nx in (50, 100, 200):
+        U, vol, cen, e = _sod_errors(nx)
+        errs.append(e)
+        col = np.round(cen[:, 0] * nx * 2).astype(int)
+        for v in range(5):
+            spread = max(np.ptp(U[v][col == k]) for k in np.unique(col))
+            assert spread <= 1e-12 * max(1.0, np.abs(U[v]).max())
+        assert np.abs(U[2:4]).max() <= 1e-12
+    assert errs[1] < 0.75 * errs[0] and errs[2] < 0.75 * errs[1], errs
+    assert errs[2] < 0.01
+
+
 # ------------------------------------------------------------------ Pi 9
 
 
