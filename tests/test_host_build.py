@@ -108,3 +108,22 @@ def test_host_build_errors():
     assert "-2" in str(e.value)
     with pytest.raises(ucns.UcnsError):
         ucns.Mesh(m, order=5)
+
+
+def test_entry_points_reject_null_arguments():
+    """Argument checks run on the host before any device work, so they hold
+    without a GPU: a missing buffer is UCNS_EINVAL (-1), never a launch."""
+    import ctypes as C
+
+    _lib_or_skip()
+    L = ucns.lib()
+    lm = ucns.Mesh(inputs.periodic_hex_mesh(4))
+    ph = ucns.phys(flux="hllc")
+    rcs = [
+        L.ucns_residual_rk_final(lm.h, C.byref(ph), None, ucns.F64, None, None, None, 0.5, None, None, None, None),
+        L.ucns_residual_rk_stage(lm.h, None, ucns.F64, 0, None, None, None, None),
+        L.ucns_reconstruct(lm.h, C.byref(ph), None, ucns.F64, None, None, None, None, None),
+        L.ucns_dt(lm.h, C.byref(ph), None, 0.5, None, None, None),
+        L.ucns_mlp_pack(None, None, None),
+    ]
+    assert rcs == [-1] * len(rcs), rcs
