@@ -735,6 +735,32 @@ static int build_operators(oracle_mesh* m, int64_t c, oracle_stencil_t* st, orac
         }
         double* B = s < 0 ? op->Bc : op->Bd[s];
         int rcq = or_lsq_operator(ns, kk, A, w, B, &rc);
+        /* A directional stencil whose members cannot fix a linear
+         * polynomial (all in one plane through the cell centroid, as on thin
+         * boundary-layer cells: a column of A vanishes up to rounding, which
+         * the unit-norm column scaling of the solve would hide) is dropped
+         * like one with too few candidates; the later stencils (and their
+         * operator blocks) move down one slot. */
+        double cmin = INFINITY, cmax = 0;
+        if (s >= 0)
+            for (int k = 0; k < kk; ++k) {
+                double cn = 0;
+                for (int j = 0; j < ns; ++j) cn += A[j * kk + k] * A[j * kk + k];
+                cmin = fmin(cmin, sqrt(cn));
+                cmax = fmax(cmax, sqrt(cn));
+            }
+        if (s >= 0 && (rcq != 0 || rc < 1e-9 || cmin < 1e-8 * cmax)) {
+            for (int t = s; t + 1 < st->ndir; ++t) {
+                st->nd[t] = st->nd[t + 1];
+                st->dface[t] = st->dface[t + 1];
+                memcpy(st->dir[t], st->dir[t + 1], sizeof(st->dir[t]));
+                op->Bd[t] = op->Bd[t + 1];
+            }
+            st->ndir--;
+            st->ndropped++;
+            if (s < st->ndir) goto retry;
+            break;
+        }
         if (s < 0 && (rcq != 0 || rc < 1e-9)) {
             if (st->ncen >= st->navail)
                 return or_fail(-3, "cell %lld: central stencil rank deficient (rcond %g)", (long long)c, rc);

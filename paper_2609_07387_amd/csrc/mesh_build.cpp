@@ -718,19 +718,42 @@ int build_operators(Mesh& m, int nt) {
                 std::lock_guard<std::mutex> g(over_mu);
                 Bc_over[c].assign(B, B + size_t(K) * n);
             }
-            // directional stencils (linear basis)
-            for (int s = 0; s < m.ndir[c]; ++s) {
+            // directional stencils (linear basis); one whose members cannot
+            // fix a linear polynomial (all in one plane through the centroid,
+            // as on thin boundary-layer cells: a column of A vanishes up to
+            // rounding, which the solve's unit-norm column scaling would
+            // hide) is dropped like a sector with too few candidates, the
+            // later ones moving down a slot
+            for (int s = 0; s < m.ndir[c];) {
                 int nd = m.nds[c * kMaxFaces + s];
-                const int64_t* ids = &m.dir[(size_t(c) * kMaxFaces + s) * kMaxDir];
+                int64_t* ids = &m.dir[(size_t(c) * kMaxFaces + s) * kMaxDir];
                 for (int j = 0; j < nd; ++j) {
                     row(ids[j], 3, A + j * 3);
                     w[j] = m.vol[ids[j]];
                 }
+                double cmin = INFINITY, cmax = 0;
+                for (int k = 0; k < 3; ++k) {
+                    double cn = 0;
+                    for (int j = 0; j < nd; ++j) cn += A[j * 3 + k] * A[j * 3 + k];
+                    cmin = std::min(cmin, std::sqrt(cn));
+                    cmax = std::max(cmax, std::sqrt(cn));
+                }
                 double rc;
-                if (!lsq_pinv(nd, 3, A, w, B, &rc)) std::fill(B, B + 3 * nd, 0.0);
+                if (!lsq_pinv(nd, 3, A, w, B, &rc) || rc < 1e-9 || cmin < 1e-8 * cmax) {
+                    for (int t = s; t + 1 < m.ndir[c]; ++t) {
+                        m.nds[c * kMaxFaces + t] = m.nds[c * kMaxFaces + t + 1];
+                        m.dface[c * kMaxFaces + t] = m.dface[c * kMaxFaces + t + 1];
+                        std::copy_n(&m.dir[(size_t(c) * kMaxFaces + t + 1) * kMaxDir], kMaxDir,
+                                    &m.dir[(size_t(c) * kMaxFaces + t) * kMaxDir]);
+                    }
+                    m.ndir[c]--;
+                    m.ndropped[c]++;
+                    continue;
+                }
                 for (int k = 0; k < 3; ++k)
                     for (int j = 0; j < nd; ++j)
                         m.Bd[((size_t(c) * m.nd_max + s) * 3 + k) * m.md_pad + j] = B[k * nd + j];
+                ++s;
             }
             // smoothness-indicator matrix:
             // O_kl = sum_{1<=|b|<=r} V^{2|b|/3-1} int D^b phi_k D^b phi_l dV

@@ -208,6 +208,158 @@ def kuhn_tet_mesh(n, lengths, periodic=(True, True, True), jitter: float = 0.15,
     return mesh
 
 
+# Local faces of a lattice hex (VTK vertex order) and, for splitting a face
+# into two triangles, the face's lowest and highest lattice corner: the Kuhn
+# split and the prism split below both cut every face along that diagonal,
+# so any two of them meet conformingly.
+_CUBE_FACES = ((0, 3, 7, 4), (1, 2, 6, 5), (0, 1, 5, 4), (3, 2, 6, 7), (0, 1, 2, 3), (4, 5, 6, 7))
+
+
+def _face_triangles(f):
+    """Two triangles of a lattice hex face (local ids), cut along the
+    diagonal from its lowest to its highest corner."""
+    score = [sum(_HEX_OFF[v]) for v in f]
+    lo, hi = f[int(np.argmin(score))], f[int(np.argmax(score))]
+    a, b = [v for v in f if v not in (lo, hi)]
+    return (lo, a, hi), (lo, hi, b)
+
+
+def mixed_bl_mesh(n=(650, 36, 128), lengths=(4.0, 1.0, 0.5), hex_cols=(130, 130), prism_layers=20, growth=1.2,
+                  first_layer=1e-3, bump=0.05) -> Mesh:
+    """Mixed-element boundary-layer box (x streamwise, y wall-normal, z
+    spanwise and periodic) on an n[0] x n[1] x n[2] lattice of cubes.
+
+    * x columns [0, hex_cols[0]) and [n0 - hex_cols[1], n0): hexahedra;
+    * the columns between: `prism_layers` layers of prisms next to the wall
+      (each cube cut into two along its x-z diagonal, triangles parallel to
+      the wall), Kuhn tetrahedra above them, and in the two columns that
+      touch the hexahedra a pyramid on the shared face plus ten tetrahedra
+      around a vertex at the cube centre (the transition).
+    Wall-normal spacing grows geometrically (first_layer, growth) through the
+    prism layers and is uniform above; the wall carries a bump of height
+    `bump` at x = L/4, faded out linearly to the top.  Boundary tags: 1 inflow
+    (x = 0), 2 outflow (x = Lx), 3 wall (y = 0), 4 far field (y = Ly)."""
+    n = tuple(int(a) for a in n)
+    nx, ny, nz = n
+    Lx, Ly, Lz = lengths
+    i1, i2 = hex_cols[0], nx - hex_cols[1]
+    jp = int(prism_layers)
+    assert i1 >= 1 and i2 <= nx - 1 and i2 - i1 >= 3 and 0 <= jp < ny
+    # lattice coordinates
+    yl = first_layer * (growth ** np.arange(jp + 1) - 1.0) / (growth - 1.0) if growth != 1.0 else \
+        first_layer * np.arange(jp + 1)
+    assert yl[-1] < Ly
+    y = np.concatenate([yl, yl[-1] + (Ly - yl[-1]) * np.arange(1, ny - jp + 1) / (ny - jp)])
+    xs = np.arange(nx + 1) * (Lx / nx)
+    zs = np.arange(nz) * (Lz / nz)
+    X, Y, Z = np.meshgrid(xs, y, zs, indexing="ij")  # [nx+1, ny+1, nz]
+    Y = Y + bump * np.exp(-25.0 * (X - 0.25 * Lx) ** 2) * (1.0 - Y / Ly)
+    nvx, nvy = nx + 1, ny + 1
+
+    def vid(i, j, k):
+        return i + nvx * (j + nvy * (k % nz))
+
+    xyz = np.stack([X.transpose(2, 1, 0).ravel(), Y.transpose(2, 1, 0).ravel(), Z.transpose(2, 1, 0).ravel()], 1)
+    # cube vertex ids [nx, ny, nz, 8]
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    cube = np.stack([vid(ii + o[0], jj + o[1], kk + o[2]) for o in _HEX_OFF], axis=-1).astype(np.int64)
+    hexzone = (ii < i1) | (ii >= i2)
+    prismzone = ~hexzone & (jj < jp)
+    trans = ~hexzone & (jj >= jp) & ((ii == i1) | (ii == i2 - 1))
+    tetzone = ~hexzone & (jj >= jp) & ~trans
+    cells, types = [], []
+    # hexahedra
+    cells.append(cube[hexzone].reshape(-1, 8))
+    types.append(np.full(cells[-1].shape[0], HEX, np.uint8))
+    # prisms: bottom triangles (0, 4, 5) and (0, 5, 1) of the y = 0 face, tops 3 above 0, 7 above 4, ...
+    pc = cube[prismzone].reshape(-1, 8)
+    for tri in ((0, 5, 1), (0, 4, 5)):
+        top = tuple({0: 3, 1: 2, 4: 7, 5: 6}[v] for v in tri)
+        cells.append(pc[:, list(tri) + list(top)])
+        types.append(np.full(pc.shape[0], PRISM, np.uint8))
+    # Kuhn tetrahedra
+    tc = cube[tetzone].reshape(-1, 8)
+    for t in _KUHN:
+        cells.append(tc[:, list(t)])
+        types.append(np.full(tc.shape[0], TET, np.uint8))
+    # transition cubes: a centre vertex, a pyramid on the face toward the hexahedra
+    tr_idx = np.argwhere(trans)
+    base_v = xyz.shape[0]
+    for c, (i, j, k) in enumerate(tr_idx):
+        v = cube[i, j, k]
+        C = base_v + c
+        hex_face = 0 if i == i1 else 1  # x-min face toward the upstream hexahedra, x-max toward downstream
+        for fi, f in enumerate(_CUBE_FACES):
+            if fi == hex_face:
+                cells.append(np.array([[v[f[0]], v[f[1]], v[f[2]], v[f[3]], C]], np.int64))
+                types.append(np.array([PYR], np.uint8))
+            else:
+                for tri in _face_triangles(f):
+                    cells.append(np.array([[v[tri[0]], v[tri[1]], v[tri[2]], C]], np.int64))
+                    types.append(np.array([TET], np.uint8))
+    # centre coordinates (the last z layer wraps: average the unwrapped vertices)
+    cen = np.zeros((len(tr_idx), 3))
+    for c, (i, j, k) in enumerate(tr_idx):
+        pts = xyz[cube[i, j, k]].copy()
+        if k == nz - 1:
+            pts[[4, 5, 6, 7], 2] += Lz
+        cen[c] = pts.mean(0)
+    xyz = np.concatenate([xyz, cen])
+    # flatten; fix orientations from the geometry (unwrapped across the period)
+    nper = {TET: 4, PYR: 5, PRISM: 6, HEX: 8}
+    ctype = np.concatenate(types)
+    ptr = np.concatenate([[0], np.cumsum([nper[int(t)] for t in ctype])]).astype(np.int64)
+    vtx = np.concatenate([c.ravel() for c in cells]).astype(np.int64)
+    mesh = Mesh(xyz=xyz, ctype=ctype, cell_ptr=ptr, cell_vtx=vtx, period=np.array([0.0, 0.0, Lz]),
+                name=f"mixed{nx}x{ny}x{nz}")
+    _orient_simplex_like(mesh)
+    # boundary faces
+    bf, tags = [], []
+    for j in range(ny):
+        for k in range(nz):
+            bf.append([vid(0, j, k), vid(0, j + 1, k), vid(0, j + 1, k + 1), vid(0, j, k + 1)])
+            tags.append(1)
+            bf.append([vid(nx, j, k), vid(nx, j + 1, k), vid(nx, j + 1, k + 1), vid(nx, j, k + 1)])
+            tags.append(2)
+    for jface, tag in ((0, 3), (ny, 4)):
+        jc = 0 if jface == 0 else ny - 1
+        fl = _CUBE_FACES[2] if jface == 0 else _CUBE_FACES[3]
+        for i in range(nx):
+            for k in range(nz):
+                v = cube[i, jc, k]
+                if i < i1 or i >= i2:
+                    bf.append([v[a] for a in fl])
+                    tags.append(tag)
+                else:
+                    for tri in _face_triangles(fl):
+                        bf.append([v[a] for a in tri])
+                        tags.append(tag)
+    mesh.bface_ptr = np.concatenate([[0], np.cumsum([len(f) for f in bf])]).astype(np.int64)
+    mesh.bface_vtx = np.array([v for f in bf for v in f], np.int64)
+    mesh.bface_tag = np.array(tags, np.int32)
+    return mesh
+
+
+def _orient_simplex_like(mesh: Mesh):
+    """Put tetrahedra, pyramids and prisms in the orientation the face tables
+    assume (right-handed: a tet's vertex 3, a pyramid's apex and a prism's top
+    on the positive side of the first three vertices), from the unwrapped
+    coordinates."""
+    P = mesh.cell_vertex_coords()
+    t = mesh.ctype
+    a, b, c, d = P[:, 0], P[:, 1], P[:, 2], P[:, 3]
+    apex = np.where((t == PYR)[:, None], P[:, 4], np.where((t == PRISM)[:, None], P[:, 3:6].mean(1), d))
+    side = np.einsum("ij,ij->i", np.cross(b - a, c - a), apex - a)
+    flip = (side < 0) & (t != HEX)
+    vtx = mesh.cell_vtx
+    for ty, swaps in ((TET, [(2, 3)]), (PYR, [(1, 3)]), (PRISM, [(1, 2), (4, 5)])):
+        rows = np.nonzero(flip & (t == ty))[0]
+        for r in rows:
+            o = mesh.cell_ptr[r]
+            for x, y in swaps:
+                vtx[o + x], vtx[o + y] = vtx[o + y], vtx[o + x]
+
+
 def _add_box_boundaries(mesh: Mesh, n, periodic, vid, hexes: bool):
     """Boundary faces on non-periodic box planes: tag 2*axis+1 (min), 2*axis+2 (max)."""
     faces, tags = [], []
@@ -366,6 +518,24 @@ def uniform_state(mesh: Mesh, rho, vel, p, gamma=1.4):
     U[0] = rho
     U[1:4] = rho * np.asarray(vel, np.float64)[:, None]
     U[4] = E
+    return U
+
+
+def bl_initial(mesh: Mesh, mach=0.5, gamma=1.4, amp=0.05):
+    """Free stream along x (rho = 1, u = 1, p = 1 / (gamma M^2)) with a smooth
+    density bump amp * sin(pi x / Lx) sin(2 pi z / Lz) at constant pressure,
+    from vertex-average cell centres (initial data, not a cell average)."""
+    P = mesh.cell_vertex_coords()
+    nv = np.diff(mesh.cell_ptr)
+    c = P.sum(1) / nv[:, None]
+    Lx = float(mesh.xyz[:, 0].max())
+    Lz = float(mesh.period[2]) if mesh.period[2] > 0 else float(mesh.xyz[:, 2].max())
+    rho = 1.0 + amp * np.sin(math.pi * c[:, 0] / Lx) * np.sin(2.0 * math.pi * c[:, 2] / Lz)
+    p = 1.0 / (gamma * mach * mach)
+    U = np.zeros((5, mesh.n_cell))
+    U[0] = rho
+    U[1] = rho
+    U[4] = p / (gamma - 1.0) + 0.5 * rho
     return U
 
 

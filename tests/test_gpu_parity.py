@@ -18,6 +18,11 @@ pytestmark = pytest.mark.gpu
 # differences are a few hundred ulps of the largest value of each group.
 TOL_STAGE = 1e-12
 TOL_STEPS = 1e-12   # relative L-inf after the stated steps
+# The mixed boundary-layer mesh has least-squares stencils with condition
+# numbers near 1e9 (thin prism layers under tetrahedra): the library's and the
+# oracle's operators, both correct, agree to about 1e-7 there (host-build
+# test), and so do the states built from them.
+TOL_CASE = {"mixed_bl_ns": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -40,6 +45,9 @@ CASES = {
                      dict(flux="hllc"), "tgv_noise", None),
     "tet_shock_box": (lambda: inputs.kuhn_tet_mesh((12, 3, 3), (4.0, 1.0, 1.0), (False, True, True), 0.15, seed=6),
                       2, dict(flux="hllc", mach=1.0), "shock", "shock"),
+    # hexahedra, prisms, pyramids and tetrahedra; inflow, outflow, no-slip wall and far field
+    "mixed_bl_ns": (lambda: inputs.mixed_bl_mesh((9, 5, 6), (2.25, 1.0, 0.75), (2, 2), 2, 1.2, 0.15, 0.05), 2,
+                    dict(flux="hllc", viscous=True, mach=0.5, reynolds=1000.0), "bl", "bl"),
 }
 
 
@@ -51,6 +59,8 @@ def _setup(name):
         U = inputs.tgv_initial(m)
     elif u0 == "tgv_noise":
         U = inputs.tgv_initial(m, noise_seed=1000)
+    elif u0 == "bl":
+        U = inputs.bl_initial(m, mach=pk["mach"])
     else:
         U = inputs.shock_box_initial(m)
     bcs = None
@@ -58,6 +68,10 @@ def _setup(name):
         rho2, u2, p2 = inputs.normal_shock_states(3.0)
         inflow = [rho2, rho2 * u2, 0, 0, p2 / 0.4 + 0.5 * rho2 * u2 * u2]
         bcs = ucns.bc({1: (ucns.BC_DIRICHLET, inflow), 2: (ucns.BC_TRANSMISSIVE, None)})
+    elif bcname == "bl":
+        free = inputs.bl_initial(m, mach=pk["mach"], amp=0.0)[:, 0]
+        bcs = ucns.bc({1: (ucns.BC_DIRICHLET, free), 2: (ucns.BC_TRANSMISSIVE, None), 3: (ucns.BC_WALL, None),
+                       4: (ucns.BC_DIRICHLET, free)})
     return m, order, ph, U, bcs
 
 
@@ -78,26 +92,27 @@ def test_stage_intermediates_fp64(torch_cuda, name):
     au = np.abs(U).max(axis=1)
     scale = np.array([au[0], au[1:4].max(), au[1:4].max(), au[1:4].max(), au[4]])
     err_fs = (np.abs(a - b)[valid] / scale[None, :]).max()
-    assert err_fs < TOL_STAGE, err_fs
+    tol = TOL_CASE.get(name, TOL_STAGE)
+    assert err_fs < tol, err_fs
     assert np.array_equal(flags, oflags)
     if ph.viscous:
         err_g = np.abs(gw - og).max() / np.abs(og).max()
-        assert err_g < TOL_STAGE, err_g
+        assert err_g < tol, err_g
     # flux per face: align by the owner-side maps
     own = sl == 0
     err_ff = np.abs(ff[fl[own]] - off[fo[own]]).max() / np.abs(off).max()
-    assert err_ff < TOL_STAGE, err_ff
+    assert err_ff < tol, err_ff
     # R is a near-cancelling sum of face fluxes (for the TGV, div(rho u) ~ 0):
     # measure its error against the size of the summed fluxes, max |F| n_f / |V|
     vol = om.cell_data()[0]
     rscale = np.abs(off).max(axis=0) * lm.nfmax / vol.min()
     err_R = (np.abs(R - oR).max(axis=1) / rscale).max()
     print(f"[gpu]   fs {err_fs:.2e} ff {err_ff:.2e} R {err_R:.2e}", flush=True)
-    assert err_R < 1e-13, err_R
+    assert err_R < (tol / 10 if name in TOL_CASE else 1e-13), err_R
 
 
 @pytest.mark.parametrize("name,steps", [("hex16_p2_rusanov", 10), ("hex7_p2_hllc_ns", 10), ("tet4_p2_hllc", 5),
-                                        ("tet3_p3_hllc", 3), ("tet_shock_box", 5)])
+                                        ("tet3_p3_hllc", 3), ("tet_shock_box", 5), ("mixed_bl_ns", 5)])
 def test_steps_fp64(torch_cuda, name, steps):
     """SSP-RK3 steps at CFL 0.5: relative L-inf <= 1e-12 against the oracle
     (the 16^3 hex Rusanov case is the paper-scale TGV parity workload)."""
@@ -109,9 +124,10 @@ def test_steps_fp64(torch_cuda, name, steps):
     Uo, ke_o, dt_o = om.run(U, as_oracle_phys(ph), 0.5, steps, as_oracle_bc(bcs))
     err = grouped_rel_linf(Ug, Uo)
     print(f"[gpu]   rel Linf {err:.3e}, dt rel {np.abs(dt_g / dt_o - 1).max():.1e}", flush=True)
-    assert np.allclose(dt_g, dt_o, rtol=1e-14)
-    assert np.allclose(ke_g, ke_o, rtol=1e-12)
-    assert err < TOL_STEPS, err
+    tol = TOL_CASE.get(name, TOL_STEPS)
+    assert np.allclose(dt_g, dt_o, rtol=max(1e-14, tol / 100))
+    assert np.allclose(ke_g, ke_o, rtol=max(1e-12, tol))
+    assert err < tol, err
 
 
 def test_gate_mask_semantics(torch_cuda):

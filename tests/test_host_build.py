@@ -37,7 +37,16 @@ def _meshes():
         "tet3p3": (inputs.kuhn_tet_mesh((3, 3, 3), (2 * math.pi,) * 3, (True,) * 3, 0.15, seed=2), 3),
         "tetbox": (inputs.kuhn_tet_mesh((4, 3, 3), (4.0, 1.0, 1.0), (False, True, True), 0.15, seed=3), 2),
         "hexbox": (inputs.hex_box_mesh((4, 3, 3), (1.0, 1.0, 1.0), (False, True, False)), 2),
+        "mixed": (inputs.mixed_bl_mesh((9, 5, 6), (4.0, 1.0, 0.5), (2, 2), 2, 1.2, 0.05), 2),
     }
+
+
+# Least-squares operators of the two codes agree to rounding times the
+# stencil's condition number: at most 1e-12 on the lattice meshes; on the
+# mixed boundary-layer mesh the thin prism layers under the tetrahedra give
+# stencils with condition numbers near 1e9, where two correct QR solves
+# (Householder against Gram-Schmidt) agree to about 1e-7.
+OP_TOL = {"mixed": 1e-6}
 
 
 @pytest.mark.parametrize("name", list(_meshes().keys()))
@@ -88,7 +97,7 @@ def test_host_build_matches_oracle(name):
             pl, po = np.argsort(ldir[s], kind="stable"), np.argsort(odir[s], kind="stable")
             d = np.abs(lo["Bd"][s][:, pl] - oo["Bd"][s][:, po]).max() / np.abs(oo["Bd"][s]).max()
             worst = max(worst, d)
-    assert worst < 1e-12, worst
+    assert worst < OP_TOL.get(name, 1e-12), worst
 
 
 def test_host_build_errors():

@@ -274,18 +274,23 @@ def test_cwenoz_shifts_weight_at_discontinuity():
 # ------------------------------------------------------------------ Pi 5, Pi 6
 
 
-@pytest.mark.parametrize("kind", ["hex", "tet"])
+@pytest.mark.parametrize("kind", ["hex", "tet", "mixed"])
 def test_free_stream_preservation(kind):
+    bcs = None
     if kind == "hex":
         m = inputs.periodic_hex_mesh(6)
-    else:
+    elif kind == "tet":
         m = inputs.kuhn_tet_mesh((4, 4, 4), (2 * math.pi,) * 3, (True,) * 3, 0.15, seed=5)
+    else:  # hexahedra, prisms, pyramids and tetrahedra; the free stream prescribed on every boundary
+        m = inputs.mixed_bl_mesh((9, 5, 6), (4.0, 1.0, 0.5), (2, 2), 2, 1.2, 0.05)
     om = oracle.OracleMesh(m, order=2)
     U = inputs.uniform_state(m, 1.3, [0.4, -0.3, 0.2], 2.0)
+    if kind == "mixed":
+        bcs = oracle.bc({t: (1, U[:, 0]) for t in (1, 2, 3, 4)})
     for flux in ("hllc", "rusanov"):
         for visc in (False, True):
             ph = oracle.phys(flux=flux, viscous=visc)
-            R = om.rhs(U, ph)
+            R = om.rhs(U, ph, bcs)
             assert np.abs(R).max() <= 1e-13 * np.abs(U).max()
 
 
