@@ -137,9 +137,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=64, help="cells per side of the periodic hex cube")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("tgv_hex_p2", "tgv_tet_p3"), default="tgv_hex_p2",
+    ap.add_argument("--mixed-lattice", default="650,36,128",
+                    help="mixed_bl: lattice cubes along x, y, z (650,36,128 gives about 8M cells)")
+    ap.add_argument("--workload", choices=("tgv_hex_p2", "tgv_tet_p3", "mixed_bl"), default="tgv_hex_p2",
                     help="tgv_hex_p2: the headline (FP64 plain vs FP32 + gate); tgv_tet_p3: the 48^3 x 6 "
-                         "jittered-tet P3 Euler case, FP64 and FP32 throughput")
+                         "jittered-tet P3 Euler case, FP64 and FP32 throughput; mixed_bl: the 8M-cell mixed-"
+                         "element boundary-layer box, FP64 plain and FP32 + gate throughput and memory")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
@@ -147,6 +150,8 @@ def main():
         sys.exit(2)
     if args.workload == "tgv_tet_p3":
         return main_tet_p3(args)
+    if args.workload == "mixed_bl":
+        return main_mixed_bl(args, tuple(int(a) for a in args.mixed_lattice.split(",")))
 
     import torch
 
@@ -272,6 +277,75 @@ def main_tet_p3(args, n=48):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hv["recon_GBs"] / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,
                      "bytes_per_cell": hv["recon_bytes_per_cell"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main_mixed_bl(args, n=(650, 36, 128)):
+    """The mixed-element boundary-layer box (about 8M cells: 60 % tetrahedra,
+    25 % prisms, 15 % hexahedra, pyramids at the hexahedron-tetrahedron
+    interfaces), P2 CWENOZ, HLLC, Navier-Stokes at Mach 0.8 and Re 1e6 per
+    unit length, impulsive start from the free stream over a no-slip bumped
+    wall: FP64 plain and FP32 + gate cell-stage updates/s and the memory each
+    takes (no CPU baseline: the oracle takes minutes per step here)."""
+    import resource
+
+    import numpy as np
+    import torch
+
+    from paper_2609_07387_amd import gate, inputs, ucns
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    m = inputs.mixed_bl_mesh(n, lengths=(4.0, 0.3, 0.5), hex_cols=(n[0] // 5, n[0] // 5))
+    mix = {name: int((m.ctype == t).sum()) for name, t in (("tet", inputs.TET), ("prism", inputs.PRISM),
+                                                           ("hex", inputs.HEX), ("pyramid", inputs.PYR))}
+    U0 = inputs.bl_initial(m, mach=0.8, amp=0.0)
+    ph = ucns.phys(flux="hllc", viscous=True, mach=0.8, reynolds=1e6)
+    free = U0[:, 0]
+    bcs = ucns.bc({1: (ucns.BC_DIRICHLET, free), 2: (ucns.BC_TRANSMISSIVE, None), 3: (ucns.BC_WALL, None),
+                   4: (ucns.BC_DIRICHLET, free)})
+    t1 = time.perf_counter()
+    print(f"[bench] {m.n_cell} cells generated in {t1 - t0:.1f} s; building operators", file=sys.stderr, flush=True)
+    lm = ucns.Mesh(m, order=2)
+    print(f"[bench] mesh generated in {t1 - t0:.1f} s, built in {time.perf_counter() - t1:.1f} s: {lm.n_cell} cells "
+          f"{mix}, {lm.n_face} faces", file=sys.stderr, flush=True)
+    nc = lm.n_cell
+    mlp = torch.tensor(np.load(gate.WEIGHTS).astype(np.float32), device="cuda")
+    variants = {}
+    for name, prec, net in (("fp64_plain", ucns.F64, None), ("fp32_gate", ucns.F32, mlp)):
+        torch.cuda.reset_peak_memory_stats()
+        solver = ucns.Solver(lm, ph, prec, bcs, cfl=0.5, mlp=net)
+        U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+        ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
+        rate = nc * 3 * args.steps / (ms / 1e3)
+        frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
+        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
+                          "arena_GB": lm.arena_bytes(prec) / 1e9,
+                          "device_peak_GB": torch.cuda.max_memory_allocated() / 1e9,
+                          "finite": bool(torch.isfinite(U).all())}
+        if net is not None:
+            variants[name]["fraction_gated"] = frac
+        print(f"[bench] {name}: {rate:.3e} cell-stage/s, {ms / args.steps:.3f} ms/step"
+              + (f", gated {frac:.1%}" if net is not None else ""), file=sys.stderr, flush=True)
+        del solver, U
+    hv = variants["fp32_gate"]
+    out = {
+        "metric": "cell-stage updates/s, P2 CWENOZ + HLLC + viscous on a mixed-element mesh",
+        "value": hv["value"], "unit": "cell-stage updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"mixed-element boundary-layer box {n[0]}x{n[1]}x{n[2]} lattice: hexahedral "
+                               "inflow/outflow blocks, 20 prism layers (growth 1.2) on a bumped no-slip wall, "
+                               "tetrahedra above, pyramids at the interfaces; P2 CWENOZ, HLLC, Navier-Stokes "
+                               "Mach 0.8, Re 1e6, SSP-RK3 CFL 0.5, per-step KE", "cells": nc, "faces": lm.n_face,
+                   "cell_mix": mix, "variant": "fp32_gate"},
+        "variants": variants,
+        "fp64_plain_value": variants["fp64_plain"]["value"],
+        "speedup_vs_fp64_plain": hv["value"] / variants["fp64_plain"]["value"],
+        "memory": {"host_peak_GB": resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 1e6,
+                   "device_GB_fp64": variants["fp64_plain"]["device_peak_GB"],
+                   "device_GB_fp32_gate": hv["device_peak_GB"], "device_capacity_GB": 288},
     }
     print(json.dumps(out), flush=True)
 

@@ -40,11 +40,15 @@ __device__ __forceinline__ void bst(T val, __amdgpu_buffer_rsrc_t rs, uint32_t v
 // a = B_c b over the central stencil.  With FEAT, js[] also receives the max
 // and the sum of |b| for rho (js[0], js[1]) and rho E (js[2], js[3]), which
 // the gate features use (padding members contribute zero jumps).
+//
+// MCw (wave-uniform, at most MC) bounds the member loop: the largest central
+// stencil among the wave's cells (slots past a cell's own stencil hold zero
+// operator rows and the cell itself, so they add nothing).
 template <class T, int K, bool FEAT = false>
 __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c, const double* ui, T a[K][5],
-                                               T* js = nullptr) {
+                                               T* js = nullptr, int MCw = 0) {
     const int64_t nc = A.nc;
-    const int MC = A.MC;
+    const int MC = MCw > 0 && MCw < A.MC ? MCw : A.MC;
     // member m's id at sten_c[m][c]; its K operator rows at Bc[m][k][c]; U[v][j]
     const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
     const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
@@ -109,6 +113,18 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
         }
         jnext = jf;
     }
+}
+
+// Largest central stencil among the wave's cells (every lane of the wave
+// calls this; lanes past the mesh count zero).
+template <class T>
+__device__ __forceinline__ int wave_max_ncen(const ReconArgs<T>& A, int64_t c, bool valid) {
+    int v = int(A.ncen[valid ? c : 0]);  // unconditional load (a lane condition would make it wait)
+    v = valid ? v : 0;
+    const int lane = int(threadIdx.x & 63u);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) v = max(v, __builtin_amdgcn_ds_bpermute((lane ^ d) << 2, v));
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 // Twelve gate features of a cell, for v in (rho, rho E): log(1e-12 + x) of
@@ -815,6 +831,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GATE && 
 void reconstruct_kernel(ReconArgs<T> A) {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     const bool valid = c < A.nc;
+    // the wave's largest central stencil (all lanes, before any divergence;
+    // skipped when every cell has MC members)
+    const int MCw = A.MCmin < A.MC ? wave_max_ncen(A, c, valid) : A.MC;
     double ui[5];
     T a[K][5];
     if constexpr (GATE) {
@@ -832,7 +851,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
                 T js[4];
-                central_coeffs<T, K, true>(A, c, ui, a, js);
+                central_coeffs<T, K, true>(A, c, ui, a, js, MCw);
                 gate_features<T, K>(A, c, ui, a, js, f);
             } else {
 #pragma unroll
@@ -843,7 +862,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
         } else if (valid) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
-            central_coeffs<T, K>(A, c, ui, a);
+            central_coeffs<T, K>(A, c, ui, a, nullptr, MCw);
             mode = A.gate[c] ? 0 : 1;
         }
         // troubled cells: the whole wave per cell when the wave has few, one
@@ -874,7 +893,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
         if (!valid) return;
 #pragma unroll
         for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
-        central_coeffs<T, K>(A, c, ui, a);
+        central_coeffs<T, K>(A, c, ui, a, nullptr, MCw);
         float lab = 0.f;
         const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
         A.flags[c] = uint8_t(ok ? 0 : 0x80);

@@ -87,6 +87,7 @@ struct ReconArgs {
     const int32_t* sten_c;
     const T* Bc;
     int MC;
+    int MCmin;  // smallest central stencil (MC when all cells have MC members)
     const uint8_t* ndir;
     const int32_t* sten_d;
     const T* Bd;
@@ -710,6 +711,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.sten_c = arena_ptr<int32_t>(ar, ar.sten_c);
     A.Bc = arena_ptr<T>(ar, ar.Bc);
     A.MC = m.mc_pad;
+    A.MCmin = m.mc_min;
     A.ndir = arena_ptr<uint8_t>(ar, ar.ndir);
     A.sten_d = arena_ptr<int32_t>(ar, ar.sten_d);
     A.Bd = arena_ptr<T>(ar, ar.Bd);

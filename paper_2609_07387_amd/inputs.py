@@ -353,11 +353,9 @@ def _orient_simplex_like(mesh: Mesh):
     flip = (side < 0) & (t != HEX)
     vtx = mesh.cell_vtx
     for ty, swaps in ((TET, [(2, 3)]), (PYR, [(1, 3)]), (PRISM, [(1, 2), (4, 5)])):
-        rows = np.nonzero(flip & (t == ty))[0]
-        for r in rows:
-            o = mesh.cell_ptr[r]
-            for x, y in swaps:
-                vtx[o + x], vtx[o + y] = vtx[o + y], vtx[o + x]
+        o = mesh.cell_ptr[:-1][flip & (t == ty)]
+        for x, y in swaps:
+            vtx[o + x], vtx[o + y] = vtx[o + y].copy(), vtx[o + x].copy()
 
 
 def _add_box_boundaries(mesh: Mesh, n, periodic, vid, hexes: bool):
