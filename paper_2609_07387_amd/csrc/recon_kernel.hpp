@@ -522,6 +522,7 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
     blend_finish<T, K, LABEL>(B, nd, lab, a);
 }
 
+// value of x in lane `lane` (wave-uniform index), read into every lane
 template <class T>
 __device__ __forceinline__ T lane_read(T x, int lane) {
     if constexpr (sizeof(T) == 4) {
@@ -549,7 +550,8 @@ __device__ __forceinline__ T lane_down(T x, int lane, int d) {
 }
 
 // Waves with at most this many troubled cells take them one at a time with
-// the whole wave (dir_blend_wave); busier waves run one lane per cell.
+// the whole wave (dir_blend_wave); busier waves take dir_blend_stencils or
+// one lane per cell.
 constexpr int kWaveBlendMax = 2;
 
 // Steps (iii)-(vi) for the troubled cells of a wave that has few of them
@@ -620,6 +622,7 @@ __device__ __forceinline__ void dir_blend_wave(const ReconArgs<T>& A, uint64_t t
 // central coefficients of a wave fit in its LDS.
 constexpr int kStencilLanesMax = 30;
 
+// value of x in lane src (any lane of the wave, per-lane index)
 template <class T>
 __device__ __forceinline__ T lane_from(T x, int src) {
     if constexpr (sizeof(T) == 4) {
