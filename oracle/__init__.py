@@ -89,6 +89,8 @@ def _declare(L):
     L.oracle_residual.argtypes = [vp, vp, vp]
     L.oracle_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp]
     L.oracle_rk_stage.argtypes = [vp, i32, dbl, vp, vp, vp]
+    L.oracle_ssp54_stage.argtypes = [vp, i32, dbl, vp, vp, vp]
+    L.oracle_run_ssp54.argtypes = [vp, C.POINTER(Phys), vp, vp, dbl, i32, vp, vp, vp]
     L.oracle_kinetic_energy.argtypes = [vp, vp, vp]
     L.oracle_dissipation.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp]
     L.oracle_run.argtypes = [vp, C.POINTER(Phys), vp, vp, dbl, i32, vp, vp, vp]
@@ -245,6 +247,9 @@ class OracleMesh:
     def rk_stage(self, stage, dt, U0, R, U):
         _check(lib().oracle_rk_stage(self.h, int(stage), float(dt), _p(U0), _p(R), _p(U)))
 
+    def ssp54_stage(self, stage, dt, W, R, U):
+        _check(lib().oracle_ssp54_stage(self.h, int(stage), float(dt), _p(W), _p(R), _p(U)))
+
     def rhs(self, U, ph, bcs=None, gate_mask=None):
         fs = self.reconstruct(U, ph, gate_mask)
         g = self.gradients(U, ph, bcs) if ph.viscous else None
@@ -262,14 +267,16 @@ class OracleMesh:
                                  _p(np.ascontiguousarray(U)), _p(a), _p(b))
         return float(a[0]), float(b[0])
 
-    def run(self, U, ph, cfl, n_steps, bcs=None, gate_mask=None):
-        """n_steps SSP-RK3 steps; returns (U_new, ke_history, dt_history)."""
+    def run(self, U, ph, cfl, n_steps, bcs=None, gate_mask=None, integrator="ssp3"):
+        """n_steps SSP-RK3 (or, integrator="ssp54", five-stage fourth-order
+        SSP-RK) steps; returns (U_new, ke_history, dt_history)."""
         U = np.array(U, np.float64, order="C", copy=True)
         ke = np.zeros(n_steps + 1)
         dts = np.zeros(max(n_steps, 1))
         gm = None if gate_mask is None else np.ascontiguousarray(gate_mask, np.uint8)
-        _check(lib().oracle_run(self.h, C.byref(ph), None if bcs is None else C.byref(bcs), _p(U), float(cfl),
-                                int(n_steps), _p(gm), _p(ke), _p(dts)))
+        fn = lib().oracle_run_ssp54 if integrator == "ssp54" else lib().oracle_run
+        _check(fn(self.h, C.byref(ph), None if bcs is None else C.byref(bcs), _p(U), float(cfl),
+                  int(n_steps), _p(gm), _p(ke), _p(dts)))
         return U, ke, dts[:n_steps]
 
     def gate_features(self, U, ph):

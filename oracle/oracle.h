@@ -107,6 +107,9 @@ int oracle_dt(const oracle_mesh* m, const oracle_phys* ph, const double* U, doub
 /* SSP-RK3 stage s: U <- a_s U0 + b_s (U + dt R) */
 int oracle_rk_stage(const oracle_mesh* m, int stage, double dt, const double* U0, const double* R,
                     double* U);
+/* Five-stage fourth-order SSP-RK stage s (0..4) in Shu-Osher form; W holds
+ * u0, u2, u3 and R(u3) as the stages write them ([4][5][n_cell]) */
+int oracle_ssp54_stage(const oracle_mesh* m, int stage, double dt, double* W, const double* R, double* U);
 /* Mean kinetic energy sum |V| |m|^2/(2 rho) / sum |V| */
 int oracle_kinetic_energy(const oracle_mesh* m, const double* U, double* ke);
 /* Solenoidal / dilatational dissipation from Green-Gauss velocity gradients */
@@ -116,6 +119,9 @@ int oracle_dissipation(const oracle_mesh* m, const oracle_phys* ph, const oracle
  * ke[n_steps+1], dt_hist[n_steps] may be NULL.  gate_mask applied every stage. */
 int oracle_run(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, double* U,
                double cfl, int n_steps, const uint8_t* gate_mask, double* ke, double* dt_hist);
+/* the same with the five-stage fourth-order SSP-RK */
+int oracle_run_ssp54(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, double* U,
+                     double cfl, int n_steps, const uint8_t* gate_mask, double* ke, double* dt_hist);
 
 /* Convective numerical flux F(uL, uR; n) of one point (unit normal n) */
 int oracle_point_flux(const oracle_phys* ph, const double* uL, const double* uR, const double* n, double* F);

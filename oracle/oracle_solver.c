@@ -424,6 +424,38 @@ int oracle_rk_stage(const oracle_mesh* m, int stage, double dt, const double* U0
     return 0;
 }
 
+/* Five-stage fourth-order SSP Runge-Kutta (Spiteri & Ruuth 2002, the
+ * integrator family the paper uses, Sec. 2.1), Shu-Osher form with L = R:
+ *   u1 = u0 + b10 dt L(u0)
+ *   u2 = a20 u0 + a21 u1 + b21 dt L(u1)
+ *   u3 = a30 u0 + a32 u2 + b32 dt L(u2)
+ *   u4 = a40 u0 + a43 u3 + b43 dt L(u3)
+ *   u5 = a52 u2 + a53 u3 + b53 dt L(u3) + a54 u4 + b54 dt L(u4)
+ * Stage s takes R = L(U) of the current U; W holds u0, u2, u3 and L(u3)
+ * (four blocks of NV n_cell values), written as the stages reach them. */
+int oracle_ssp54_stage(const oracle_mesh* m, int stage, double dt, double* W, const double* R, double* U) {
+    static const double b10 = 0.391752226571890;
+    static const double a20 = 0.444370493651235, a21 = 0.555629506348765, b21 = 0.368410593050371;
+    static const double a30 = 0.620101851488403, a32 = 0.379898148511597, b32 = 0.251891774271694;
+    static const double a40 = 0.178079954393132, a43 = 0.821920045606868, b43 = 0.544974750228521;
+    static const double a52 = 0.517231671970585, a53 = 0.096059710526147, b53 = 0.063692468666290;
+    static const double a54 = 0.386708617503269, b54 = 0.226007483236906;
+    if (stage < 0 || stage > 4) return or_fail(-1, "stage %d", stage);
+    int64_t n = NV * m->n_cell;
+    double *u0 = W, *u2 = W + n, *u3 = W + 2 * n, *L3 = W + 3 * n;
+    for (int64_t k = 0; k < n; ++k) {
+        double u = U[k], r = R[k];
+        switch (stage) {
+            case 0: u0[k] = u; U[k] = u + b10 * dt * r; break;
+            case 1: U[k] = a20 * u0[k] + a21 * u + b21 * dt * r; u2[k] = U[k]; break;
+            case 2: U[k] = a30 * u0[k] + a32 * u + b32 * dt * r; u3[k] = U[k]; break;
+            case 3: L3[k] = r; U[k] = a40 * u0[k] + a43 * u + b43 * dt * r; break;
+            default: U[k] = a52 * u2[k] + a53 * u3[k] + b53 * dt * L3[k] + a54 * u + b54 * dt * r; break;
+        }
+    }
+    return 0;
+}
+
 int oracle_kinetic_energy(const oracle_mesh* m, const double* U, double* ke) {
     int64_t nc = m->n_cell;
     double s = 0, vs = 0;
@@ -468,12 +500,25 @@ static int eval_rhs(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc
     return oracle_residual(m, ff, R);
 }
 
+static int run_steps(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, double* U, double cfl,
+                     int n_steps, const uint8_t* gate_mask, double* ke, double* dt_hist, int ssp54);
+
 int oracle_run(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, double* U, double cfl,
                int n_steps, const uint8_t* gate_mask, double* ke, double* dt_hist) {
+    return run_steps(m, ph, bc, U, cfl, n_steps, gate_mask, ke, dt_hist, 0);
+}
+
+int oracle_run_ssp54(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, double* U, double cfl,
+                     int n_steps, const uint8_t* gate_mask, double* ke, double* dt_hist) {
+    return run_steps(m, ph, bc, U, cfl, n_steps, gate_mask, ke, dt_hist, 1);
+}
+
+static int run_steps(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, double* U, double cfl,
+                     int n_steps, const uint8_t* gate_mask, double* ke, double* dt_hist, int ssp54) {
     int64_t nc = m->n_cell, nf = m->n_face;
     for (int64_t c = 0; c < nc; ++c)
         if (!m->need[c]) return or_fail(-1, "oracle_run needs every cell built");
-    double* U0 = malloc(sizeof(double) * NV * nc);
+    double* U0 = malloc(sizeof(double) * NV * nc * (ssp54 ? 4 : 1));
     double* R = malloc(sizeof(double) * NV * nc);
     double* fs = calloc((size_t)nf * 2 * OR_QM * NV, sizeof(double));
     double* ff = malloc(sizeof(double) * NV * nf);
@@ -485,10 +530,10 @@ int oracle_run(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc,
         rc = oracle_dt(m, ph, U, cfl, &dt);
         if (rc) break;
         if (dt_hist) dt_hist[n] = dt;
-        memcpy(U0, U, sizeof(double) * NV * nc);
-        for (int s = 0; s < 3 && !rc; ++s) {
+        if (!ssp54) memcpy(U0, U, sizeof(double) * NV * nc);
+        for (int s = 0; s < (ssp54 ? 5 : 3) && !rc; ++s) {
             rc = eval_rhs(m, ph, bc, U, gate_mask, fs, gw, ff, R);
-            if (!rc) rc = oracle_rk_stage(m, s, dt, U0, R, U);
+            if (!rc) rc = ssp54 ? oracle_ssp54_stage(m, s, dt, U0, R, U) : oracle_rk_stage(m, s, dt, U0, R, U);
         }
         if (ke) oracle_kinetic_energy(m, U, &ke[n + 1]);
     }

@@ -610,6 +610,38 @@ def test_ssp_rk3_stability_polynomial():
     assert np.allclose(U, 1 + z + z ** 2 / 2 + z ** 3 / 6, rtol=1e-14, atol=1e-15)
 
 
+def _ssp54_step(om, U, dt, rhs):
+    """One five-stage step of the oracle's SSP-RK on a state array with a
+    right-hand side given by the test."""
+    W = np.zeros((4,) + U.shape)
+    U = U.copy()
+    for s in range(5):
+        om.ssp54_stage(s, dt, W, rhs(U), U)
+    return U
+
+
+def test_ssp54_linear_and_nonlinear_order():
+    """Five-stage SSP-RK (Spiteri-Ruuth coefficients): on y' = lambda y one
+    step multiplies by a quintic that equals exp(z) through z^4 (the linear
+    order conditions), and on the nonlinear y' = -y^2 (exact 1/(1 + t)) the
+    error at t = 1 falls 16-fold per halving of dt (fourth order)."""
+    om = oracle.OracleMesh(inputs.periodic_hex_mesh(6), order=2)
+    shape = (5, om.n_cell)
+    zs = np.linspace(-1.5, 0.5, 6)
+    vals = [_ssp54_step(om, np.ones(shape), 1.0, lambda U, z=z: z * U)[0, 0] for z in zs]
+    c = np.polyfit(zs, vals, 5)[::-1]  # coefficients of z^0 .. z^5
+    for k in range(5):
+        assert abs(c[k] - 1.0 / math.factorial(k)) < 1e-12, (k, c[k])
+    assert abs(c[5] - 1.0 / 120) > 1e-6  # a different method would reach fifth order here
+    errs = []
+    for n in (10, 20, 40):
+        U = np.ones(shape)
+        for _ in range(n):
+            U = _ssp54_step(om, U, 1.0 / n, lambda V: -V * V)
+        errs.append(abs(U[0, 0] - 0.5))
+    assert 14.0 < errs[0] / errs[1] < 18.0 and 14.0 < errs[1] / errs[2] < 18.0, errs
+
+
 def test_normal_shock_rankine_hugoniot():
     """Post-shock state of the shocked box satisfies the Rankine-Hugoniot jump
     conditions in the shock frame."""
