@@ -235,6 +235,18 @@ int ucns_rk_stage(const ucns_mesh* mesh, int stage, const double* dt_dev, double
 int ucns_residual_rk_stage(const ucns_mesh* mesh, const void* face_flux, int precision, int stage,
                            const double* dt_dev, double* U0, double* U, ucns_stream stream);
 
+/* The residual fused with stage s (0 .. 4) of the five-stage fourth-order
+ * SSP Runge-Kutta method of Spiteri and Ruuth (the integrator family of
+ * Sec. 2.1), Shu-Osher form, R = R(U) of the current U:
+ *   u1 = u0 + b10 dt R(u0);  u2 = a20 u0 + a21 u1 + b21 dt R(u1);
+ *   u3 = a30 u0 + a32 u2 + b32 dt R(u2);  u4 = a40 u0 + a43 u3 + b43 dt R(u3);
+ *   u5 = a52 u2 + a53 u3 + b53 dt R(u3) + a54 u4 + b54 dt R(u4)
+ * with the published coefficients.  W (device double [4][5][n_cell],
+ * caller-owned) keeps u0, u2, u3 and R(u3) between the stages of a step;
+ * dt is read from the device scalar. */
+int ucns_residual_ssp54_stage(const ucns_mesh* mesh, const void* face_flux, int precision, int stage,
+                              const double* dt_dev, double* W, double* U, ucns_stream stream);
+
 /* The last SSP-RK3 stage (ucns_residual_rk_stage with stage 2) fused with the
  * two reductions a step ends with, taken on the new U while it is in
  * registers: the time step of the next step (as ucns_dt with cfl) into

@@ -605,6 +605,49 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(ResArgs<T> A) {
     }
 }
 
+// Five-stage fourth-order SSP-RK (Spiteri & Ruuth), Shu-Osher form, stage s
+// on R = -(1/|V|) sum_f s_f F_f of the current U:
+//   s0: u1 = u0 + b10 dt R(u0)                      (W0 <- u0)
+//   s1: u2 = a20 u0 + a21 u1 + b21 dt R(u1)         (W1 <- u2)
+//   s2: u3 = a30 u0 + a32 u2 + b32 dt R(u2)         (W2 <- u3)
+//   s3: u4 = a40 u0 + a43 u3 + b43 dt R(u3)         (W3 <- R(u3))
+//   s4: u5 = a52 u2 + a53 u3 + b53 dt R(u3) + a54 u4 + b54 dt R(u4)
+struct Ssp54 {
+    double b10, a20, a21, b21, a30, a32, b32, a40, a43, b43, a52, a53, b53, a54, b54;
+};
+constexpr Ssp54 kSsp54{0.391752226571890, 0.444370493651235, 0.555629506348765, 0.368410593050371,
+                       0.620101851488403, 0.379898148511597, 0.251891774271694, 0.178079954393132,
+                       0.821920045606868, 0.544974750228521, 0.517231671970585, 0.096059710526147,
+                       0.063692468666290, 0.386708617503269, 0.226007483236906};
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void residual_ssp54_kernel(ResArgs<T> A, double* W) {
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= A.nc) return;
+    double acc[5];
+    face_sum<T>(A, c, acc);
+    const double iv = -1.0 / A.vol[c];
+    const double dt = *A.dt;
+    const int64_t n = 5 * A.nc;
+    constexpr Ssp54 k = kSsp54;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const int64_t i = v * A.nc + c;
+        const double u = A.U[i], r = acc[v] * iv;
+        double un;
+        switch (A.stage) {
+            case 0: W[i] = u; un = u + k.b10 * dt * r; break;
+            case 1: un = k.a20 * W[i] + k.a21 * u + k.b21 * dt * r; W[n + i] = un; break;
+            case 2: un = k.a30 * W[i] + k.a32 * u + k.b32 * dt * r; W[2 * n + i] = un; break;
+            case 3: W[3 * n + i] = r; un = k.a40 * W[i] + k.a43 * u + k.b43 * dt * r; break;
+            default:
+                un = k.a52 * W[n + i] + k.a53 * W[2 * n + i] + k.b53 * dt * W[3 * n + i] + k.a54 * u + k.b54 * dt * r;
+                break;
+        }
+        A.U[i] = un;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void rk_stage_kernel(int64_t n, double* U0, const double* R, double* U,
                                                           const double* dt, double a, double b, int stage) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1035,6 +1078,29 @@ int ucns_residual_rk_stage(const ucns_mesh* mesh, const void* face_flux, int pre
     UCNS_REQUIRE(stage >= 0 && stage <= 2, UCNS_EINVAL, "stage must be 0, 1 or 2");
     UCNS_REQUIRE(aligned(face_flux) && aligned(U0) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
     return launch_residual(mesh, face_flux, precision, nullptr, stage, dt_dev, U0, U, stream);
+}
+
+int ucns_residual_ssp54_stage(const ucns_mesh* mesh, const void* face_flux, int precision, int stage,
+                              const double* dt_dev, double* W, double* U, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && face_flux && dt_dev && W && U, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(stage >= 0 && stage <= 4, UCNS_EINVAL, "stage must be 0 .. 4");
+    UCNS_REQUIRE(aligned(face_flux) && aligned(W) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    const Mesh& m = *mesh->m;
+    const Arena& ar = m.arena[precision];
+    UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    auto go = [&](auto zero) {
+        using T = decltype(zero);
+        ResArgs<T> A{static_cast<const T*>(face_flux), m.nc, arena_ptr<int32_t>(ar, ar.c2f), m.nfmax,
+                     arena_ptr<double>(ar, ar.vol), nullptr, nullptr, U, dt_dev, 0.0, 0.0, stage};
+        hipLaunchKernelGGL(residual_ssp54_kernel<T>, dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A, W);
+    };
+    if (precision == UCNS_F64)
+        go(double(0));
+    else
+        go(float(0));
+    return hip_check("ucns_residual_ssp54_stage");
 }
 
 int ucns_rk_stage(const ucns_mesh* mesh, int stage, const double* dt_dev, double* U0, const double* R,

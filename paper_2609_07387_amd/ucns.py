@@ -28,6 +28,7 @@ EXPORTS = [
     "ucns_workspace_elems", "ucns_dt", "ucns_reconstruct", "ucns_gradients", "ucns_face_flux", "ucns_residual",
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
     "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
+    "ucns_residual_ssp54_stage",
 ]
 
 
@@ -93,6 +94,7 @@ def lib():
         L.ucns_rk_stage.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ucns_residual_rk_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
         L.ucns_diag_ke.argtypes = [vp, vp, vp, vp, vp]
+        L.ucns_residual_ssp54_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
         L.ucns_residual_rk_final.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.ucns_gate_features.argtypes = [vp, vp, i32, vp, vp]
         L.ucns_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
@@ -326,6 +328,13 @@ def residual_rk_final(mesh, ph, ff, precision, dt_dev, U0, U, cfl, scratch, dt_n
                                        float(cfl), _dp(scratch), _dp(dt_next), _dp(ke_dev), _stream(stream)))
 
 
+def residual_ssp54_stage(mesh, ff, precision, stage, dt_dev, W, U, stream=None):
+    """Residual fused with stage 0..4 of the five-stage fourth-order SSP-RK;
+    W (float64 [4][5][n_cell]) carries the stage states between calls."""
+    check(lib().ucns_residual_ssp54_stage(mesh.h, _dp(ff), precision, int(stage), _dp(dt_dev), _dp(W), _dp(U),
+                                          _stream(stream)))
+
+
 def diag_ke(mesh, U, scratch, ke_dev, stream=None):
     check(lib().ucns_diag_ke(mesh.h, _dp(U), _dp(scratch), _dp(ke_dev), _stream(stream)))
 
@@ -334,10 +343,12 @@ class Solver:
     """SSP-RK3 driver over the C-ABI calls (one stream, no host syncs)."""
 
     def __init__(self, mesh: Mesh, ph: Phys, precision=F64, bcs=None, cfl=0.5, gate_mask=None, device="cuda",
-                 mlp=None, label=False):
+                 mlp=None, label=False, integrator="ssp3"):
         """gate_mask: fixed per-cell mask (1 = smooth); mlp: gate network
         parameters (device float32) evaluated inside every reconstruction;
-        label: also record max |omega - lambda| per cell (ws.label)."""
+        label: also record max |omega - lambda| per cell (ws.label);
+        integrator: "ssp3" (Shu-Osher SSP-RK3) or "ssp54" (five-stage
+        fourth-order SSP-RK)."""
         import torch
 
         self.mesh, self.ph, self.precision, self.bcs, self.cfl = mesh, ph, precision, bcs, cfl
@@ -351,6 +362,10 @@ class Solver:
         self.mlp = mlp
         self.mlp_image = mlp_pack(mlp) if mlp is not None else None
         self._dt_key = None  # (data pointer, version) of the U whose dt ws.dt holds
+        assert integrator in ("ssp3", "ssp54"), integrator
+        self.integrator = integrator
+        self.W = (torch.empty((4, 5, mesh.n_cell), dtype=torch.float64, device=device)
+                  if integrator == "ssp54" else None)
 
     def rhs_stage(self, U):
         ws = self.ws
@@ -374,6 +389,13 @@ class Solver:
         and forces one)."""
         ws = self.ws
         self.ensure_dt(U)
+        if self.integrator == "ssp54":
+            for s in range(5):
+                self.rhs_stage(U)
+                residual_ssp54_stage(self.mesh, ws.face_flux, self.precision, s, ws.dt, self.W, U)
+            diag_ke(self.mesh, U, ws.reduce, ws.ke)
+            self._dt_key = None  # the next step takes its own dt pass
+            return
         for s in range(2):  # stage 0 stores U^n into U0
             self.rhs_stage(U)
             residual_rk_stage(self.mesh, ws.face_flux, self.precision, s, ws.dt, self.U0, U)

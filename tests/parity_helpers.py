@@ -75,11 +75,11 @@ def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
             ff.double().cpu().numpy().reshape(lm.n_face, 5), R.cpu().numpy(), flags.cpu().numpy())
 
 
-def gpu_run(lm, ph, U_np, precision, n_steps, cfl, bcs=None, gate_mask=None, device="cuda"):
+def gpu_run(lm, ph, U_np, precision, n_steps, cfl, bcs=None, gate_mask=None, device="cuda", integrator="ssp3"):
     import torch
 
     gm = None if gate_mask is None else torch.tensor(gate_mask, dtype=torch.uint8, device=device)
-    s = ucns.Solver(lm, ph, precision, bcs, cfl, gm, device)
+    s = ucns.Solver(lm, ph, precision, bcs, cfl, gm, device, integrator=integrator)
     U = torch.tensor(U_np, dtype=torch.float64, device=device).contiguous()
     ke, dts = s.run(U, n_steps, ke_history=True)
     torch.cuda.synchronize()

@@ -130,6 +130,24 @@ def test_steps_fp64(torch_cuda, name, steps):
     assert err < tol, err
 
 
+@pytest.mark.parametrize("name,steps", [("hex16_p2_rusanov", 5), ("mixed_bl_ns", 3)])
+def test_ssp54_steps_fp64(torch_cuda, name, steps):
+    """Five-stage fourth-order SSP-RK steps (ucns_residual_ssp54_stage)
+    against the oracle's own implementation of the method."""
+    print(f"[gpu] ssp54 steps {name} x{steps}", flush=True)
+    m, order, ph, U, bcs = _setup(name)
+    lm = ucns.Mesh(m, order=order)
+    om = oracle.OracleMesh(m, order=order)
+    Ug, ke_g, dt_g = gpu_run(lm, ph, U, ucns.F64, steps, 0.5, bcs, integrator="ssp54")
+    Uo, ke_o, dt_o = om.run(U, as_oracle_phys(ph), 0.5, steps, as_oracle_bc(bcs), integrator="ssp54")
+    err = grouped_rel_linf(Ug, Uo)
+    print(f"[gpu]   rel Linf {err:.3e}", flush=True)
+    tol = TOL_CASE.get(name, TOL_STEPS)
+    assert np.allclose(dt_g, dt_o, rtol=max(1e-14, tol / 100))
+    assert np.allclose(ke_g, ke_o, rtol=max(1e-12, tol))
+    assert err < tol, err
+
+
 def test_gate_mask_semantics(torch_cuda):
     """mask all ones = linear central path; all zeros = full CWENOZ, each
     troubled cell in its own lane as in the ungated kernel; a sparse mask
