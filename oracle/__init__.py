@@ -63,7 +63,7 @@ class Opts(C.Structure):
 
 class Phys(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("reynolds", C.c_double), ("prandtl", C.c_double),
-                ("viscous", C.c_int), ("flux", C.c_int)]
+                ("viscous", C.c_int), ("flux", C.c_int), ("grad", C.c_int)]
 
 
 class BC(C.Structure):
@@ -85,6 +85,7 @@ def _declare(L):
     L.oracle_cell_quadrature.argtypes = [vp, i64, vp, vp, i32]
     L.oracle_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp, vp]
     L.oracle_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, vp]
+    L.oracle_gradients_lsq.argtypes = [vp, C.POINTER(Phys), vp, vp, vp]
     L.oracle_face_flux.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp, vp]
     L.oracle_residual.argtypes = [vp, vp, vp]
     L.oracle_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp]
@@ -107,8 +108,12 @@ def _check(rc):
         raise RuntimeError(f"oracle error {rc}: {lib().oracle_last_error().decode()}")
 
 
-def phys(gamma=1.4, mach=0.1, reynolds=1600.0, prandtl=0.72, viscous=False, flux="hllc") -> Phys:
-    return Phys(gamma, mach, reynolds, prandtl, int(bool(viscous)), 1 if flux == "hllc" else 0)
+def phys(gamma=1.4, mach=0.1, reynolds=1600.0, prandtl=0.72, viscous=False, flux="hllc",
+         gradients="green_gauss") -> Phys:
+    if gradients not in ("green_gauss", "least_squares"):
+        raise ValueError(f"gradients: {gradients!r}")
+    return Phys(gamma, mach, reynolds, prandtl, int(bool(viscous)), 1 if flux == "hllc" else 0,
+                1 if gradients == "least_squares" else 0)
 
 
 def point_flux(ph, uL, uR, n):
@@ -221,9 +226,11 @@ class OracleMesh:
         return (fs, flags, label) if with_flags else fs
 
     def gradients(self, U, ph, bcs=None):
+        """Cell gradients of (u, v, w, T) by the method ph.grad selects."""
         U = np.ascontiguousarray(U, np.float64)
         g = np.zeros((12, self.n_cell))
-        _check(lib().oracle_gradients(self.h, C.byref(ph), None if bcs is None else C.byref(bcs), _p(U), _p(g)))
+        fn = lib().oracle_gradients_lsq if ph.grad == 1 else lib().oracle_gradients
+        _check(fn(self.h, C.byref(ph), None if bcs is None else C.byref(bcs), _p(U), _p(g)))
         return g
 
     def face_flux(self, U, fs, ph, gradW=None, bcs=None):

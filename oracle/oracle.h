@@ -46,6 +46,7 @@ typedef struct {
     double gamma, mach, reynolds, prandtl;
     int viscous;        /* 0 Euler, 1 Navier-Stokes */
     int flux;           /* 0 Rusanov, 1 HLLC */
+    int grad;           /* viscous cell gradients: 0 Green-Gauss, 1 least squares */
 } oracle_phys;
 
 /* Boundary condition per face tag (1..7): kind 0 none, 1 Dirichlet state,
@@ -97,6 +98,11 @@ int oracle_reconstruct(const oracle_mesh* m, const oracle_phys* ph, const double
 /* Green-Gauss gradients of (u, v, w, T): gradW [12][n_cell], row = 3*var + dir */
 int oracle_gradients(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc,
                      const double* U, double* gradW);
+/* Least-squares gradients of (u, v, w, T) over the face neighbours, boundary
+ * faces entering through their ghost state at the mirrored centroid; same
+ * layout.  The residual path takes this one when ph->grad == 1. */
+int oracle_gradients_lsq(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc,
+                         const double* U, double* gradW);
 /* Face fluxes [n_face][5] (owner -> neighbour, integrated over the face); U
  * (cell averages) supplies the transmissive boundary ghost state */
 int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, const double* U,

@@ -279,6 +279,77 @@ int oracle_gradients(const oracle_mesh* m, const oracle_phys* ph, const oracle_b
     return 0;
 }
 
+/* Least-squares cell gradients of W = (u, v, w, T) (Sec. 2.2 and Sec. 2.1:
+ * the viscous terms take least-squares gradients with boundary-condition
+ * constraints).  Reading of what the paper leaves open: a linear fit
+ *     min_g  sum_j w_j (W_j - W_i - g . d_j)^2,   w_j = 1 / |d_j|^2,
+ * over the face neighbours j, with d_j the offset from c_i to the image of
+ * c_j next to cell i (periodic seams included).  A boundary face enters as
+ * its ghost state (the same ghost as above) placed at the mirror image of c_i
+ * in the face plane, d = 2 ((x_f - c_i) . n) n: the no-slip wall's mirrored
+ * velocity puts u = 0 on the wall, the wall's temperature and the
+ * transmissive ghost give zero normal derivative, a Dirichlet ghost imposes
+ * its state.  Solved per cell from the 3x3 normal equations by Cramer's rule. */
+static double det3(const double A[3][3]) {
+    return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+
+int oracle_gradients_lsq(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, const double* U,
+                         double* gradW) {
+    int64_t nc = m->n_cell;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t c = 0; c < nc; ++c) {
+        double ui[NV], Wi[4], M[3][3] = {{0}}, rhs[4][3] = {{0}};
+        for (int v = 0; v < NV; ++v) ui[v] = U[v * nc + c];
+        prim_W(ph, ui, Wi);
+        for (int lf = 0; lf < or_cell_nfaces(m->type[c]); ++lf) {
+            int64_t f = m->c2f[OR_MAXF * c + lf];
+            int side = m->c2s[OR_MAXF * c + lf];
+            int64_t other = m->fcell[2 * f + (1 - side)];
+            double uo[NV], Wo[4], d[3];
+            if (other >= 0) {
+                /* the neighbour's image next to c: owner frame = neighbour frame + shift */
+                double sh = side ? -1.0 : 1.0;
+                for (int a = 0; a < 3; ++a) d[a] = m->cen[3 * other + a] + sh * m->fshift[3 * f + a] - m->cen[3 * c + a];
+                for (int v = 0; v < NV; ++v) uo[v] = U[v * nc + other];
+            } else {
+                double dn = 0;
+                for (int a = 0; a < 3; ++a) dn += (m->fcen[3 * f + a] - m->cen[3 * c + a]) * m->fnrm[3 * f + a];
+                for (int a = 0; a < 3; ++a) d[a] = 2.0 * dn * m->fnrm[3 * f + a];
+                ghost_state(bc, (int)(-1 - other), ui, ui, uo);
+            }
+            prim_W(ph, uo, Wo);
+            double w = 1.0 / (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) M[a][b] += w * d[a] * d[b];
+            for (int var = 0; var < 4; ++var)
+                for (int a = 0; a < 3; ++a) rhs[var][a] += w * d[a] * (Wo[var] - Wi[var]);
+        }
+        double det = det3(M);
+        if (!(fabs(det) > 0)) {
+            bad = 1;
+            continue;
+        }
+        for (int var = 0; var < 4; ++var)
+            for (int a = 0; a < 3; ++a) {
+                /* Cramer: replace column a of M by the right-hand side */
+                double A[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int k = 0; k < 3; ++k) A[r][k] = k == a ? rhs[var][r] : M[r][k];
+                gradW[(3 * var + a) * nc + c] = det3(A) / det;
+            }
+    }
+    return bad ? or_fail(-1, "singular least-squares gradient system") : 0;
+}
+
+/* Viscous-gradient choice of the physics options: Green-Gauss or least squares. */
+static int cell_gradients(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc* bc, const double* U,
+                          double* gradW) {
+    return ph->grad == 1 ? oracle_gradients_lsq(m, ph, bc, U, gradW) : oracle_gradients(m, ph, bc, U, gradW);
+}
+
 /* ------------------------------------------------------------ face flux */
 
 /* Viscous flux F_v . n at one quadrature point (Newtonian stress with
@@ -495,7 +566,10 @@ static int eval_rhs(const oracle_mesh* m, const oracle_phys* ph, const oracle_bc
                     const uint8_t* gate_mask, double* fs, double* gw, double* ff, double* R) {
     int rc = oracle_reconstruct(m, ph, U, gate_mask, fs, NULL, NULL);
     if (rc) return rc;
-    if (ph->viscous) oracle_gradients(m, ph, bc, U, gw);
+    if (ph->viscous) {
+        rc = cell_gradients(m, ph, bc, U, gw);
+        if (rc) return rc;
+    }
     oracle_face_flux(m, ph, bc, U, fs, ph->viscous ? gw : NULL, ff);
     return oracle_residual(m, ff, R);
 }
