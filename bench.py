@@ -130,6 +130,9 @@ def cpu_baseline(seconds=12.0):
                       f"steps in {dt:.1f} s, mesh build excluded"}
 
 
+GRAD_NAME = {"green_gauss": "Green-Gauss", "least_squares": "least-squares"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +146,8 @@ def main():
                     help="tgv_hex_p2: the headline (FP64 plain vs FP32 + gate); tgv_tet_p3: the 48^3 x 6 "
                          "jittered-tet P3 Euler case, FP64 and FP32 throughput; mixed_bl: the 8M-cell mixed-"
                          "element boundary-layer box, FP64 plain and FP32 + gate throughput and memory")
+    ap.add_argument("--gradients", choices=("green_gauss", "least_squares"), default="green_gauss",
+                    help="viscous cell gradients of the Navier-Stokes workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
@@ -160,7 +165,7 @@ def main():
     torch.cuda.set_device(0)
     m = inputs.periodic_hex_mesh(args.n)
     U0 = inputs.tgv_initial(m)
-    ph = ucns.phys(flux="hllc", viscous=True, mach=0.1, reynolds=1600.0)
+    ph = ucns.phys(flux="hllc", viscous=True, mach=0.1, reynolds=1600.0, gradients=args.gradients)
     t0 = time.perf_counter()
     lm = ucns.Mesh(m, order=2)
     print(f"[bench] mesh build {time.perf_counter() - t0:.1f} s, {lm.n_cell} cells, {lm.n_face} faces", file=sys.stderr,
@@ -210,7 +215,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if head != "fp64_plain" else "f64", "data": "synthetic",
         "config": {"workload": f"TGV {args.n}^3 periodic hex, P2 CWENOZ, HLLC, Navier-Stokes Re 1600 Mach 0.1, "
-                               "Green-Gauss, SSP-RK3 CFL 0.5, per-step KE", "cells": nc, "faces": lm.n_face,
+                               f"{GRAD_NAME[args.gradients]} gradients, SSP-RK3 CFL 0.5, per-step KE",
+                   "cells": nc, "faces": lm.n_face,
                    "variant": head + (" (FP32 reconstruction/flux, FP64 state/RK/reductions, BF16 gate network)"
                                       if head == "fp32_gate" else "")},
         "variants": variants,
@@ -301,7 +307,7 @@ def main_mixed_bl(args, n=(650, 36, 128)):
     mix = {name: int((m.ctype == t).sum()) for name, t in (("tet", inputs.TET), ("prism", inputs.PRISM),
                                                            ("hex", inputs.HEX), ("pyramid", inputs.PYR))}
     U0 = inputs.bl_initial(m, mach=0.8, amp=0.0)
-    ph = ucns.phys(flux="hllc", viscous=True, mach=0.8, reynolds=1e6)
+    ph = ucns.phys(flux="hllc", viscous=True, mach=0.8, reynolds=1e6, gradients=args.gradients)
     free = U0[:, 0]
     bcs = ucns.bc({1: (ucns.BC_DIRICHLET, free), 2: (ucns.BC_TRANSMISSIVE, None), 3: (ucns.BC_WALL, None),
                    4: (ucns.BC_DIRICHLET, free)})
@@ -338,7 +344,8 @@ def main_mixed_bl(args, n=(650, 36, 128)):
         "config": {"workload": f"mixed-element boundary-layer box {n[0]}x{n[1]}x{n[2]} lattice: hexahedral "
                                "inflow/outflow blocks, 20 prism layers (growth 1.2) on a bumped no-slip wall, "
                                "tetrahedra above, pyramids at the interfaces; P2 CWENOZ, HLLC, Navier-Stokes "
-                               "Mach 0.8, Re 1e6, SSP-RK3 CFL 0.5, per-step KE", "cells": nc, "faces": lm.n_face,
+                               f"Mach 0.8, Re 1e6, {GRAD_NAME[args.gradients]} gradients, SSP-RK3 CFL 0.5, "
+                               "per-step KE", "cells": nc, "faces": lm.n_face,
                    "cell_mix": mix, "variant": "fp32_gate"},
         "variants": variants,
         "fp64_plain_value": variants["fp64_plain"]["value"],

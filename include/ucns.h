@@ -1,6 +1,6 @@
 /* libucns -- MI355X (gfx950) explicit residual evaluation of a high-order
  * unstructured finite-volume solver for the compressible Navier-Stokes
- * equations: least-squares CWENOZ reconstruction, Green-Gauss gradients,
+ * equations: least-squares CWENOZ reconstruction, Green-Gauss or least-squares gradients,
  * HLLC/Rusanov + viscous face fluxes, per-cell residual and SSP-RK3 update.
  *
  * The method is the one stated in Sec. 2.2 of "Towards Heterogeneous
@@ -52,7 +52,7 @@ enum {
     UCNS_OK = 0,
     UCNS_EINVAL = -1,  /* bad argument, size or alignment */
     UCNS_EMESH = -2,   /* invalid mesh: non-positive volume, non-manifold or unmatched face */
-    UCNS_ERANK = -3,   /* a central stencil stays rank deficient */
+    UCNS_ERANK = -3,   /* a central stencil stays rank deficient, or a cell's least-squares gradient fit is singular */
     UCNS_EHIP = -4,    /* HIP runtime error */
     UCNS_ENOMEM = -5,  /* caller buffer too small */
     UCNS_ESTATE = -6,  /* call out of order (e.g. compute before upload) */
@@ -62,6 +62,7 @@ enum {
 enum { UCNS_TET = 4, UCNS_PYR = 5, UCNS_PRISM = 6, UCNS_HEX = 8 };
 enum { UCNS_F64 = 0, UCNS_F32 = 1 };
 enum { UCNS_RUSANOV = 0, UCNS_HLLC = 1 };
+enum { UCNS_GRAD_GREEN_GAUSS = 0, UCNS_GRAD_LSQ = 1 };
 enum { UCNS_BC_NONE = 0, UCNS_BC_DIRICHLET = 1, UCNS_BC_TRANSMISSIVE = 2, UCNS_BC_WALL = 3 };
 
 /* Mesh description (host arrays, read during ucns_mesh_build only).
@@ -100,6 +101,7 @@ typedef struct {
     double gamma, mach, reynolds, prandtl;
     int viscous;        /* 0 Euler, 1 Navier-Stokes */
     int flux;           /* UCNS_RUSANOV or UCNS_HLLC */
+    int grad;           /* viscous cell gradients: UCNS_GRAD_GREEN_GAUSS (0) or UCNS_GRAD_LSQ */
 } ucns_phys;
 
 /* Boundary condition per face tag 1..7 (index 0 unused). */
@@ -174,6 +176,10 @@ int ucns_mesh_cell_geometry(const ucns_mesh* mesh, double* vol, double* cen, dou
 int ucns_mesh_stencil(const ucns_mesh* mesh, int64_t cell, int64_t* central, int32_t* ncen, int64_t* dir,
                       int32_t* ndir, int32_t* dface);
 int ucns_mesh_operators(const ucns_mesh* mesh, int64_t cell, double* Bc, double* Bd, double* O, double* Phi);
+/* Least-squares gradient weights of one cell, G[6][3] by local face slot
+ * (zero for absent slots): grad W_c = sum_lf G[lf] (W_lf - W_c), W_lf the
+ * face neighbour's value or the boundary ghost's. */
+int ucns_mesh_gradient_weights(const ucns_mesh* mesh, int64_t cell, double* G);
 
 /* --------------------------------------------------------- workspaces */
 
@@ -205,8 +211,19 @@ int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, doubl
 int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
                      const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream);
 
-/* Green-Gauss gradients of W = (u, v, w, T) from cell averages (face value
- * the mean of the two cells; ghost states on boundaries).  gradW [12][n_cell]. */
+/* Cell gradients of W = (u, v, w, T) from cell averages, gradW [12][n_cell]
+ * (row 3*var + dir), by the method phys->grad names:
+ *  - UCNS_GRAD_GREEN_GAUSS: face value the mean of the two cells, ghost state
+ *    on boundaries;
+ *  - UCNS_GRAD_LSQ: the least-squares gradients the paper's viscous terms use
+ *    (Sec. 2.1, Sec. 2.2), read as the linear fit over the face neighbours
+ *    with weights 1/|d|^2 (d the centroid offset, across periodic seams); a
+ *    boundary face enters as its ghost state at the centroid's mirror image
+ *    in the face plane, which carries the boundary condition into the fit
+ *    (no-slip: zero wall velocity; adiabatic wall and transmissive outflow:
+ *    zero normal derivative).  The fit's weights per face slot are built
+ *    with the mesh (UCNS_ERANK there if a cell's fit is singular).
+ * Any other phys->grad returns UCNS_EINVAL. */
 int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const double* U,
                    int precision, void* gradW, ucns_stream stream);
 

@@ -833,6 +833,39 @@ int build_operators(Mesh& m, int nt) {
 
 }  // namespace
 
+// Least-squares gradient weights: grad W_i = sum_slots G_slot (W_slot - W_i),
+// G = pinv(diag(s) D) diag(s) with rows d = the fdc offset seen from cell i
+// (owner->neighbour, negated from the neighbour's side; boundary faces the
+// mirrored centroid) and s = 1/|d|, i.e. weights 1/|d|^2.
+static int build_gradient_weights(Mesh& m) {
+    m.glsq.assign(size_t(m.nc) * kMaxFaces * 3, 0.0);
+    for (int64_t c = 0; c < m.nc; ++c) {
+        double D[kMaxFaces * 3], s[kMaxFaces], G[3 * kMaxFaces], rc = 0;
+        int slot[kMaxFaces], n = 0;
+        for (int lf = 0; lf < kMaxFaces; ++lf) {
+            const int32_t fs = m.c2f[c * kMaxFaces + lf];
+            if (fs < 0) continue;
+            const int64_t f = fs >> 1;
+            const double sg = (fs & 1) ? -1.0 : 1.0;
+            double dd = 0;
+            for (int a = 0; a < 3; ++a) {
+                D[n * 3 + a] = sg * m.fdc[3 * f + a];
+                dd += D[n * 3 + a] * D[n * 3 + a];
+            }
+            s[n] = 1.0 / std::sqrt(dd);
+            for (int a = 0; a < 3; ++a) D[n * 3 + a] *= s[n];
+            slot[n++] = lf;
+        }
+        if (n < 3 || !lsq_pinv(n, 3, D, s, G, &rc) || rc < 1e-10) {
+            set_error("cell " + std::to_string(c) + ": least-squares gradient fit is singular");
+            return UCNS_ERANK;
+        }
+        for (int j = 0; j < n; ++j)
+            for (int a = 0; a < 3; ++a) m.glsq[(size_t(c) * kMaxFaces + slot[j]) * 3 + a] = G[a * n + j];
+    }
+    return UCNS_OK;
+}
+
 int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads, Mesh** out) {
     if (!d || !o || !out) {
         set_error("null argument");
@@ -910,7 +943,8 @@ int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads,
             for (int a = 0; a < 3; ++a) m->fdc[3 * f + a] = 2.0 * dn * m->fnrm[3 * f + a];
         }
     }
-    rc = build_stencils(*m, nt);
+    rc = build_gradient_weights(*m);
+    if (rc == UCNS_OK) rc = build_stencils(*m, nt);
     if (rc == UCNS_OK) rc = build_operators(*m, nt);
     if (rc != UCNS_OK) {
         delete m;
@@ -959,8 +993,11 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     auto* ndc = reinterpret_cast<T*>(base + a.ndc);
     auto* hb = reinterpret_cast<T*>(base + a.hb);
     auto* ncen = reinterpret_cast<uint8_t*>(base + a.ncen);
+    auto* glsq = reinterpret_cast<T*>(base + a.glsq);
     for (int64_t c = 0; c < nc; ++c) {
         hb[c] = T(m.hb[c]);
+        for (int lf = 0; lf < NF; ++lf)
+            for (int k = 0; k < 3; ++k) glsq[(size_t(lf) * 3 + k) * nc + c] = T(m.glsq[(size_t(c) * kMaxFaces + lf) * 3 + k]);
         ncen[c] = uint8_t(m.ncen[c]);
         for (int lf = 0; lf < NF; ++lf) {
             const int32_t fs = m.c2f[c * kMaxFaces + lf];
@@ -1066,6 +1103,7 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.ndc = take(ts * NF * 3 * nc);
     a.hb = take(ts * nc);
     a.ncen = take(nc);
+    a.glsq = take(ts * NF * 3 * nc);
     a.bytes = off;
     if (image) {
         image->assign(a.bytes, 0);

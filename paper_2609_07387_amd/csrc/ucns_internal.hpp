@@ -27,6 +27,7 @@ struct Arena {
     size_t cnq = 0;  // [nfmax][nc] Gauss points of each of a cell's face slots (0: no face)
     size_t vol = 0, hdt = 0, fcell = 0, flf = 0, fnrm = 0, farea = 0, fw = 0, fdc = 0, fnq = 0;
     size_t nbr = 0, ndc = 0, hb = 0, ncen = 0;  // gate features: face neighbours, offsets, basis scale, stencil size
+    size_t glsq = 0;  // [nfmax][3][nc] least-squares gradient weights per face slot
     void* dev = nullptr;  // caller-owned device pointer after upload
 };
 
@@ -50,6 +51,7 @@ struct Mesh {
     std::vector<int32_t> c2f;     // [nc][kMaxFaces] = 2 f + side, -1 unused
     // ---- cells
     std::vector<double> vol, cen, hb, hdt;
+    std::vector<double> glsq;     // [nc][kMaxFaces][3] least-squares gradient weights
     double total_vol = 0;  // sum of vol, in cell order
     std::vector<double> moments;  // [nc][nmom] central moments
     int mom_deg = 0, nmom = 0;

@@ -275,11 +275,14 @@ struct GradArgs {
     const T* fnrm;
     const T* farea;
     const double* vol;
+    const T* glsq;  // [nfmax][3][nc] least-squares weights per face slot
     T* gradW;
 };
 
-// Green-Gauss: grad W_i = (1/|V_i|) sum_f (W_i + W_j)/2 n_f |S_f| (outward).
-template <class T>
+// Green-Gauss (LSQ false): grad W_i = (1/|V_i|) sum_f (W_i + W_j)/2 n_f |S_f|
+// (outward).  Least squares (LSQ true): grad W_i = sum_slots G_slot (W_j - W_i)
+// with the fit's weights built with the mesh; boundary slots take the ghost.
+template <class T, bool LSQ>
 __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<T> P, BcT<T> B) {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= A.nc) return;
@@ -308,9 +311,17 @@ __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<
             const int64_t f = f2[i] >= 0 ? f2[i] >> 1 : 0;
             const int side = f2[i] & 1;
             other[i] = A.fcell[2 * f + (1 - side)];
-            sa[i] = (side ? T(-0.5) : T(0.5)) * A.farea[f];
+            if constexpr (LSQ) {
+                // a slot beyond the cell's faces holds zero weights
+                const int slot = g0 + i < A.NF ? g0 + i : 0;
+                sa[i] = T(0);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) nr[i][a] = A.fnrm[3 * f + a];
+                for (int a = 0; a < 3; ++a) nr[i][a] = A.glsq[int64_t(3 * slot + a) * nc + c];
+            } else {
+                sa[i] = (side ? T(-0.5) : T(0.5)) * A.farea[f];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) nr[i][a] = A.fnrm[3 * f + a];
+            }
         }
         T uo[G][5];
 #pragma unroll
@@ -327,13 +338,13 @@ __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<
             prim_W(P, uo[i], Wo);
 #pragma unroll
             for (int var = 0; var < 4; ++var) {
-                const T wf = (Wi[var] + Wo[var]) * sa[i];
+                const T wf = LSQ ? Wo[var] - Wi[var] : (Wi[var] + Wo[var]) * sa[i];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) g[3 * var + a] += wf * nr[i][a];
             }
         }
     }
-    const T iv = T(1.0 / A.vol[c]);
+    const T iv = LSQ ? T(1) : T(1.0 / A.vol[c]);
 #pragma unroll
     for (int k = 0; k < 12; ++k) A.gradW[k * nc + c] = g[k] * iv;
 }
@@ -936,6 +947,14 @@ int ucns_mesh_operators(const ucns_mesh* mesh, int64_t cell, double* Bc, double*
     return UCNS_OK;
 }
 
+int ucns_mesh_gradient_weights(const ucns_mesh* mesh, int64_t cell, double* G) {
+    UCNS_REQUIRE(mesh && G, UCNS_EINVAL, "null argument");
+    const Mesh& m = *mesh->m;
+    UCNS_REQUIRE(cell >= 0 && cell < m.nc, UCNS_EINVAL, "cell out of range");
+    std::memcpy(G, &m.glsq[size_t(cell) * kMaxFaces * 3], sizeof(double) * kMaxFaces * 3);
+    return UCNS_OK;
+}
+
 int ucns_workspace_elems(const ucns_mesh* mesh, int64_t* face_state, int64_t* face_flux, int64_t* gradW,
                          int64_t* reduce_scratch) {
     UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
@@ -991,6 +1010,8 @@ int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
                    void* gradW, ucns_stream stream) {
     UCNS_REQUIRE(mesh && phys && U && gradW, UCNS_EINVAL, "null argument");
     UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(phys->grad == UCNS_GRAD_GREEN_GAUSS || phys->grad == UCNS_GRAD_LSQ, UCNS_EINVAL,
+                 "bad gradient method");
     UCNS_REQUIRE(aligned(U) && aligned(gradW), UCNS_EINVAL, "device buffers must be 256-byte aligned");
     const Mesh& m = *mesh->m;
     const Arena& ar = m.arena[precision];
@@ -1000,9 +1021,13 @@ int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
         using T = decltype(zero);
         GradArgs<T> A{U, m.nc, arena_ptr<int32_t>(ar, ar.c2f), m.nfmax, arena_ptr<int32_t>(ar, ar.fcell),
                       arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<double>(ar, ar.vol),
-                      static_cast<T*>(gradW)};
-        hipLaunchKernelGGL(gradients_kernel<T>, dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A, make_phys<T>(phys),
-                           make_bc<T>(bc));
+                      arena_ptr<T>(ar, ar.glsq), static_cast<T*>(gradW)};
+        if (phys->grad == UCNS_GRAD_LSQ)
+            hipLaunchKernelGGL((gradients_kernel<T, true>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A,
+                               make_phys<T>(phys), make_bc<T>(bc));
+        else
+            hipLaunchKernelGGL((gradients_kernel<T, false>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A,
+                               make_phys<T>(phys), make_bc<T>(bc));
     };
     if (precision == UCNS_F64)
         go(double(0));

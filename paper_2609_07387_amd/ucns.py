@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libucns.so")
 
 F64, F32 = 0, 1
 RUSANOV, HLLC = 0, 1
+GRADIENTS = {"green_gauss": 0, "least_squares": 1}  # ucns_phys.grad
 BC_NONE, BC_DIRICHLET, BC_TRANSMISSIVE, BC_WALL = 0, 1, 2, 3
 MAX_FACES, MAX_DIR = 6, 16
 
@@ -28,7 +29,7 @@ EXPORTS = [
     "ucns_workspace_elems", "ucns_dt", "ucns_reconstruct", "ucns_gradients", "ucns_face_flux", "ucns_residual",
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
     "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
-    "ucns_residual_ssp54_stage",
+    "ucns_residual_ssp54_stage", "ucns_mesh_gradient_weights",
 ]
 
 
@@ -46,7 +47,7 @@ class ReconOpts(C.Structure):
 
 class Phys(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("reynolds", C.c_double), ("prandtl", C.c_double),
-                ("viscous", C.c_int), ("flux", C.c_int)]
+                ("viscous", C.c_int), ("flux", C.c_int), ("grad", C.c_int)]
 
 
 class BC(C.Structure):
@@ -85,6 +86,7 @@ def lib():
         L.ucns_mesh_cell_geometry.argtypes = [vp, vp, vp, vp]
         L.ucns_mesh_stencil.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ucns_mesh_operators.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ucns_mesh_gradient_weights.argtypes = [vp, i64, vp]
         L.ucns_workspace_elems.argtypes = [vp, vp, vp, vp, vp]
         L.ucns_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp, vp, vp]
         L.ucns_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, vp, vp]
@@ -130,8 +132,13 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def phys(gamma=1.4, mach=0.1, reynolds=1600.0, prandtl=0.72, viscous=False, flux="hllc") -> Phys:
-    return Phys(gamma, mach, reynolds, prandtl, int(bool(viscous)), HLLC if flux == "hllc" else RUSANOV)
+def phys(gamma=1.4, mach=0.1, reynolds=1600.0, prandtl=0.72, viscous=False, flux="hllc",
+         gradients="green_gauss") -> Phys:
+    """gradients: "green_gauss" or "least_squares" (the viscous cell gradients)."""
+    if gradients not in GRADIENTS:
+        raise ValueError(f"gradients: {gradients!r}")
+    return Phys(gamma, mach, reynolds, prandtl, int(bool(viscous)), HLLC if flux == "hllc" else RUSANOV,
+                GRADIENTS[gradients])
 
 
 def bc(entries=None) -> BC:
@@ -217,6 +224,12 @@ class Mesh:
         Phi = np.zeros((self.nfmax, self.qmax, K))
         check(lib().ucns_mesh_operators(self.h, int(cell), _np(Bc), _np(Bd), _np(O), _np(Phi)))
         return dict(Bc=Bc, Bd=[Bd[s, :, :len(dirs[s])].copy() for s in range(len(dirs))], O=O, Phi=Phi)
+
+    def gradient_weights(self, cell):
+        """Least-squares gradient weights G[6][3] of one cell by local face slot."""
+        G = np.zeros((MAX_FACES, 3))
+        check(lib().ucns_mesh_gradient_weights(self.h, int(cell), _np(G)))
+        return G
 
     # ---- device
     def upload(self, precision, device="cuda"):

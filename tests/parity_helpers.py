@@ -95,7 +95,7 @@ def oracle_stage(om, ph, U, bcs=None, gate_mask=None):
 
 
 def as_oracle_phys(ph):
-    return oracle.Phys(ph.gamma, ph.mach, ph.reynolds, ph.prandtl, ph.viscous, ph.flux)
+    return oracle.Phys(ph.gamma, ph.mach, ph.reynolds, ph.prandtl, ph.viscous, ph.flux, ph.grad)
 
 
 def as_oracle_bc(b):

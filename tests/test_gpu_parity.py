@@ -22,7 +22,7 @@ TOL_STEPS = 1e-12   # relative L-inf after the stated steps
 # numbers near 1e9 (thin prism layers under tetrahedra): the library's and the
 # oracle's operators, both correct, agree to about 1e-7 there (host-build
 # test), and so do the states built from them.
-TOL_CASE = {"mixed_bl_ns": 1e-6}
+TOL_CASE = {"mixed_bl_ns": 1e-6, "mixed_bl_ns_lsq": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -48,6 +48,13 @@ CASES = {
     # hexahedra, prisms, pyramids and tetrahedra; inflow, outflow, no-slip wall and far field
     "mixed_bl_ns": (lambda: inputs.mixed_bl_mesh((9, 5, 6), (2.25, 1.0, 0.75), (2, 2), 2, 1.2, 0.15, 0.05), 2,
                     dict(flux="hllc", viscous=True, mach=0.5, reynolds=1000.0), "bl", "bl"),
+    # least-squares viscous gradients: jittered periodic tetrahedra, and the
+    # mixed mesh whose wall and inflow/outflow ghosts enter the fit
+    "tet4_p2_hllc_ns_lsq": (lambda: inputs.kuhn_tet_mesh((4, 4, 4), (2 * math.pi,) * 3, (True,) * 3, 0.15, seed=0),
+                            2, dict(flux="hllc", viscous=True, gradients="least_squares"), "tgv_noise", None),
+    "mixed_bl_ns_lsq": (lambda: inputs.mixed_bl_mesh((9, 5, 6), (2.25, 1.0, 0.75), (2, 2), 2, 1.2, 0.15, 0.05), 2,
+                        dict(flux="hllc", viscous=True, mach=0.5, reynolds=1000.0, gradients="least_squares"),
+                        "bl", "bl"),
 }
 
 
@@ -112,7 +119,8 @@ def test_stage_intermediates_fp64(torch_cuda, name):
 
 
 @pytest.mark.parametrize("name,steps", [("hex16_p2_rusanov", 10), ("hex7_p2_hllc_ns", 10), ("tet4_p2_hllc", 5),
-                                        ("tet3_p3_hllc", 3), ("tet_shock_box", 5), ("mixed_bl_ns", 5)])
+                                        ("tet3_p3_hllc", 3), ("tet_shock_box", 5), ("mixed_bl_ns", 5),
+                                        ("tet4_p2_hllc_ns_lsq", 5), ("mixed_bl_ns_lsq", 5)])
 def test_steps_fp64(torch_cuda, name, steps):
     """SSP-RK3 steps at CFL 0.5: relative L-inf <= 1e-12 against the oracle
     (the 16^3 hex Rusanov case is the paper-scale TGV parity workload)."""
@@ -283,6 +291,23 @@ def test_fp32_variant_accuracy(torch_cuda):
     Uo, _, _ = om.run(U, as_oracle_phys(ph), 0.5, 10)
     e_run = grouped_rel_linf(Ug, Uo)
     print(f"[gpu] fp32 stage R err {e_stage:.2e}, 10-step U err {e_run:.2e}", flush=True)
+    assert e_run < 1e-5
+
+
+def test_fp32_lsq_gradients(torch_cuda):
+    """FP32 least-squares gradients and a short FP32 run on jittered
+    tetrahedra stay within single-precision error of the FP64 oracle."""
+    m, order, ph, U, bcs = _setup("tet4_p2_hllc_ns_lsq")
+    lm = ucns.Mesh(m, order=order)
+    om = oracle.OracleMesh(m, order=order)
+    _, gw, _, _, _ = gpu_stage(lm, ph, U, ucns.F32)
+    og = om.gradients(U, as_oracle_phys(ph))
+    e_g = np.abs(gw - og).max() / np.abs(og).max()
+    Ug, _, _ = gpu_run(lm, ph, U, ucns.F32, 10, 0.5)
+    Uo, _, _ = om.run(U, as_oracle_phys(ph), 0.5, 10)
+    e_run = grouped_rel_linf(Ug, Uo)
+    print(f"[gpu] fp32 lsq gradient err {e_g:.2e}, 10-step U err {e_run:.2e}", flush=True)
+    assert e_g < 1e-4
     assert e_run < 1e-5
 
 

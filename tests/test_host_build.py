@@ -100,6 +100,43 @@ def test_host_build_matches_oracle(name):
     assert worst < OP_TOL.get(name, 1e-12), worst
 
 
+@pytest.mark.parametrize("name", list(_meshes().keys()))
+def test_lsq_gradient_weights_match_oracle(name):
+    """The library's least-squares gradient weights (built with the mesh)
+    applied on the host to a smooth random field give the oracle's
+    least-squares gradients in every cell.  Without boundary conditions the
+    boundary ghost is the cell itself, so a boundary slot adds no difference
+    but its mirrored row still shapes the fit."""
+    _lib_or_skip()
+    m, order = _meshes()[name]
+    lm = ucns.Mesh(m, order=order)
+    om = oracle.OracleMesh(m, order=order)
+    _, cen, _ = om.cell_data()
+    rng = np.random.default_rng(21)
+    k = rng.normal(size=(3, 3))
+    rho = 1.0 + 0.2 * np.sin(cen @ k[0])
+    vel = 0.3 * np.cos(cen @ k[1:].T).T
+    vel = np.vstack([vel, 0.1 * np.sin(cen[:, 0])])
+    p = 50.0 + np.cos(cen @ k[2])
+    U = np.vstack([rho, rho * vel, p / 0.4 + 0.5 * rho * (vel ** 2).sum(0)])
+    W = np.vstack([vel, 1.4 * 0.01 * p / rho])
+    og = om.gradients(U, oracle.phys(viscous=True, gradients="least_squares"))
+    c2f, fcell, _, _ = lm.faces()
+    lg = np.zeros_like(og)
+    for c in range(lm.n_cell):
+        G = lm.gradient_weights(c)
+        for lf in range(6):
+            if c2f[c, lf] < 0:
+                assert not G[lf].any()
+                continue
+            f, side = c2f[c, lf] >> 1, c2f[c, lf] & 1
+            j = fcell[f, 1 - side]
+            if j >= 0:
+                lg[:, c] += (np.outer(W[:, j] - W[:, c], G[lf])).ravel()
+    err = np.abs(lg - og).max() / np.abs(og).max()
+    assert err < 1e-12, err
+
+
 def test_host_build_errors():
     _lib_or_skip()
     m = inputs.periodic_hex_mesh(4)
