@@ -51,7 +51,9 @@ typedef struct {
 
 /* Boundary condition per face tag (1..7): kind 0 none, 1 Dirichlet state,
  * 2 transmissive (ghost = interior cell average), 3 no-slip adiabatic wall
- * (ghost = interior point state with mirrored velocity). */
+ * (ghost = interior point state with mirrored velocity), 4 symmetry plane
+ * (ghost = mirror image of the interior point state in the face plane; the
+ * face's viscous gradient averages the cell's with its mirror image). */
 typedef struct {
     int kind[8];
     double state[8][5];

@@ -171,11 +171,14 @@ static void prim_W(const oracle_phys* ph, const double* u, double* W) {
 
 /* Ghost state across a boundary face (tag kinds in oracle.h): Dirichlet takes
  * the prescribed state; the no-slip wall mirrors the full velocity of the
- * interior point state `in`; transmissive (zero-gradient) outflow copies the
- * interior cell's average `avg` (zeroth-order extrapolation: copying the
+ * interior point state `in`; the symmetry plane is the mirror image of `in`
+ * in the face plane (unit normal n): density and energy kept, momentum
+ * reflected by M = I - 2 n n^T; transmissive (zero-gradient) outflow copies
+ * the interior cell's average `avg` (zeroth-order extrapolation: copying the
  * reconstructed point value instead feeds a one-sided extrapolation back
  * into the boundary cell). */
-static void ghost_state(const oracle_bc* bc, int tag, const double* in, const double* avg, double* out) {
+static void ghost_state(const oracle_bc* bc, int tag, const double* in, const double* avg, const double* n,
+                        double* out) {
     int kind = bc ? bc->kind[tag] : 2;
     if (kind == 1) {
         memcpy(out, bc->state[tag], sizeof(double) * NV);
@@ -184,6 +187,13 @@ static void ghost_state(const oracle_bc* bc, int tag, const double* in, const do
         out[1] = -in[1];
         out[2] = -in[2];
         out[3] = -in[3];
+        out[4] = in[4];
+    } else if (kind == 4) {
+        out[0] = in[0];
+        for (int a = 0; a < 3; ++a) {
+            out[1 + a] = 0.0;
+            for (int b = 0; b < 3; ++b) out[1 + a] += ((a == b ? 1.0 : 0.0) - 2.0 * n[a] * n[b]) * in[1 + b];
+        }
         out[4] = in[4];
     } else {
         memcpy(out, avg, sizeof(double) * NV);
@@ -268,7 +278,7 @@ int oracle_gradients(const oracle_mesh* m, const oracle_phys* ph, const oracle_b
             if (other >= 0) {
                 for (int v = 0; v < NV; ++v) uo[v] = U[v * nc + other];
             } else {
-                ghost_state(bc, (int)(-1 - other), ui, ui, uo);
+                ghost_state(bc, (int)(-1 - other), ui, ui, n, uo);
             }
             prim_W(ph, uo, Wo);
             for (int var = 0; var < 4; ++var)
@@ -318,7 +328,7 @@ int oracle_gradients_lsq(const oracle_mesh* m, const oracle_phys* ph, const orac
                 double dn = 0;
                 for (int a = 0; a < 3; ++a) dn += (m->fcen[3 * f + a] - m->cen[3 * c + a]) * m->fnrm[3 * f + a];
                 for (int a = 0; a < 3; ++a) d[a] = 2.0 * dn * m->fnrm[3 * f + a];
-                ghost_state(bc, (int)(-1 - other), ui, ui, uo);
+                ghost_state(bc, (int)(-1 - other), ui, ui, m->fnrm + 3 * f, uo);
             }
             prim_W(ph, uo, Wo);
             double w = 1.0 / (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -351,6 +361,30 @@ static int cell_gradients(const oracle_mesh* m, const oracle_phys* ph, const ora
 }
 
 /* ------------------------------------------------------------ face flux */
+
+/* Gradient of the mirror image of a flow in the plane with unit normal n:
+ * with M = I - 2 n n^T the mirrored velocity field u'(x) = M u(Mx) has
+ * gradient M G M (G_ij = du_i/dx_j), the mirrored temperature gradient M g_T.
+ * A symmetry face averages the cell's gradient with this one. */
+static void mirror_gradient(const double* g, const double* n, double* gm) {
+    double M[3][3], MG[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[a][b] = (a == b ? 1.0 : 0.0) - 2.0 * n[a] * n[b];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            MG[i][j] = 0.0;
+            for (int k = 0; k < 3; ++k) MG[i][j] += M[i][k] * g[3 * k + j];
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            gm[3 * i + j] = 0.0;
+            for (int k = 0; k < 3; ++k) gm[3 * i + j] += MG[i][k] * M[k][j];
+        }
+    for (int j = 0; j < 3; ++j) {
+        gm[9 + j] = 0.0;
+        for (int k = 0; k < 3; ++k) gm[9 + j] += M[j][k] * g[9 + k];
+    }
+}
 
 /* Viscous flux F_v . n at one quadrature point (Newtonian stress with
  * Stokes' hypothesis, Fourier heat flux).  Reading of the closure the paper
@@ -405,7 +439,11 @@ int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_b
                 for (int a = 0; a < 3; ++a) d[a] = m->cen[3 * cR + a] + m->fshift[3 * f + a] - m->cen[3 * cL + a];
                 Lint = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             } else {
-                memcpy(gR, gL, sizeof gL);
+                if (bc && bc->kind[-1 - cR] == 4) {
+                    mirror_gradient(gL, n, gR);
+                } else {
+                    memcpy(gR, gL, sizeof gL);
+                }
                 double d = 0;
                 for (int a = 0; a < 3; ++a) d += (m->fcen[3 * f + a] - m->cen[3 * cL + a]) * n[a];
                 Lint = 2.0 * fabs(d);
@@ -418,7 +456,7 @@ int oracle_face_flux(const oracle_mesh* m, const oracle_phys* ph, const oracle_b
             if (cR >= 0) {
                 uR = face_state + (((size_t)f * 2 + 1) * OR_QM + q) * NV;
             } else {
-                ghost_state(bc, (int)(-1 - cR), uL, uavg, uRb);
+                ghost_state(bc, (int)(-1 - cR), uL, uavg, n, uRb);
                 uR = uRb;
             }
             double F[NV];

@@ -684,6 +684,65 @@ def test_lsq_gradients_reduce_to_central_differences_on_uniform_hex():
     assert np.abs(g - gg).max() < 1e-12 * scale.max()
 
 
+def _slab(kind):
+    """Periodic in x and z, bounded in y by planes at y = 0 (tag 3) and
+    y = 1 (tag 4); the jittered tetrahedra keep those planes flat."""
+    if kind == "hex":
+        return inputs.hex_box_mesh((5, 4, 5), (1.0, 1.0, 1.0), (True, False, True))
+    return inputs.kuhn_tet_mesh((4, 4, 4), (1.0, 1.0, 1.0), (True, False, True), 0.15, seed=8)
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet"])
+def test_symmetry_plane_keeps_a_parallel_stream(kind):
+    """A uniform stream parallel to symmetry planes is an exact steady
+    solution of the Navier-Stokes equations: the residual vanishes to
+    rounding with either gradient method.  With no-slip walls in place of
+    the planes the same stream feels the walls' shear (contrast)."""
+    m = _slab(kind)
+    om = oracle.OracleMesh(m, order=2)
+    U = inputs.uniform_state(m, 1.2, [0.4, 0.0, 0.2], 1.5)
+    sym = oracle.bc({3: (4, None), 4: (4, None)})
+    wall = oracle.bc({3: (3, None), 4: (3, None)})
+    for grad in ("green_gauss", "least_squares"):
+        for flux in ("hllc", "rusanov"):
+            ph = oracle.phys(flux=flux, viscous=True, reynolds=50.0, gradients=grad)
+            assert np.abs(om.rhs(U, ph, sym)).max() <= 1e-13 * np.abs(U).max()
+            assert np.abs(om.rhs(U, ph, wall)[1]).max() > 1e-3
+
+
+@pytest.mark.parametrize("grad", ["green_gauss", "least_squares"])
+def test_symmetry_plane_passes_no_mass_energy_or_shear(grad):
+    """Mirror-image boundary: no mass, energy or tangential momentum crosses
+    a symmetry plane (the ghost reverses the normal velocity only, and the
+    face gradient, averaged with its mirror image, carries no shear stress or
+    heat flux).  On the slab, periodic along the planes, total mass, energy
+    and x- and z-momentum stay constant to rounding over viscous steps while
+    the y-momentum changes (pressure on the planes); no-slip walls change the
+    tangential momentum (contrast)."""
+    m = _slab("tet")
+    om = oracle.OracleMesh(m, order=2)
+    vol, cen, _ = om.cell_data()
+    x, y, z = cen.T
+    two_pi = 2 * math.pi
+    rho = 1.0 + 0.1 * np.sin(two_pi * x) * np.cos(math.pi * y)
+    vel = np.stack([0.3 + 0.1 * np.cos(two_pi * z) * y, 0.2 * np.sin(two_pi * x) + 0.1,
+                    0.1 * np.sin(two_pi * (x + z)) * (1 - y)])
+    p = 1.0 / (1.4 * 0.25) + 0.05 * np.cos(two_pi * z)
+    U = np.vstack([rho, rho * vel, p / 0.4 + 0.5 * rho * (vel ** 2).sum(0)])
+    ph = oracle.phys(flux="hllc", viscous=True, mach=0.5, reynolds=20.0, gradients=grad)
+    tot0 = (U * vol).sum(1)
+    Us, _, _ = om.run(U, ph, 0.5, 4, oracle.bc({3: (4, None), 4: (4, None)}))
+    tot = (Us * vol).sum(1)
+    scale = np.abs(U * vol).sum(1)
+    for v in (0, 1, 3, 4):
+        assert abs(tot[v] - tot0[v]) < 1e-13 * scale[v], v
+    assert abs(tot[2] - tot0[2]) > 1e-6 * scale[2]
+    Uw, _, _ = om.run(U, ph, 0.5, 4, oracle.bc({3: (3, None), 4: (3, None)}))
+    totw = (Uw * vol).sum(1)
+    assert abs(totw[1] - tot0[1]) > 1e-6 * scale[1]
+    assert abs(totw[0] - tot0[0]) < 1e-13 * scale[0]
+
+
 def test_tgv_initial_diagnostics_converge():
     """TGV initial field (Sec. 4.2): <|u|^2/2> = 1/8, <|curl u|^2> = 3/4, so
     eps_s(0) = 3 mu / 4 = 4.6875e-4 at Re 1600; div u = 0 (eps_d -> 0)."""
