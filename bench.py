@@ -131,6 +131,8 @@ def cpu_baseline(seconds=12.0):
 
 
 GRAD_NAME = {"green_gauss": "Green-Gauss", "least_squares": "least-squares"}
+RK_NAME = {"ssp3": "SSP-RK3", "ssp54": "five-stage fourth-order SSP-RK"}
+STAGES = {"ssp3": 3, "ssp54": 5}
 
 
 def main():
@@ -148,6 +150,8 @@ def main():
                          "element boundary-layer box, FP64 plain and FP32 + gate throughput and memory")
     ap.add_argument("--gradients", choices=("green_gauss", "least_squares"), default="green_gauss",
                     help="viscous cell gradients of the Navier-Stokes workloads")
+    ap.add_argument("--integrator", choices=("ssp3", "ssp54"), default="ssp3",
+                    help="tgv_hex_p2: SSP-RK3 (3 stages) or the five-stage fourth-order SSP-RK")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
@@ -182,10 +186,10 @@ def main():
         runs.append(("fp32_gate", ucns.F32, mlp))
     variants = {}
     for name, prec, net in runs:
-        solver = ucns.Solver(lm, ph, prec, cfl=0.5, mlp=net)
+        solver = ucns.Solver(lm, ph, prec, cfl=0.5, mlp=net, integrator=args.integrator)
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
-        rate = nc * 3 * args.steps / (ms / 1e3)
+        rate = nc * STAGES[args.integrator] * args.steps / (ms / 1e3)
         rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns, solver.mlp_image,
                          solver.ws.mask_out)
         frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
@@ -215,7 +219,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if head != "fp64_plain" else "f64", "data": "synthetic",
         "config": {"workload": f"TGV {args.n}^3 periodic hex, P2 CWENOZ, HLLC, Navier-Stokes Re 1600 Mach 0.1, "
-                               f"{GRAD_NAME[args.gradients]} gradients, SSP-RK3 CFL 0.5, per-step KE",
+                               f"{GRAD_NAME[args.gradients]} gradients, {RK_NAME[args.integrator]} CFL 0.5, "
+                               "per-step KE",
                    "cells": nc, "faces": lm.n_face,
                    "variant": head + (" (FP32 reconstruction/flux, FP64 state/RK/reductions, BF16 gate network)"
                                       if head == "fp32_gate" else "")},

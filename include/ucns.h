@@ -63,7 +63,7 @@ enum { UCNS_TET = 4, UCNS_PYR = 5, UCNS_PRISM = 6, UCNS_HEX = 8 };
 enum { UCNS_F64 = 0, UCNS_F32 = 1 };
 enum { UCNS_RUSANOV = 0, UCNS_HLLC = 1 };
 enum { UCNS_GRAD_GREEN_GAUSS = 0, UCNS_GRAD_LSQ = 1 };
-enum { UCNS_BC_NONE = 0, UCNS_BC_DIRICHLET = 1, UCNS_BC_TRANSMISSIVE = 2, UCNS_BC_WALL = 3 };
+enum { UCNS_BC_NONE = 0, UCNS_BC_DIRICHLET = 1, UCNS_BC_TRANSMISSIVE = 2, UCNS_BC_WALL = 3, UCNS_BC_SYMMETRY = 4 };
 
 /* Mesh description (host arrays, read during ucns_mesh_build only).
  * Cell vertex order: VTK for tet and hex; prism: bottom triangle (0,1,2)
@@ -104,7 +104,19 @@ typedef struct {
     int grad;           /* viscous cell gradients: UCNS_GRAD_GREEN_GAUSS (0) or UCNS_GRAD_LSQ */
 } ucns_phys;
 
-/* Boundary condition per face tag 1..7 (index 0 unused). */
+/* Boundary condition per face tag 1..7 (index 0 unused); the paper lists the
+ * conditions (Sec. 3.6, boundary conditions) but not their form.  The ghost
+ * state across a boundary face, at each Gauss point:
+ *  - UCNS_BC_DIRICHLET: state[tag] (inflow, far field);
+ *  - UCNS_BC_TRANSMISSIVE (also any other kind): the owner's cell average;
+ *  - UCNS_BC_WALL (no-slip, adiabatic): the interior point state with its
+ *    velocity reversed;
+ *  - UCNS_BC_SYMMETRY: the interior point state with its momentum reflected
+ *    in the face plane, m - 2 (m . n) n; the viscous face gradient is the
+ *    mean of the cell's gradient and its mirror image (no shear stress, no
+ *    heat flux through the plane).  Other kinds use the cell's own gradient.
+ * Cell gradients use the same ghosts with the cell average as the interior
+ * state. */
 typedef struct {
     int kind[8];
     double state[8][5]; /* conserved state for UCNS_BC_DIRICHLET */

@@ -230,15 +230,26 @@ __device__ __forceinline__ void prim_W(const PhysT<T>& P, const T* u, T* W) {
     W[3] = P.gM2 * pressure(P, u) * ir;
 }
 
+// Kind of a boundary tag, selected with compile-time indices (a run-time
+// index into the by-value table would move it to scratch memory).
+template <class T>
+__device__ __forceinline__ int bc_kind(const BcT<T>& B, int tag) {
+    int kind = UCNS_BC_TRANSMISSIVE;
+#pragma unroll
+    for (int t = 1; t < 8; ++t)
+        if (t == tag) kind = B.kind[t];
+    return kind;
+}
+
 // Ghost state across a boundary face: Dirichlet takes the prescribed state,
 // the no-slip wall mirrors the velocity of the interior point state `in`,
-// transmissive outflow copies the interior cell average `avg` (zeroth-order
-// extrapolation; copying the reconstructed point value would feed the
-// boundary cell's one-sided extrapolation back into it).
+// the symmetry plane reflects its momentum in the face plane (n the unit
+// face normal; either orientation), transmissive outflow copies the interior
+// cell average `avg` (zeroth-order extrapolation; copying the reconstructed
+// point value would feed the boundary cell's one-sided extrapolation back
+// into it).
 template <class T>
-__device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, const T* avg, T* out) {
-    // select the tag's entry with compile-time indices (a run-time index into
-    // the by-value table would move it to scratch memory)
+__device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, const T* avg, const T* n, T* out) {
     int kind = UCNS_BC_TRANSMISSIVE;
     T st[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
@@ -256,6 +267,12 @@ __device__ __forceinline__ void ghost(const BcT<T>& B, int tag, const T* in, con
         out[1] = -in[1];
         out[2] = -in[2];
         out[3] = -in[3];
+        out[4] = in[4];
+    } else if (kind == UCNS_BC_SYMMETRY) {
+        const T mn2 = T(2) * (in[1] * n[0] + in[2] * n[1] + in[3] * n[2]);
+        out[0] = in[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[1 + a] = in[1 + a] - mn2 * n[a];
         out[4] = in[4];
     } else {
 #pragma unroll
@@ -333,7 +350,15 @@ __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<
 #pragma unroll
         for (int i = 0; i < G; ++i) {
             if (f2[i] < 0) continue;
-            if (other[i] < 0) ghost(B, -1 - other[i], ui, ui, uo[i]);
+            if (other[i] < 0) {
+                // the symmetry ghost needs the face normal, which the
+                // least-squares weights do not carry (boundary faces only)
+                T nb[3];
+                const int64_t fb = f2[i] >> 1;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) nb[a] = LSQ ? A.fnrm[3 * fb + a] : nr[i][a];
+                ghost(B, -1 - other[i], ui, ui, nb, uo[i]);
+            }
             T Wo[4];
             prim_W(P, uo[i], Wo);
 #pragma unroll
@@ -400,6 +425,30 @@ __device__ void viscous_flux(const PhysT<T>& P, const Prim<T>& L, const Prim<T>&
     Fv[4] = e;
 }
 
+// Face gradient on a symmetry plane: the mean of the cell's gradient and its
+// mirror image.  With velocity gradient G (G_ij = du_i/dx_j) and mirror
+// M = I - 2 n n^T, (G + M G M)/2 = G - n (n^T G) - (G n) n^T + 2 (n^T G n) n n^T
+// (the normal-tangential couplings vanish: no shear stress on the plane);
+// the temperature gradient loses its normal part (no heat flux).
+template <class T>
+__device__ __forceinline__ void symmetry_gradient(T* G, const T* n) {
+    T a[3], b[3], s = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        a[j] = n[0] * G[j] + n[1] * G[3 + j] + n[2] * G[6 + j];
+        b[j] = G[3 * j] * n[0] + G[3 * j + 1] * n[1] + G[3 * j + 2] * n[2];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s += n[j] * b[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) G[3 * i + j] += -n[i] * a[j] - b[i] * n[j] + T(2) * s * n[i] * n[j];
+    const T gn = G[9] * n[0] + G[10] * n[1] + G[11] * n[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) G[9 + j] -= gn * n[j];
+}
+
 // One lane per face; the Gauss-point sum is the lane's own loop.  Adjacent
 // lanes take adjacent faces (numbered by owner), so each point-state load of
 // a wave reads a few contiguous runs of the owners' and neighbours' slots,
@@ -435,6 +484,7 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         for (int k = 0; k < 12; ++k) G0[k] = T(0.5) * (A.gradW[k * nc + cL] + A.gradW[k * nc + cRg]);
         const T dx = A.fdc[3 * f], dy = A.fdc[3 * f + 1], dz = A.fdc[3 * f + 2];
         pen = T(4.0 / 3.0) / sqrt(dx * dx + dy * dy + dz * dz);
+        if (cR < 0 && bc_kind(B, -1 - cR) == UCNS_BC_SYMMETRY) symmetry_gradient(G0, n);
     }
     T F[5] = {T(0), T(0), T(0), T(0), T(0)};
     // FP32 loads the next point's two states while it evaluates this one's
@@ -463,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         } else {
             load_point(q, uL, uR);
         }
-        if (cR < 0) ghost(B, -1 - cR, uL, avg, uR);
+        if (cR < 0) ghost(B, -1 - cR, uL, avg, n, uR);
         const Prim<T> qL = prim(P, uL, n), qR = prim(P, uR, n);
         if (P.flux == UCNS_HLLC)
             hllc_flux(qL, qR, uL, uR, n, Fq);

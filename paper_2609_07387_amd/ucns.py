@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libucns.so")
 F64, F32 = 0, 1
 RUSANOV, HLLC = 0, 1
 GRADIENTS = {"green_gauss": 0, "least_squares": 1}  # ucns_phys.grad
-BC_NONE, BC_DIRICHLET, BC_TRANSMISSIVE, BC_WALL = 0, 1, 2, 3
+BC_NONE, BC_DIRICHLET, BC_TRANSMISSIVE, BC_WALL, BC_SYMMETRY = 0, 1, 2, 3, 4
 MAX_FACES, MAX_DIR = 6, 16
 
 # Names declared in include/ucns.h (checked by the test-suite against the

@@ -55,7 +55,27 @@ CASES = {
     "mixed_bl_ns_lsq": (lambda: inputs.mixed_bl_mesh((9, 5, 6), (2.25, 1.0, 0.75), (2, 2), 2, 1.2, 0.15, 0.05), 2,
                         dict(flux="hllc", viscous=True, mach=0.5, reynolds=1000.0, gradients="least_squares"),
                         "bl", "bl"),
+    # jittered tetrahedra between two symmetry planes (periodic along them),
+    # a viscous flow with normal velocity at the planes
+    "tet_slab_sym_ns": (lambda: inputs.kuhn_tet_mesh((4, 4, 4), (1.0, 1.0, 1.0), (True, False, True), 0.15, seed=8),
+                        2, dict(flux="hllc", viscous=True, mach=0.5, reynolds=20.0), "slab", "sym"),
+    "tet_slab_sym_ns_lsq": (lambda: inputs.kuhn_tet_mesh((4, 4, 4), (1.0, 1.0, 1.0), (True, False, True), 0.15,
+                                                         seed=8), 2,
+                            dict(flux="hllc", viscous=True, mach=0.5, reynolds=20.0, gradients="least_squares"),
+                            "slab", "sym"),
 }
+
+
+def _slab_state(x):
+    """Smooth state with normal velocity at the planes y = 0 and y = 1."""
+    X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+    t = 2 * math.pi
+    rho = 1.0 + 0.1 * np.sin(t * X) * np.cos(math.pi * Y)
+    u = 0.3 + 0.1 * np.cos(t * Z) * Y
+    v = 0.2 * np.sin(t * X) + 0.1
+    w = 0.1 * np.sin(t * (X + Z)) * (1 - Y)
+    p = 1.0 / (1.4 * 0.25) + 0.05 * np.cos(t * Z)
+    return np.stack([rho, rho * u, rho * v, rho * w, p / 0.4 + 0.5 * rho * (u * u + v * v + w * w)], axis=-1)
 
 
 def _setup(name):
@@ -68,6 +88,8 @@ def _setup(name):
         U = inputs.tgv_initial(m, noise_seed=1000)
     elif u0 == "bl":
         U = inputs.bl_initial(m, mach=pk["mach"])
+    elif u0 == "slab":
+        U = inputs.cell_averages(m, _slab_state).T.copy()
     else:
         U = inputs.shock_box_initial(m)
     bcs = None
@@ -79,6 +101,8 @@ def _setup(name):
         free = inputs.bl_initial(m, mach=pk["mach"], amp=0.0)[:, 0]
         bcs = ucns.bc({1: (ucns.BC_DIRICHLET, free), 2: (ucns.BC_TRANSMISSIVE, None), 3: (ucns.BC_WALL, None),
                        4: (ucns.BC_DIRICHLET, free)})
+    elif bcname == "sym":
+        bcs = ucns.bc({3: (ucns.BC_SYMMETRY, None), 4: (ucns.BC_SYMMETRY, None)})
     return m, order, ph, U, bcs
 
 
@@ -120,7 +144,8 @@ def test_stage_intermediates_fp64(torch_cuda, name):
 
 @pytest.mark.parametrize("name,steps", [("hex16_p2_rusanov", 10), ("hex7_p2_hllc_ns", 10), ("tet4_p2_hllc", 5),
                                         ("tet3_p3_hllc", 3), ("tet_shock_box", 5), ("mixed_bl_ns", 5),
-                                        ("tet4_p2_hllc_ns_lsq", 5), ("mixed_bl_ns_lsq", 5)])
+                                        ("tet4_p2_hllc_ns_lsq", 5), ("mixed_bl_ns_lsq", 5), ("tet_slab_sym_ns", 5),
+                                        ("tet_slab_sym_ns_lsq", 5)])
 def test_steps_fp64(torch_cuda, name, steps):
     """SSP-RK3 steps at CFL 0.5: relative L-inf <= 1e-12 against the oracle
     (the 16^3 hex Rusanov case is the paper-scale TGV parity workload)."""
