@@ -171,5 +171,16 @@ def test_entry_points_reject_null_arguments():
         L.ucns_reconstruct(lm.h, C.byref(ph), None, ucns.F64, None, None, None, None, None),
         L.ucns_dt(lm.h, C.byref(ph), None, 0.5, None, None, None),
         L.ucns_mlp_pack(None, None, None),
+        L.ucns_gradients(lm.h, C.byref(ph), None, None, ucns.F64, None, None),
+        L.ucns_mesh_gradient_weights(lm.h, 0, None),
     ]
     assert rcs == [-1] * len(rcs), rcs
+    # an unknown gradient method is refused before any device state is looked at
+    buf = (C.c_double * 64)()  # 512 bytes: holds a 256-byte aligned address; never dereferenced
+    aligned = C.c_void_p((C.addressof(buf) + 255) & ~255)
+    bad = ucns.phys(flux="hllc", viscous=True)
+    bad.grad = 7
+    assert L.ucns_gradients(lm.h, C.byref(bad), None, aligned, ucns.F64, aligned, None) == -1
+    assert "gradient method" in L.ucns_last_error().decode()
+    G = np.zeros((6, 3))
+    assert L.ucns_mesh_gradient_weights(lm.h, lm.n_cell, G.ctypes.data_as(C.c_void_p)) == -1
