@@ -9,8 +9,9 @@ in HBM when the timed region starts.
 
 Prints one JSON line: the headline variant's cell-stage updates/s, both
 variants (FP64 plain and FP32 reconstruction/flux), the roofline of the
-dominant kernel (reconstruction) timed with HIP events on its own stream, and
-the FP64 CPU oracle timed on the host cores on a bounded sample.
+dominant kernel (reconstruction) timed with HIP events on its launch stream
+around each of its calls in a replay of the timed steps, and the FP64 CPU
+oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import json
@@ -81,20 +82,22 @@ def time_steps(solver, U, steps, warmup, torch):
     return e0.elapsed_time(e1), wall
 
 
-def time_recon(lm, ph, U, precision, fs, flags, reps, torch, ucns, mlp_image=None, mask_out=None):
-    """Mean duration of one reconstruction call (all the kernels it
-    launches), HIP events recorded on the stream the kernels are launched on."""
-    s = torch.cuda.current_stream()
-    for _ in range(3):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp_image=mlp_image, mask_out=mask_out)
+def time_recon_replay(solver, U0, steps, warmup, torch):
+    """Mean duration of the reconstruction calls (all the kernels one call
+    launches) of the timed steps, from HIP events recorded on the launch
+    stream around each call.  The events would add gaps to the timed loop,
+    so the warm-up and timed steps are replayed from the same initial state
+    (the path is deterministic: the same states, the same troubled cells)
+    with the events in place."""
+    U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        solver.step(U, ke=True)
+    solver.recon_events = []
+    for _ in range(steps):
+        solver.step(U, ke=True)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        ucns.reconstruct(lm, ph, U, precision, fs, None, flags, mlp_image=mlp_image, mask_out=mask_out)
-    e1.record(s)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    ev, solver.recon_events = solver.recon_events, None
+    return sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
 
 def copy_calibration(torch, nbytes=256 << 20):
@@ -190,8 +193,7 @@ def main():
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
         rate = nc * STAGES[args.integrator] * args.steps / (ms / 1e3)
-        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 20, torch, ucns, solver.mlp_image,
-                         solver.ws.mask_out)
+        rms = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
         gate = net is not None
         rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate)
@@ -231,7 +233,8 @@ def main():
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,
-                     "bytes_per_cell": hv["recon_bytes_per_cell"]},
+                     "bytes_per_cell": hv["recon_bytes_per_cell"], "launch_ms": hv["recon_ms"],
+                     "launches_timed": args.steps * STAGES[args.integrator]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
@@ -263,7 +266,7 @@ def main_tet_p3(args, n=48):
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
         rate = nc * 3 * args.steps / (ms / 1e3)
-        rms = time_recon(lm, ph, U, prec, solver.ws.face_state, solver.ws.flags, 10, torch, ucns)
+        rms = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         rbc = recon_bytes_per_cell(lm, prec)
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall, "recon_ms": rms,
                           "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
