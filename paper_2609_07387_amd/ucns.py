@@ -379,8 +379,9 @@ class Solver:
         self.integrator = integrator
         self.W = (torch.empty((4, 5, mesh.n_cell), dtype=torch.float64, device=device)
                   if integrator == "ssp54" else None)
-        # a list here collects a (start, end) HIP-event pair around every
-        # reconstruction call, recorded on the launch stream (timing only)
+        # a list here collects, for every reconstruction call, a (start, end)
+        # HIP-event pair recorded on the launch stream and, with the network,
+        # the call's count of cells taken as smooth (a device scalar); timing only
         self.recon_events = None
 
     def rhs_stage(self, U):
@@ -390,12 +391,14 @@ class Solver:
             import torch
 
             s = torch.cuda.current_stream()
-            ev.append((torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)))
+            ev.append([torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), None])
             ev[-1][0].record(s)
         reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags, ws.label,
                     mlp_image=self.mlp_image, mask_out=ws.mask_out)
         if ev is not None:
             ev[-1][1].record(s)
+            if ws.mask_out is not None:
+                ev[-1][2] = ws.mask_out.sum()
         if self.ph.viscous:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
         face_flux(self.mesh, self.ph, self.bcs, U, ws.face_state, ws.gradW, self.precision, ws.face_flux)
