@@ -248,7 +248,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,
                      "bytes_per_cell": hv["recon_bytes_per_cell"], "launch_ms": hv["recon_ms"],
-                     "launches_timed": args.steps * STAGES[args.integrator]},
+                     "launches_timed": args.steps * STAGES[args.integrator],
+                     "measured_GBs": traffic / (hv["recon_ms"] / 1e3) / 1e9 if traffic else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
