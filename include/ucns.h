@@ -189,8 +189,9 @@ int ucns_mesh_stencil(const ucns_mesh* mesh, int64_t cell, int64_t* central, int
                       int32_t* ndir, int32_t* dface);
 int ucns_mesh_operators(const ucns_mesh* mesh, int64_t cell, double* Bc, double* Bd, double* O, double* Phi);
 /* Least-squares gradient weights of one cell, G[6][3] by local face slot
- * (zero for absent slots): grad W_c = sum_lf G[lf] (W_lf - W_c), W_lf the
- * face neighbour's value or the boundary ghost's. */
+ * (host memory, caller-owned; zero for absent slots): grad W_c =
+ * sum_lf G[lf] (W_lf - W_c), W_lf the face neighbour's value or the boundary
+ * ghost's.  UCNS_EINVAL for a NULL mesh or G or a cell out of range. */
 int ucns_mesh_gradient_weights(const ucns_mesh* mesh, int64_t cell, double* G);
 
 /* --------------------------------------------------------- workspaces */
