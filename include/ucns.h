@@ -171,6 +171,17 @@ int ucns_mesh_info(const ucns_mesh* mesh, int64_t* info);
 /* Bytes of the device arena holding all mesh arrays for one precision. */
 int ucns_mesh_arena_bytes(const ucns_mesh* mesh, int precision, size_t* bytes);
 
+/* Largest byte span that one buffer descriptor of the reconstruction
+ * kernels covers for a mesh of n_cell cells with n_unknowns basis terms (9 at
+ * P2, 19 at P3) and n_face_slots faces per cell (6 with hexahedra), in the
+ * given precision; a host-side query, no device work.  The kernels address
+ * each array through descriptors with 32-bit offsets, so ucns_reconstruct and
+ * ucns_gate_features return UCNS_EINVAL for a mesh whose span exceeds
+ * 0xffffffff bytes (at P2: about 59M cells in FP64, 107M in FP32).  Writes
+ * *span; UCNS_EINVAL for a NULL span, a negative n_cell or non-positive
+ * counts. */
+int ucns_recon_span_bytes(int64_t n_cell, int precision, int n_unknowns, int n_face_slots, uint64_t* span);
+
 /* Copies the packed mesh arrays of one precision into the caller's device
  * arena (256-byte aligned, at least ucns_mesh_arena_bytes) on stream; the
  * handle keeps the pointer.  The arena must outlive every later compute call
@@ -229,7 +240,7 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
  *  - UCNS_GRAD_GREEN_GAUSS: face value the mean of the two cells, ghost state
  *    on boundaries;
  *  - UCNS_GRAD_LSQ: the least-squares gradients the paper's viscous terms use
- *    (Sec. 2.1, Sec. 2.2), read as the linear fit over the face neighbours
+ *    (Sec. 2.2), read as the linear fit over the face neighbours
  *    with weights 1/|d|^2 (d the centroid offset, across periodic seams); a
  *    boundary face enters as its ghost state at the centroid's mirror image
  *    in the face plane, which carries the boundary condition into the fit
@@ -267,7 +278,7 @@ int ucns_residual_rk_stage(const ucns_mesh* mesh, const void* face_flux, int pre
 
 /* The residual fused with stage s (0 .. 4) of the five-stage fourth-order
  * SSP Runge-Kutta method of Spiteri and Ruuth (the integrator family of
- * Sec. 2.1), Shu-Osher form, R = R(U) of the current U:
+ * Sec. 2.2), Shu-Osher form, R = R(U) of the current U:
  *   u1 = u0 + b10 dt R(u0);  u2 = a20 u0 + a21 u1 + b21 dt R(u1);
  *   u3 = a30 u0 + a32 u2 + b32 dt R(u2);  u4 = a40 u0 + a43 u3 + b43 dt R(u3);
  *   u5 = a52 u2 + a53 u3 + b53 dt R(u3) + a54 u4 + b54 dt R(u4)
@@ -286,6 +297,16 @@ int ucns_residual_ssp54_stage(const ucns_mesh* mesh, const void* face_flux, int 
 int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux, int precision,
                            const double* dt_dev, double* U0, double* U, double cfl, double* reduce_scratch,
                            double* dt_next_dev, double* ke_dev, ucns_stream stream);
+
+/* Health check of a run: waits for the stream, then reads the device time
+ * step that ucns_dt or ucns_residual_rk_final wrote.  Those reductions write
+ * NaN when any cell's admissible step is NaN or not positive, which happens
+ * exactly when a state is NaN/Inf or has non-positive density or pressure;
+ * the time step is the run's device status word.  Returns UCNS_ENUM in that
+ * case (and for an infinite step), UCNS_EHIP if the stream reports an
+ * asynchronous error, UCNS_OK otherwise.  Synchronous (a host round trip):
+ * call it every few steps, not every stage. */
+int ucns_check(const double* dt_dev, ucns_stream stream);
 
 /* Kinetic energy sum |V| |m|^2 / (2 rho) / sum |V| (deterministic two-pass
  * sum in a fixed order); writes *ke_dev. */

@@ -289,7 +289,7 @@ int oracle_gradients(const oracle_mesh* m, const oracle_phys* ph, const oracle_b
     return 0;
 }
 
-/* Least-squares cell gradients of W = (u, v, w, T) (Sec. 2.2 and Sec. 2.1:
+/* Least-squares cell gradients of W = (u, v, w, T) (Sec. 2.2:
  * the viscous terms take least-squares gradients with boundary-condition
  * constraints).  Reading of what the paper leaves open: a linear fit
  *     min_g  sum_j w_j (W_j - W_i - g . d_j)^2,   w_j = 1 / |d_j|^2,
@@ -534,7 +534,7 @@ int oracle_rk_stage(const oracle_mesh* m, int stage, double dt, const double* U0
 }
 
 /* Five-stage fourth-order SSP Runge-Kutta (Spiteri & Ruuth 2002, the
- * integrator family the paper uses, Sec. 2.1), Shu-Osher form with L = R:
+ * integrator family the paper uses, Sec. 2.2), Shu-Osher form with L = R:
  *   u1 = u0 + b10 dt L(u0)
  *   u2 = a20 u0 + a21 u1 + b21 dt L(u1)
  *   u3 = a30 u0 + a32 u2 + b32 dt L(u2)

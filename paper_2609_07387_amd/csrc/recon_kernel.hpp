@@ -14,12 +14,22 @@
 // full memory round trip per stencil member.
 
 // Buffer loads: the array's base and size sit in a resource descriptor in
-// scalar registers, a row offset (wave-uniform) in a scalar register and the
-// lane's byte offset in one 32-bit vector register, so no access needs
-// per-lane 64-bit address arithmetic.  Each descriptor covers at most 4 GiB.
+// scalar registers, a small row offset (wave-uniform) in a scalar register
+// and the lane's byte offset in one 32-bit vector register, so no access
+// needs per-lane 64-bit address arithmetic.  Offsets are 32-bit: a row index
+// that can grow with the stencil or face-point count goes into the
+// descriptor's 64-bit base instead (row_rsrc), so the only offsets left are a
+// few rows of one array, and the launcher refuses meshes whose largest
+// remaining span (recon_span_bytes) reaches 4 GiB.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint64_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
                                              int(bytes < 0xffffffffull ? uint32_t(bytes) : 0xffffffffu), 0x00020000);
+}
+// Descriptor of `rows` rows of n_cell entries starting at row `row` of a
+// cell-fastest array (64-bit base arithmetic in scalar registers).
+template <class E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const E* base, int64_t row, int64_t nc, int rows = 1) {
+    return rsrc(base + row * nc, uint64_t(rows) * uint64_t(nc) * sizeof(E));
 }
 template <class T>
 __device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
@@ -50,10 +60,10 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
     const int64_t nc = A.nc;
     const int MC = MCw > 0 && MCw < A.MC ? MCw : A.MC;
     // member m's id at sten_c[m][c]; its K operator rows at Bc[m][k][c]; U[v][j]
-    const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
+    const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
     const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
-    const auto rS = rsrc(A.sten_c, uint64_t(MC) * rowI);
     const auto rU = rsrc(A.U, uint64_t(5) * rowU);
+    auto member_id = [&](int m) { return bld<int32_t>(row_rsrc(A.sten_c, m, nc), c4, 0u); };
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -68,12 +78,12 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
     T b[DEPTH + 1][K];
     int32_t jn[DEPTH + 1];  // ids of members m+1 .. m+DEPTH+1 (jn[0] unused after the prologue)
 #pragma unroll
-    for (int d = 0; d <= DEPTH; ++d) jn[d] = bld<int32_t>(rS, c4, uint32_t(last(d)) * rowI);
+    for (int d = 0; d <= DEPTH; ++d) jn[d] = member_id(last(d));
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
-        const auto rB = rsrc(A.Bc + int64_t(last(d)) * K * nc, uint64_t(K) * rowT);
+        const auto rB = row_rsrc(A.Bc, int64_t(last(d)) * K, nc, K);
 #pragma unroll
         for (int k = 0; k < K; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
     }
@@ -82,11 +92,11 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
     for (int m = 0; m < MC; ++m) {
         // issue member m+DEPTH (operands) and the id of member m+DEPTH+1
         const int mf = last(m + DEPTH);
-        const int32_t jf = bld<int32_t>(rS, c4, uint32_t(last(m + DEPTH + 1)) * rowI);
+        const int32_t jf = member_id(last(m + DEPTH + 1));
 #pragma unroll
         for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
         {
-            const auto rB = rsrc(A.Bc + int64_t(mf) * K * nc, uint64_t(K) * rowT);
+            const auto rB = row_rsrc(A.Bc, int64_t(mf) * K, nc, K);
 #pragma unroll
             for (int k = 0; k < K; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
         }
@@ -164,7 +174,6 @@ __device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, 
     const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
     const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
     const auto rN = rsrc(A.nbr, uint64_t(NF) * rowI);
-    const auto rD = rsrc(A.ndc, uint64_t(NF) * 3 * rowT);
     const auto rU = rsrc(A.U, uint64_t(5) * rowU);
     int32_t jn[kMaxFaces];
     T dn[kMaxFaces][3];
@@ -173,7 +182,8 @@ __device__ __forceinline__ void gate_features(const ReconArgs<T>& A, int64_t c, 
     for (int lf = 0; lf < kMaxFaces; ++lf) {
         jn[lf] = lf < NF ? bld<int32_t>(rN, c4, uint32_t(lf) * rowI) : -1;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dn[lf][d] = lf < NF ? bld<T>(rD, cT, uint32_t(lf * 3 + d) * rowT) : T(0);
+        for (int d = 0; d < 3; ++d)
+            dn[lf][d] = lf < NF ? bld<T>(row_rsrc(A.ndc, int64_t(lf) * 3, nc, 3), cT, uint32_t(d) * rowT) : T(0);
     }
 #pragma unroll
     for (int lf = 0; lf < kMaxFaces; ++lf)
@@ -298,7 +308,7 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
     const uint32_t cT = uint32_t(c) * uint32_t(sizeof(T));
     T pm[K];
     {
-        const auto rM = rsrc(A.pmean, uint64_t(K) * rowT);
+        const auto rM = row_rsrc(A.pmean, 0, nc, K);
 #pragma unroll
         for (int k = 0; k < K; ++k) pm[k] = bld<T>(rM, cT, uint32_t(k) * rowT);
     }
@@ -309,15 +319,14 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
     // ((lf Q + q) 5 + v).  The next face's offsets and point count load while
     // this face's points are formed, so only the first face waits on memory.
     constexpr int QM = face_qmax<K>();
-    const auto rX = rsrc(A.xi, uint64_t(NF) * Q * 3 * rowT);
-    const auto rQ = rsrc(A.cnq, uint64_t(NF) * uint64_t(nc));
     auto load_face = [&](int lf, T (&x)[QM][3]) {
 #pragma unroll
-        for (int q = 0; q < QM; ++q)
+        for (int q = 0; q < QM; ++q) {
+            const auto rX = row_rsrc(A.xi, (int64_t(lf) * Q + q) * 3, nc, 3);
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-                x[q][d] = q < Q ? bld<T>(rX, cT, uint32_t((lf * Q + q) * 3 + d) * rowT) : T(0);
-        return int(__builtin_amdgcn_raw_buffer_load_b8(rQ, int(uint32_t(c)), int(uint32_t(lf) * uint32_t(nc)), 0));
+            for (int d = 0; d < 3; ++d) x[q][d] = q < Q ? bld<T>(rX, cT, uint32_t(d) * rowT) : T(0);
+        }
+        return int(__builtin_amdgcn_raw_buffer_load_b8(row_rsrc(A.cnq, lf, nc), int(uint32_t(c)), 0, 0));
     };
     T x[QM][3], xn[QM][3];
     int nq = load_face(0, x);
@@ -343,7 +352,7 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
             for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
             const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
             ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
-            const auto rF = rsrc(A.fs + (int64_t(lf) * Q + q) * 5 * nc, uint64_t(5) * rowT);
+            const auto rF = row_rsrc(A.fs, (int64_t(lf) * Q + q) * 5, nc, 5);
 #pragma unroll
             for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cT, uint32_t(v) * rowT);
         }
@@ -452,11 +461,11 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
     // nd hold zero operators and are not counted); the id of member t at
     // sten_d[t][c], its 3 operator rows at Bd[t][k][c]
     const int MD = A.MD, total = A.ND * MD;
-    const uint32_t rowI = uint32_t(nc) * 4u, rowT = uint32_t(nc) * uint32_t(sizeof(T));
+    const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T));
     const uint32_t rowU = uint32_t(nc) * 8u;
     const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
-    const auto rS = rsrc(A.sten_d, uint64_t(total) * rowI);
     const auto rU = rsrc(A.U, uint64_t(5) * rowU);
+    auto member_id = [&](int t) { return bld<int32_t>(row_rsrc(A.sten_d, t, nc), c4, 0u); };
     // loads DEPTH members ahead (ids one further), as in central_coeffs
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
     auto last = [&](int t) { return t < total ? t : total - 1; };
@@ -464,12 +473,12 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
     T b[DEPTH + 1][3];
     int32_t jn[DEPTH + 1];
 #pragma unroll
-    for (int d = 0; d <= DEPTH; ++d) jn[d] = bld<int32_t>(rS, c4, uint32_t(last(d)) * rowI);
+    for (int d = 0; d <= DEPTH; ++d) jn[d] = member_id(last(d));
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
-        const auto rB = rsrc(A.Bd + int64_t(last(d)) * 3 * nc, uint64_t(3) * rowT);
+        const auto rB = row_rsrc(A.Bd, int64_t(last(d)) * 3, nc, 3);
 #pragma unroll
         for (int k = 0; k < 3; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
     }
@@ -483,11 +492,11 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
 #pragma unroll 1
     for (int t = 0; t < total; ++t) {
         const int tf = last(t + DEPTH);
-        const int32_t jf = bld<int32_t>(rS, c4, uint32_t(last(t + DEPTH + 1)) * rowI);
+        const int32_t jf = member_id(last(t + DEPTH + 1));
 #pragma unroll
         for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
         {
-            const auto rB = rsrc(A.Bd + int64_t(tf) * 3 * nc, uint64_t(3) * rowT);
+            const auto rB = row_rsrc(A.Bd, int64_t(tf) * 3, nc, 3);
 #pragma unroll
             for (int k = 0; k < 3; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
         }

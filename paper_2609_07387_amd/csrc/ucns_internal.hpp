@@ -1,6 +1,7 @@
 // Internal host-side structures of libucns (not part of the C ABI).
 #pragma once
 #include <cstddef>
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -19,6 +20,22 @@ constexpr int kDirMin = 4;       // fewer candidates drop the sector
 constexpr int kNumVar = 5;
 
 void set_error(const std::string& msg);
+
+// Largest byte span one buffer descriptor of the reconstruction kernels
+// covers (offsets inside a descriptor are 32-bit, so it must stay below
+// 4 GiB): the state U (5 rows of FP64), a member's or the basis means' K
+// operator rows, or the NF rows of face-neighbour ids.  Every other stream
+// (stencil ids, face-point offsets, directional operators, point states)
+// takes its row index in the descriptor's 64-bit base and spans at most
+// 5 rows of the precision's type.
+inline uint64_t recon_span_bytes(int64_t nc, int elem_bytes, int K, int NF) {
+    uint64_t per_cell = 40;
+    per_cell = std::max<uint64_t>(per_cell, uint64_t(K) * uint64_t(elem_bytes));
+    per_cell = std::max<uint64_t>(per_cell, uint64_t(NF) * 4u);
+    per_cell = std::max<uint64_t>(per_cell, uint64_t(5) * uint64_t(elem_bytes));
+    return per_cell * uint64_t(nc);
+}
+constexpr uint64_t kMaxDescriptorBytes = 0xffffffffull;
 
 // Offsets (bytes) of every array inside one precision's device arena.
 struct Arena {

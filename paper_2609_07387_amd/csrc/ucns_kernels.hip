@@ -599,8 +599,9 @@ __device__ __forceinline__ double rk_combine(double a, double b, double u0, doub
     return fma(a, u0, b * fma(dt, r, u));
 }
 
-// Admissible time step of one cell (Sec. 2.3 reading; cfl applied by the
-// caller): h / (|u| + c), and with viscosity rho h^2 / (2 mu max(4/3, gamma/Pr)).
+// Admissible time step of one cell (reading of compute_time_step, Listing 1 in
+// Sec. 3.2; cfl applied by the caller): h / (|u| + c), and with viscosity
+// rho h^2 / (2 mu max(4/3, gamma/Pr)).
 // NaN or a non-positive value returns -inf, which poisons the minimum.
 __device__ __forceinline__ double cell_dt(const PhysT<double>& P, const double* u, double h) {
     const double sp = sqrt(u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
@@ -846,6 +847,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
 template <class T, int K>
 int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
     if (A.Q > face_qmax<K>()) return UCNS_EINVAL;
+    if (recon_span_bytes(A.nc, int(sizeof(T)), K, A.NF) > kMaxDescriptorBytes) return UCNS_EINVAL;
     const dim3 grid(grid_for(A.nc)), block(kBlock);
     if (A.mlp || A.gate) {
         hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
@@ -870,6 +872,7 @@ int launch_recon(const Mesh& m, const Arena& ar, double gm1, const double* U, co
 
 template <class T>
 int launch_features(const Mesh& m, const Arena& ar, const double* U, float* out, hipStream_t st) {
+    if (recon_span_bytes(m.nc, int(sizeof(T)), m.K, m.nfmax) > kMaxDescriptorBytes) return UCNS_EINVAL;
     const ReconArgs<T> A = make_recon_args<T>(m, ar, 0.4, U, nullptr, nullptr, nullptr, nullptr);
     if (m.K == 9)
         hipLaunchKernelGGL((gate_features_kernel<T, 9>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A, out);
@@ -921,6 +924,13 @@ int ucns_mesh_arena_bytes(const ucns_mesh* mesh, int precision, size_t* bytes) {
     Arena a;
     pack_arena(*mesh->m, precision, a, nullptr);
     *bytes = a.bytes;
+    return UCNS_OK;
+}
+
+int ucns_recon_span_bytes(int64_t n_cell, int precision, int n_unknowns, int n_face_slots, uint64_t* span) {
+    UCNS_REQUIRE(span && n_cell >= 0 && n_unknowns > 0 && n_face_slots > 0, UCNS_EINVAL, "bad argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    *span = recon_span_bytes(n_cell, precision == UCNS_F64 ? 8 : 4, n_unknowns, n_face_slots);
     return UCNS_OK;
 }
 
@@ -1050,7 +1060,8 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
                                          : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);
     if (rc != UCNS_OK) {
-        set_error("unsupported reconstruction order");
+        set_error("unsupported reconstruction order, face-point count, or a mesh beyond the 4 GiB span of one "
+                  "buffer descriptor (ucns_recon_span_bytes)");
         return rc;
     }
     return hip_check("ucns_reconstruct");
@@ -1233,6 +1244,26 @@ int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* scratch, double
     return hip_check("ucns_diag_ke");
 }
 
+int ucns_check(const double* dt_dev, ucns_stream stream) {
+    UCNS_REQUIRE(dt_dev, UCNS_EINVAL, "null argument");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(st);
+    double dt = 0.0;
+    if (e == hipSuccess) e = hipMemcpy(&dt, dt_dev, sizeof dt, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        set_error(std::string("ucns_check: ") + hipGetErrorString(e));
+        return UCNS_EHIP;
+    }
+    // the reductions write NaN when any cell's time step is NaN or not
+    // positive (a NaN or Inf state, negative density or pressure)
+    if (!(dt > 0.0 && dt < INFINITY)) {
+        set_error("ucns_check: the time step is NaN, infinite or not positive (a cell state is NaN/Inf or has "
+                  "non-positive density or pressure)");
+        return UCNS_ENUM;
+    }
+    return UCNS_OK;
+}
+
 int ucns_gate_features(const ucns_mesh* mesh, const double* U, int precision, float* features, ucns_stream stream) {
     UCNS_REQUIRE(mesh && U && features, UCNS_EINVAL, "null argument");
     UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
@@ -1244,7 +1275,8 @@ int ucns_gate_features(const ucns_mesh* mesh, const double* U, int precision, fl
     const int rc = precision == UCNS_F64 ? launch_features<double>(m, ar, U, features, st)
                                          : launch_features<float>(m, ar, U, features, st);
     if (rc != UCNS_OK) {
-        set_error("unsupported reconstruction order");
+        set_error("unsupported reconstruction order, or a mesh beyond the 4 GiB span of one buffer descriptor "
+                  "(ucns_recon_span_bytes)");
         return rc;
     }
     return hip_check("ucns_gate_features");

@@ -443,8 +443,9 @@ def cell_averages(mesh: Mesh, func, npt: int = 4, chunk: int = 200000) -> np.nda
         pts = np.einsum("qk,tkd->tqd", bary, T)
         f = func(pts)  # [t, q, 5]
         acc_t = np.einsum("q,tqv->tv", w, f) * vt[:, None]
-        np.add.at(acc, cid, acc_t)
-        np.add.at(vol, cid, vt)
+        for v in range(5):
+            acc[:, v] += np.bincount(cid, weights=acc_t[:, v], minlength=nc)
+        vol += np.bincount(cid, weights=vt, minlength=nc)
     return acc / vol[:, None]
 
 

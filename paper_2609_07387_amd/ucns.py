@@ -29,7 +29,8 @@ EXPORTS = [
     "ucns_workspace_elems", "ucns_dt", "ucns_reconstruct", "ucns_gradients", "ucns_face_flux", "ucns_residual",
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
     "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
-    "ucns_residual_ssp54_stage", "ucns_mesh_gradient_weights",
+    "ucns_residual_ssp54_stage", "ucns_mesh_gradient_weights", "ucns_recon_span_bytes",
+    "ucns_check",
 ]
 
 
@@ -88,6 +89,8 @@ def lib():
         L.ucns_mesh_operators.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ucns_mesh_gradient_weights.argtypes = [vp, i64, vp]
         L.ucns_workspace_elems.argtypes = [vp, vp, vp, vp, vp]
+        L.ucns_recon_span_bytes.argtypes = [i64, i32, i32, i32, C.POINTER(C.c_uint64)]
+        L.ucns_check.argtypes = [vp, vp]
         L.ucns_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp, vp, vp]
         L.ucns_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, vp, vp]
         L.ucns_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, i32, vp, vp]
@@ -268,6 +271,14 @@ class Workspace:
 
 # ------------------------------------------------------------ entry points
 
+def recon_span_bytes(n_cell, precision, n_unknowns, n_face_slots):
+    """Largest byte span of one reconstruction buffer descriptor (host query)."""
+    out = C.c_uint64()
+    check(lib().ucns_recon_span_bytes(int(n_cell), int(precision), int(n_unknowns), int(n_face_slots),
+                                      C.byref(out)))
+    return int(out.value)
+
+
 def dt(mesh, ph, U, cfl, scratch, dt_dev, stream=None):
     check(lib().ucns_dt(mesh.h, C.byref(ph), _dp(U), float(cfl), _dp(scratch), _dp(dt_dev), _stream(stream)))
 
@@ -346,6 +357,12 @@ def residual_ssp54_stage(mesh, ff, precision, stage, dt_dev, W, U, stream=None):
     W (float64 [4][5][n_cell]) carries the stage states between calls."""
     check(lib().ucns_residual_ssp54_stage(mesh.h, _dp(ff), precision, int(stage), _dp(dt_dev), _dp(W), _dp(U),
                                           _stream(stream)))
+
+
+def check_state(dt_dev, stream=None):
+    """Raises UcnsError (code UCNS_ENUM = -7) when the device time step is
+    NaN, infinite or not positive, i.e. the state has gone bad (synchronous)."""
+    check(lib().ucns_check(_dp(dt_dev), _stream(stream)))
 
 
 def diag_ke(mesh, U, scratch, ke_dev, stream=None):
@@ -432,20 +449,33 @@ class Solver:
                           ws.dt, ws.ke)
         self._dt_key = (U.data_ptr(), U._version)
 
-    def run(self, U, n_steps, ke_history=False):
+    def check(self):
+        """Raises UcnsError if the last computed time step flags a NaN/Inf or
+        non-positive state (one host round trip)."""
+        check_state(self.ws.dt)
+
+    def run(self, U, n_steps, ke_history=False, check_every=0):
+        """n_steps steps of U in place; with check_every > 0 the state is
+        checked (check()) every that many steps, and always at the end."""
         import torch
 
         hist, dts = [], []
         if ke_history:
             diag_ke(self.mesh, U, self.ws.reduce, self.ws.ke)
             hist.append(self.ws.ke.clone())
-        for _ in range(n_steps):
+        for i in range(n_steps):
             if ke_history:
                 self.ensure_dt(U)
                 dts.append(self.ws.dt.clone())
             self.step(U)
             if ke_history:
                 hist.append(self.ws.ke.clone())
+            if check_every > 0 and (i + 1) % check_every == 0:
+                self.ensure_dt(U)
+                self.check()
+        if n_steps > 0:
+            self.ensure_dt(U)   # the SSP-RK3 step already left the new state's dt
+            self.check()
         if ke_history:
             return torch.cat(hist).cpu().numpy(), torch.cat(dts).cpu().numpy()
         return None

@@ -185,3 +185,53 @@ def test_trained_gate_shock_box_500_steps(torch_cuda):
           f"gated {ev['gated']['fraction_gated']:.3f}", flush=True)
     assert ev["rel_L1_gated_vs_full"] < 1e-3
     assert ev["gated"]["fraction_gated"] > 0.5
+
+
+def _lattice_params(seed=0):
+    """Parameters on a coarse dyadic lattice: every input, weight and hidden
+    value of the forward pass is exact in bfloat16, and every FP32 sum is
+    exact, so the matrix-core forward computes the plain FP64 network up to
+    the rounding of the final sigmoid."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(ucns.MLP_NPARAM)
+    o = ucns.MLP_OFF
+    p[o["isig"]:o["isig"] + 12] = 1.0                     # mu = 0, isig = 1
+    W1 = rng.choice([-1.0, -0.5, 0.0, 0.5, 1.0], size=(16, 64))
+    W1[12:] = 0.0
+    p[o["W1"]:o["W1"] + 1024] = W1.ravel()
+    p[o["b1"]:o["b1"] + 64] = rng.choice([-1.0, -0.5, 0.0, 0.5], size=64)
+    p[o["W2"]:o["W2"] + 4096] = rng.choice([-0.25, 0.0, 0.25], size=4096)
+    p[o["b2"]:o["b2"] + 64] = rng.choice([-0.5, 0.0, 0.5], size=64)
+    p[o["w3"]:o["w3"] + 64] = rng.choice([-1.0, 0.0, 1.0], size=64) / 32.0
+    p[o["b3"]] = -0.75
+    p[o["theta"]] = 0.5
+    return p
+
+
+def test_mlp_forward_lattice_matches_plain_fp64(torch_cuda):
+    """On lattice parameters and integer features (all bf16-exact, hidden
+    values quarter-integers of magnitude < 64), the BF16 matrix-core forward
+    equals the plain FP64 network (no bf16 emulation in the oracle) within
+    1e-6 in probability, and the gate mask equals the thresholded FP64
+    probabilities exactly."""
+    torch = torch_cuda
+    p = _lattice_params(3)
+    rng = np.random.default_rng(4)
+    F = rng.integers(-2, 3, size=(1000, 12)).astype(np.float32)   # ragged: 1000 rows
+    z64, c = omlp.forward(p, F.astype(np.float64))
+    # the lattice claims: hidden values exact in bfloat16
+    assert np.array_equal(omlp.bf16(c["h1"]), c["h1"]) and np.abs(c["h1"]).max() < 64
+    ref = omlp.sigmoid(z64)
+    pt = torch.tensor(p, dtype=torch.float32, device="cuda")
+    Ft = torch.tensor(F, device="cuda")
+    prob = torch.empty(len(F), dtype=torch.float32, device="cuda")
+    ucns.mlp_forward(pt, Ft, prob)
+    mask = torch.empty(len(F), dtype=torch.uint8, device="cuda")
+    ucns.gate_mask(pt, Ft, mask)
+    torch.cuda.synchronize()
+    got = prob.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max()
+    print(f"[gpu] lattice network: max |prob - FP64| {err:.2e}, z range {z64.min():.2f}..{z64.max():.2f}", flush=True)
+    assert err < 1e-6, err
+    far = np.abs(ref - 0.5) > 1e-5   # decisions away from the threshold
+    assert np.array_equal(mask.cpu().numpy()[far], (ref < 0.5)[far].astype(np.uint8))

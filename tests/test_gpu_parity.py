@@ -412,3 +412,33 @@ def test_ke_history_tgv32(torch_cuda):
         print(f"[gpu] KE history prec {prec}: KE {e_ke:.2e}, dissipation {e_eps:.2e}", flush=True)
         assert e_ke < tol
         assert e_eps < 1e3 * tol
+
+
+def test_check_flags_a_bad_state(torch_cuda):
+    """ucns_check: a healthy run passes; a state with a NaN cell, or a cell of
+    negative pressure, makes the device time step NaN and the check returns
+    UCNS_ENUM (the condition is set from the host; every kernel runs
+    normally)."""
+    torch = torch_cuda
+    m, order, ph, U0, bcs = _setup("hex7_p2_hllc_ns")
+    lm = ucns.Mesh(m, order=order)
+    s = ucns.Solver(lm, ph, ucns.F64, bcs, 0.5)
+    U = torch.tensor(U0, device="cuda")
+    s.run(U, 2, check_every=1)
+    for bad in ("nan", "negative pressure"):
+        Ub = torch.tensor(U0, device="cuda")
+        if bad == "nan":
+            Ub[3, 17] = float("nan")
+        else:
+            Ub[4, 17] = 0.5 * float(U0[1, 17] ** 2 / U0[0, 17]) - 1.0
+        ucns.dt(lm, ph, Ub, 0.5, s.ws.reduce, s.ws.dt)
+        with pytest.raises(ucns.UcnsError) as e:
+            ucns.check_state(s.ws.dt)
+        assert "error -7" in str(e.value), str(e.value)
+    # the fused last stage of a step reports it the same way
+    Ub = torch.tensor(U0, device="cuda")
+    Ub[0, 5] = float("nan")
+    s2 = ucns.Solver(lm, ph, ucns.F64, bcs, 0.5)
+    with pytest.raises(ucns.UcnsError) as e:
+        s2.run(Ub, 1)
+    assert "error -7" in str(e.value)

@@ -173,6 +173,7 @@ def test_entry_points_reject_null_arguments():
         L.ucns_mlp_pack(None, None, None),
         L.ucns_gradients(lm.h, C.byref(ph), None, None, ucns.F64, None, None),
         L.ucns_mesh_gradient_weights(lm.h, 0, None),
+        L.ucns_check(None, None),
     ]
     assert rcs == [-1] * len(rcs), rcs
     # an unknown gradient method is refused before any device state is looked at
@@ -184,3 +185,29 @@ def test_entry_points_reject_null_arguments():
     assert "gradient method" in L.ucns_last_error().decode()
     G = np.zeros((6, 3))
     assert L.ucns_mesh_gradient_weights(lm.h, lm.n_cell, G.ctypes.data_as(C.c_void_p)) == -1
+
+
+def test_recon_span_arithmetic():
+    """The reconstruction's 32-bit descriptor offsets: the largest span one
+    descriptor covers stays below 4 GiB on the 8,007,680-cell mixed mesh in
+    FP64 (at P2 a cell needs max(40, 9 x 8) bytes per row group), grows
+    linearly with the cell count, and reaches 4 GiB only at meshes the
+    reconstruction then refuses (about 59.6M cells at P2 FP64)."""
+    _lib_or_skip()
+    limit = 0xffffffff
+    nc = 8_007_680
+    span = ucns.recon_span_bytes(nc, ucns.F64, 9, 6)
+    assert span == 72 * nc and span < limit
+    # the face-point offsets of all 6 x 4 points of a cell as one stream of
+    # 72 FP64 rows would have spanned past 4 GiB at this size: that stream now
+    # takes its row in the descriptor base, so it is not part of the span
+    assert 72 * 8 * nc > limit
+    assert ucns.recon_span_bytes(nc, ucns.F32, 9, 6) == 40 * nc
+    assert ucns.recon_span_bytes(nc, ucns.F64, 19, 6) == 152 * nc
+    assert ucns.recon_span_bytes(1000, ucns.F64, 9, 6) * 1000 == ucns.recon_span_bytes(1_000_000, ucns.F64, 9, 6)
+    n_max = limit // 72
+    assert ucns.recon_span_bytes(n_max, ucns.F64, 9, 6) <= limit
+    assert ucns.recon_span_bytes(n_max + 1, ucns.F64, 9, 6) > limit
+    for bad in ((-1, ucns.F64, 9, 6), (10, 7, 9, 6), (10, ucns.F64, 0, 6), (10, ucns.F64, 9, 0)):
+        with pytest.raises(ucns.UcnsError):
+            ucns.recon_span_bytes(*bad)
