@@ -116,27 +116,78 @@ def copy_calibration(torch, nbytes=256 << 20):
     return nbytes
 
 
-def cpu_baseline(seconds=12.0):
-    """The FP64 oracle as it stands, on this host: 32^3 hex TGV with the same
-    scheme (per-cell work is that of the 64^3 workload), SSP-RK3 steps until
-    `seconds` have elapsed; mesh build excluded."""
+def _cpu_baseline_child(lib_path, threads):
+    """Child process of cpu_baseline (no GPU): the tuned oracle on the 32^3
+    TGV (mesh built on all `threads`), 3 timed runs of 30 SSP-RK3 steps on
+    `threads` threads, then one run of 6 steps on 1 thread, each from the
+    same initial state; prints one JSON line of cell-stage rates."""
+    import ctypes
+
+    os.environ["OMP_NUM_THREADS"] = str(threads)
     import oracle
     from paper_2609_07387_amd import inputs
 
+    oracle.use_library(lib_path)
+    gomp = ctypes.CDLL("libgomp.so.1")   # the OpenMP runtime the oracle runs on
     m = inputs.periodic_hex_mesh(32)
-    U = inputs.tgv_initial(m)
+    U0 = inputs.tgv_initial(m)
     om = oracle.OracleMesh(m, order=2)
     ph = oracle.phys(flux="hllc", viscous=True)
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds and steps < 400:
-        U, _, _ = om.run(U, ph, 0.5, 1)
-        steps += 1
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": m.n_cell * 3 * steps / dt, "unit": "cell-stage updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"32^3 periodic hex TGV, same scheme (P2 CWENOZ, HLLC, NS, Green-Gauss), {steps} SSP-RK3 "
-                      f"steps in {dt:.1f} s, mesh build excluded"}
+    out = {}
+    for name, nthr, steps, runs in (("all", threads, 30, 3), ("one", 1, 6, 1)):
+        gomp.omp_set_num_threads(nthr)
+        rates = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            om.run(U0, ph, 0.5, steps)
+            rates.append(m.n_cell * 3 * steps / (time.perf_counter() - t0))
+        out[name] = rates
+    print(json.dumps(out), flush=True)
+
+
+def _lscpu():
+    import subprocess
+
+    out = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except (OSError, subprocess.SubprocessError):
+        return out
+    for line in txt.splitlines():
+        k, _, v = line.partition(":")
+        if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+            out[k.strip()] = v.strip()
+    return out
+
+
+def cpu_baseline():
+    """The FP64 oracle, unchanged but built -O3 -march=native for this host,
+    on the 32^3 hex TGV with the same scheme (per-cell work is that of the
+    64^3 workload), mesh build excluded: the mean of 3 runs on the threads
+    this process may use (OMP_NUM_THREADS, else its CPU affinity), and one
+    run on 1 thread, in a child process (no GPU; about 30 s of host time)."""
+    import subprocess
+    import tempfile
+
+    import oracle
+
+    tmp = tempfile.mkdtemp(prefix="ucns_oracle_")
+    lib_path = oracle.build(out=os.path.join(tmp, "liboracle_tuned.so"), tuned=True)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", avail))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", lib_path, str(threads)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600, env=dict(os.environ))
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed: {r.stderr[-2000:]}")
+    legs = json.loads(r.stdout.strip().splitlines()[-1])
+    mean = sum(legs["all"]) / len(legs["all"])
+    cpu = _lscpu()
+    return {"value": mean, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+            "sample": "32^3 periodic hex TGV, same scheme (P2 CWENOZ, HLLC, NS, Green-Gauss); mean of 3 runs of 30 "
+                      "SSP-RK3 steps on the threads shown, plus 6 steps on 1 thread; oracle built -O3 "
+                      "-march=native on this host; mesh build excluded",
+            "runs": legs["all"], "spread": (max(legs["all"]) - min(legs["all"])) / mean,
+            "one_thread": legs["one"][0], "host": cpu}
 
 
 GRAD_NAME = {"green_gauss": "Green-Gauss", "least_squares": "least-squares"}
@@ -162,8 +213,13 @@ def main():
                     help="viscous cell gradients of the Navier-Stokes workloads")
     ap.add_argument("--runs", type=int, default=1,
                     help="tgv_hex_p2: timed runs per variant, each from the initial state (value: their mean)")
+    ap.add_argument("--stencil-factor", type=float, default=2.0,
+                    help="tgv_tet_p3: central stencil size over K(r,3) (2: the workload's; 3: the size that is "
+                         "stable at P3 on jittered tetrahedra)")
     ap.add_argument("--integrator", choices=("ssp3", "ssp54"), default="ssp3",
                     help="tgv_hex_p2: SSP-RK3 (3 stages) or the five-stage fourth-order SSP-RK")
+    if len(sys.argv) > 1 and sys.argv[1] == "--cpu-baseline-child":
+        return _cpu_baseline_child(sys.argv[2], int(sys.argv[3]))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
@@ -204,10 +260,19 @@ def main():
         for _ in range(args.runs):
             U = torch.tensor(U0, dtype=torch.float64, device="cuda")
             per_run.append(time_steps(solver, U, args.steps, args.warmup, torch))
+        solver.check()   # the final state is finite with positive density and pressure (host round trip)
         ms = sum(r[0] for r in per_run) / len(per_run)
         wall = sum(r[1] for r in per_run) / len(per_run)
         rate = nc * STAGES[args.integrator] * args.steps / (ms / 1e3)
         rms, frac = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
+        # the configuration's own 200-step window (after the same warm-up),
+        # reported beside the timed window when that one is shorter
+        long_rate = None
+        if args.steps < 200:
+            U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+            lms, _ = time_steps(solver, U, 200, args.warmup, torch)
+            solver.check()
+            long_rate = nc * STAGES[args.integrator] * 200 / (lms / 1e3)
         gate = net is not None
         rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate)
                + frac * recon_bytes_per_cell(lm, prec, linear=True, gate=gate))
@@ -218,8 +283,11 @@ def main():
                           "path_GBs": step_bytes_per_cell(lm, prec, recon=rbc) * rate / 1e9}
         if net is not None:
             variants[name]["fraction_gated"] = frac
+        if long_rate is not None:
+            variants[name]["value_200_steps"] = long_rate
         print(f"[bench] {name}: {rate:.3e} cell-stage/s, {ms / args.steps:.3f} ms/step, recon {rms:.3f} ms"
-              + (f", gated {frac:.1%}" if net is not None else ""), file=sys.stderr, flush=True)
+              + (f", gated {frac:.1%}" if net is not None else "")
+              + (f"; 200-step window {long_rate:.3e}" if long_rate else ""), file=sys.stderr, flush=True)
         del solver
     copy_calibration(torch)
     head = "fp32_gate" if "fp32_gate" in variants else "fp64_plain"
@@ -243,6 +311,8 @@ def main():
         "variants": variants,
         "fp64_plain_value": variants["fp64_plain"]["value"],
         "speedup_vs_fp64_plain": hv["value"] / variants["fp64_plain"]["value"],
+        "speedup_vs_fp64_plain_200_steps": (hv["value_200_steps"] / variants["fp64_plain"]["value_200_steps"]
+                                            if "value_200_steps" in hv else None),
         "roofline": {"kernel": "ucns_reconstruct call: " + " + ".join(kname.split("|")), "bound": "hbm",
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -271,7 +341,7 @@ def main_tet_p3(args, n=48):
     U0 = inputs.tgv_initial(m, noise_seed=1000)
     ph = ucns.phys(flux="hllc", viscous=False)
     t0 = time.perf_counter()
-    lm = ucns.Mesh(m, order=3)
+    lm = ucns.Mesh(m, order=3, stencil_factor=args.stencil_factor)
     print(f"[bench] mesh build {time.perf_counter() - t0:.1f} s, {lm.n_cell} cells, {lm.n_face} faces", file=sys.stderr,
           flush=True)
     nc = lm.n_cell
@@ -298,6 +368,7 @@ def main_tet_p3(args, n=48):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"TGV {n}^3 x 6 jittered periodic tets (+1 % velocity noise), P3 CWENOZ, HLLC, "
                                "Euler, SSP-RK3 CFL 0.5, per-step KE", "cells": nc, "faces": lm.n_face,
+                   "central_stencil": f"{args.stencil_factor:g} K(r,3) cells ({lm.mc_pad} padded)",
                    "variant": "fp32 (FP32 reconstruction/flux, FP64 state/RK/reductions)"},
         "variants": variants,
         "fp64_value": variants["fp64"]["value"],

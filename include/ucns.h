@@ -86,13 +86,15 @@ typedef struct {
 } ucns_mesh_desc;
 
 /* Reconstruction options.  order r = 2 or 3 (P2, P3); central stencil
- * 2 K(r,3) cells; 8 cells per directional (linear) stencil; triangle faces
- * use the 3-point rule, quadrilateral faces r x r Gauss points. */
+ * round(stencil_factor K(r,3)) cells (closed over distance ties); 8 cells per
+ * directional (linear) stencil; triangle faces use the 3-point rule,
+ * quadrilateral faces r x r Gauss points. */
 typedef struct {
-    int order;          /* 2 or 3 */
-    double lambda_c;    /* central linear weight before normalisation, 1000 */
-    double eps;         /* epsilon of the nonlinear weights, 1e-12 */
-    int max_layers;     /* vertex-neighbour layers searched, 3 */
+    int order;              /* 2 or 3 */
+    double lambda_c;        /* central linear weight before normalisation, 1000 */
+    double eps;             /* epsilon of the nonlinear weights, 1e-12 */
+    int max_layers;         /* vertex-neighbour layers searched, 3 */
+    double stencil_factor;  /* central stencil size over K(r,3), 2 (<= 0 also means 2) */
 } ucns_recon_opts;
 
 /* Physics: nondimensional with rho_ref = u_ref = L = 1, p_ref = 1/(gamma M^2),

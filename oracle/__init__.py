@@ -25,14 +25,19 @@ MAXF = 6    # max faces per cell
 MAXMD = 16  # directional stencil stride
 
 
-def build(verbose: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain -O2, OpenMP, no -march tuning)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared", "-o", _LIB]
+def build(verbose: bool = False, out: str | None = None, tuned: bool = False) -> str:
+    """Compile the oracle with gcc and OpenMP.  The checker (default, into
+    oracle/liboracle.so) is plain -O2 with no -march tuning and no FMA
+    contraction, so its results do not depend on the host; tuned=True builds
+    -O3 -march=native (for timing on the host that runs it) into `out`."""
+    out = out or _LIB
+    opt = ["-O3", "-march=native"] if tuned else ["-O2", "-ffp-contract=off"]
+    cmd = ["gcc", *opt, "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared", "-o", out]
     cmd += [os.path.join(_HERE, s) for s in _SRC] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return _LIB
+    return out
 
 
 _lib = None
@@ -48,6 +53,16 @@ def lib():
     return _lib
 
 
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same sources (e.g. a tuned
+    build for timing); call before any other use of this module."""
+    global _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _lib = C.CDLL(path)
+    _declare(_lib)
+
+
 class MeshIn(C.Structure):
     _fields_ = [
         ("n_vert", C.c_int64), ("xyz", C.c_void_p), ("n_cell", C.c_int64), ("type", C.c_void_p),
@@ -58,7 +73,7 @@ class MeshIn(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("order", C.c_int), ("tri_qp", C.c_int), ("lambda_c", C.c_double), ("eps", C.c_double),
-                ("max_layers", C.c_int)]
+                ("max_layers", C.c_int), ("stencil_factor", C.c_double)]
 
 
 class Phys(C.Structure):
@@ -139,7 +154,7 @@ class OracleMesh:
     """Oracle-side mesh: geometry, faces, stencils and operators built by the
     oracle's own code from the raw mesh arrays."""
 
-    def __init__(self, mesh, order=2, need=None, lambda_c=1000.0, eps=1e-12, max_layers=3):
+    def __init__(self, mesh, order=2, need=None, lambda_c=1000.0, eps=1e-12, max_layers=3, stencil_factor=2.0):
         L = lib()
         self._keep = [np.ascontiguousarray(mesh.xyz, np.float64), np.ascontiguousarray(mesh.ctype, np.uint8),
                       np.ascontiguousarray(mesh.cell_ptr, np.int64), np.ascontiguousarray(mesh.cell_vtx, np.int64),
@@ -148,7 +163,7 @@ class OracleMesh:
         xyz, ty, cp, cv, bp, bv, bt = self._keep
         mi = MeshIn(xyz.shape[0], _p(xyz), ty.shape[0], _p(ty), _p(cp), _p(cv),
                     (C.c_double * 3)(*[float(x) for x in mesh.period]), bt.shape[0], _p(bp), _p(bv), _p(bt))
-        op = Opts(order, 3, lambda_c, eps, max_layers)
+        op = Opts(order, 3, lambda_c, eps, max_layers, stencil_factor)
         self._need = None if need is None else np.ascontiguousarray(need, np.uint8)
         h = C.c_void_p()
         _check(L.oracle_build(C.byref(mi), C.byref(op), _p(self._need), 0, C.byref(h)))

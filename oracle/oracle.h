@@ -40,6 +40,7 @@ typedef struct {
     double lambda_c;    /* central linear weight before normalisation (1000) */
     double eps;         /* epsilon of the nonlinear weights (1e-12) */
     int max_layers;     /* vertex-neighbour layers searched for stencils (3) */
+    double stencil_factor; /* central stencil size Mc = round(stencil_factor K(r,3)) (2) */
 } oracle_opts;
 
 typedef struct {

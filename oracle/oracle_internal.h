@@ -39,6 +39,7 @@ struct oracle_mesh {
     const int64_t* bface_vtx;
     const int32_t* bface_tag;
     int order, K, max_layers;
+    double stencil_factor;
     double lambda_c, eps;
     int expo[OR_MAXK][3];
     /* faces */

@@ -494,7 +494,8 @@ static int cmp_cand(const void* pa, const void* pb) {
  * paper cites the selection algorithm without stating it).  Reading:
  *  - candidate pool: cells within L vertex-neighbour layers, L the smallest
  *    value >= 2 with at least 2*Mc candidates, capped at max_layers;
- *  - central stencil: the Mc = 2 K(r,3) nearest centroids (periodic minimum
+ *  - central stencil: the Mc = round(f K(r,3)) nearest centroids, f the
+ *    stencil factor (2 by default: twice the basis size; periodic minimum
  *    image), extended by every candidate within (1 + 1e-9) of the Mc-th
  *    distance ("shell closure", so ties never split);
  *  - one directional stencil per face: candidates whose centroid lies in the
@@ -503,7 +504,7 @@ static int cmp_cand(const void* pa, const void* pb) {
  *    candidates drops the stencil. */
 static int build_stencil(const oracle_mesh* m, int64_t c, const int64_t* v2c_ptr, const int64_t* v2c,
                          char* mark, int64_t* list, cand* pool, oracle_stencil_t* st) {
-    int K = m->K, Mc = 2 * (K + 1);
+    int K = m->K, Mc = (int)lround(m->stencil_factor * (K + 1));
     int64_t npool = 0;
     /* BFS over vertex adjacency */
     int64_t head = 0;
@@ -850,6 +851,7 @@ int oracle_build(const oracle_mesh_in* in, const oracle_opts* opt, const uint8_t
     m->lambda_c = opt->lambda_c;
     m->eps = opt->eps;
     m->max_layers = opt->max_layers;
+    m->stencil_factor = opt->stencil_factor > 0 ? opt->stencil_factor : 2.0;
     monomial_exponents(m->order, m->expo);
     int rc = build_faces(m);
     if (rc) {

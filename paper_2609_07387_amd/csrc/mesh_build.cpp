@@ -416,12 +416,13 @@ struct Cand {
 
 // Stencil rule (the paper cites the selection algorithm without giving it):
 // vertex-neighbour layers until >= 2 Mc candidates (at least 2, at most
-// max_layers layers); central = Mc nearest centroids (periodic minimum image)
+// max_layers layers); central = Mc = round(stencil_factor K(r,3)) nearest
+// centroids (periodic minimum image)
 // closed over distance ties within 1e-9; directional = up to 8 nearest
 // candidates inside the closed cone from the centroid through each face,
 // closed over ties, dropped below 4.
 int build_stencils(Mesh& m, int nt) {
-    const int Mc = 2 * (m.K + 1);
+    const int Mc = int(std::lround(m.stencil_factor * (m.K + 1)));
     std::vector<int64_t> v2c_ptr(m.nv + 1, 0), v2c(m.cptr[m.nc]);
     for (int64_t p = 0; p < m.cptr[m.nc]; ++p) v2c_ptr[m.cvtx[p] + 1]++;
     for (int64_t v = 0; v < m.nv; ++v) v2c_ptr[v + 1] += v2c_ptr[v];
@@ -897,6 +898,7 @@ int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads,
     m->lambda_c = o->lambda_c;
     m->eps = o->eps;
     m->max_layers = o->max_layers;
+    m->stencil_factor = o->stencil_factor > 0 ? o->stencil_factor : 2.0;
     m->mom_deg = std::max(o->order, 2 * o->order - 2);
     bool has_quad = false, has_tri = false;
     m->nfmax = 0;

@@ -59,6 +59,7 @@ struct Mesh {
     int order = 2, K = 9, qmax = 4, nfmax = 6, max_layers = 3;
     bool uniform_type = true;  // every cell of one type
     double lambda_c = 1000.0, eps = 1e-12;
+    double stencil_factor = 2.0;  // central stencil = round(stencil_factor K(r,3)) cells
     // ---- faces (numbered by owner cell, then owner-local face)
     int64_t nf = 0, nbnd = 0;
     std::vector<int64_t> fcell;   // [nf][2]; side 1 = -1 - tag on the boundary

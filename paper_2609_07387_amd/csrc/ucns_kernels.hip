@@ -606,9 +606,11 @@ __device__ __forceinline__ double rk_combine(double a, double b, double u0, doub
 __device__ __forceinline__ double cell_dt(const PhysT<double>& P, const double* u, double h) {
     const double sp = sqrt(u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
     const double cs = sqrt(P.gamma * pressure(P, u) / u[0]);
-    double t = h / (sp + cs);
+    const double ti = h / (sp + cs);  // NaN for a NaN state or a negative pressure
+    double t = ti;
+    // (fmin would return the viscous bound past a NaN convective one)
     if (P.viscous) t = fmin(t, u[0] * h * h / (2.0 * P.mu * fmax(4.0 / 3.0, P.gamma / P.pr)));
-    return t > 0.0 ? t : -INFINITY;
+    return ti > 0.0 && t > 0.0 ? t : -INFINITY;
 }
 
 // R_i = -(1/|V_i|) sum_f s_if F_f over the cell's faces in local order.
@@ -1202,14 +1204,12 @@ int ucns_rk_stage(const ucns_mesh* mesh, int stage, const double* dt_dev, double
     return hip_check("ucns_rk_stage");
 }
 
-int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux, int precision,
-                           const double* dt_dev, double* U0, double* U, double cfl, double* scratch,
-                           double* dt_next_dev, double* ke_dev, ucns_stream stream) {
-    UCNS_REQUIRE(mesh && phys && face_flux && dt_dev && U0 && U && scratch && dt_next_dev && ke_dev, UCNS_EINVAL,
-                 "null argument");
-    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
-    UCNS_REQUIRE(cfl > 0, UCNS_EINVAL, "cfl must be positive");
-    UCNS_REQUIRE(aligned(face_flux) && aligned(U0) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+namespace {
+// The last SSP-RK3 stage with the step's reductions; `scratch` holds the
+// 2 x grid_for(n_cell) per-block partials (time step, kinetic energy).
+int launch_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux, int precision,
+                    const double* dt_dev, double* U0, double* U, double cfl, double* scratch, double* dt_next_dev,
+                    double* ke_dev, ucns_stream stream) {
     const Mesh& m = *mesh->m;
     const Arena& ar = m.arena[precision];
     UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
@@ -1229,6 +1229,18 @@ int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const v
     hipLaunchKernelGGL(rk_final_kernel, dim3(1), dim3(kBlock), 0, st, int(nb), scratch, cfl, 1.0 / m.total_vol,
                        dt_next_dev, ke_dev);
     return hip_check("ucns_residual_rk_final");
+}
+}  // namespace
+
+int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux, int precision,
+                           const double* dt_dev, double* U0, double* U, double cfl, double* scratch,
+                           double* dt_next_dev, double* ke_dev, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && face_flux && dt_dev && U0 && U && scratch && dt_next_dev && ke_dev, UCNS_EINVAL,
+                 "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(cfl > 0, UCNS_EINVAL, "cfl must be positive");
+    UCNS_REQUIRE(aligned(face_flux) && aligned(U0) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    return launch_rk_final(mesh, phys, face_flux, precision, dt_dev, U0, U, cfl, scratch, dt_next_dev, ke_dev, stream);
 }
 
 int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* scratch, double* ke_dev, ucns_stream stream) {

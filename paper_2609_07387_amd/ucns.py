@@ -43,7 +43,8 @@ class MeshDesc(C.Structure):
 
 
 class ReconOpts(C.Structure):
-    _fields_ = [("order", C.c_int), ("lambda_c", C.c_double), ("eps", C.c_double), ("max_layers", C.c_int)]
+    _fields_ = [("order", C.c_int), ("lambda_c", C.c_double), ("eps", C.c_double), ("max_layers", C.c_int),
+                ("stencil_factor", C.c_double)]
 
 
 class Phys(C.Structure):
@@ -160,7 +161,7 @@ def bc(entries=None) -> BC:
 class Mesh:
     """Library mesh handle (host build) plus its device arenas."""
 
-    def __init__(self, mesh, order=2, lambda_c=1000.0, eps=1e-12, max_layers=3, n_threads=0):
+    def __init__(self, mesh, order=2, lambda_c=1000.0, eps=1e-12, max_layers=3, n_threads=0, stencil_factor=2.0):
         L = lib()
         self._keep = [np.ascontiguousarray(mesh.xyz, np.float64), np.ascontiguousarray(mesh.ctype, np.uint8),
                       np.ascontiguousarray(mesh.cell_ptr, np.int64), np.ascontiguousarray(mesh.cell_vtx, np.int64),
@@ -169,7 +170,7 @@ class Mesh:
         xyz, ty, cp, cv, bp, bv, bt = self._keep
         d = MeshDesc(xyz.shape[0], _np(xyz), ty.shape[0], _np(ty), _np(cp), _np(cv),
                      (C.c_double * 3)(*[float(x) for x in mesh.period]), bt.shape[0], _np(bp), _np(bv), _np(bt))
-        o = ReconOpts(order, lambda_c, eps, max_layers)
+        o = ReconOpts(order, lambda_c, eps, max_layers, stencil_factor)
         h = C.c_void_p()
         check(L.ucns_mesh_build(C.byref(d), C.byref(o), int(n_threads), C.byref(h)))
         self.h = h

@@ -211,3 +211,21 @@ def test_recon_span_arithmetic():
     for bad in ((-1, ucns.F64, 9, 6), (10, 7, 9, 6), (10, ucns.F64, 0, 6), (10, ucns.F64, 9, 0)):
         with pytest.raises(ucns.UcnsError):
             ucns.recon_span_bytes(*bad)
+
+
+def test_host_build_matches_oracle_stencil_factor_3():
+    """Central stencils of 3 K(r,3) cells (60 at P3) on jittered tetrahedra:
+    the same stencil sets and operators in both codes."""
+    _lib_or_skip()
+    m = inputs.kuhn_tet_mesh((4, 4, 4), (2 * math.pi,) * 3, (True,) * 3, 0.15, seed=2)
+    lm = ucns.Mesh(m, order=3, stencil_factor=3.0)
+    om = oracle.OracleMesh(m, order=3, stencil_factor=3.0)
+    assert lm.mc_min == om.mc_min >= 60
+    for c in (0, 7, 200, m.n_cell - 1):
+        lc, ld, _ = lm.stencil(c)
+        oc, od, _ = om.stencil(c)
+        assert sorted(lc) == sorted(oc)
+        lo, oo = lm.operators(c), om.operators(c)
+        # operator columns follow each code's own member order
+        pl, po = np.argsort(lc), np.argsort(oc)
+        assert np.abs(lo["Bc"][:, pl] - oo["Bc"][:, po]).max() < 1e-12 * np.abs(oo["Bc"]).max()
