@@ -310,6 +310,21 @@ int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const v
  * call it every few steps, not every stage. */
 int ucns_check(const double* dt_dev, ucns_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * operation as ucns_residual_rk_final, with the same arguments except that
+ * there is no reduce_scratch.  Its per-block partials live in a fixed device
+ * array inside the library (4 MiB per GPU, held until the process ends), so
+ * this call allocates nothing and calls no allocating routine; the caller
+ * still passes U, U0, face_flux and the device scalars.  Limit: meshes of at
+ * most 67,108,864 cells (262,144 blocks of 256); larger ones return
+ * UCNS_EINVAL.  Every call on one GPU shares that GPU's array (nothing in it
+ * needs to start at zero: each call writes every partial it reads), so calls
+ * that overlap on one GPU, e.g. on two streams, race. */
+int ucns_residual_rk_final_noalloc(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux,
+                                   int precision, const double* dt_dev, double* U0, double* U, double cfl,
+                                   double* dt_next_dev, double* ke_dev, ucns_stream stream);
+
 /* Kinetic energy sum |V| |m|^2 / (2 rho) / sum |V| (deterministic two-pass
  * sum in a fixed order); writes *ke_dev. */
 int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* reduce_scratch, double* ke_dev,

@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ucns_internal.hpp"
@@ -887,6 +888,49 @@ int launch_features(const Mesh& m, const Arena& ar, const double* U, float* out,
 
 }  // namespace
 
+// ============================================ static scratch (no allocation)
+
+// Per-block reduction partials of ucns_residual_rk_final_noalloc: a fixed
+// device array (4 MiB on every GPU the library runs on, held until the
+// process ends), so that call allocates nothing.  Its host-side name is not
+// a device address: each device's copy is looked up once with
+// hipGetSymbolAddress and only that pointer is used.
+constexpr int64_t kStaticScratchBlocks = int64_t(1) << 18;
+static __device__ __align__(256) double scratch[2 * kStaticScratchBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on the first
+// call per device).
+int static_scratch(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error(std::string("hipGetDevice: ") + hipGetErrorString(e));
+        return UCNS_EHIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the static scratch table");
+        return UCNS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return UCNS_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return UCNS_OK;
+}
+}  // namespace
+
 // =================================================================== C ABI
 
 struct ucns_mesh_impl_guard {};
@@ -1241,6 +1285,23 @@ int ucns_residual_rk_final(const ucns_mesh* mesh, const ucns_phys* phys, const v
     UCNS_REQUIRE(cfl > 0, UCNS_EINVAL, "cfl must be positive");
     UCNS_REQUIRE(aligned(face_flux) && aligned(U0) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
     return launch_rk_final(mesh, phys, face_flux, precision, dt_dev, U0, U, cfl, scratch, dt_next_dev, ke_dev, stream);
+}
+
+int ucns_residual_rk_final_noalloc(const ucns_mesh* mesh, const ucns_phys* phys, const void* face_flux,
+                                   int precision, const double* dt_dev, double* U0, double* U, double cfl,
+                                   double* dt_next_dev, double* ke_dev, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && face_flux && dt_dev && U0 && U && dt_next_dev && ke_dev, UCNS_EINVAL,
+                 "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(cfl > 0, UCNS_EINVAL, "cfl must be positive");
+    UCNS_REQUIRE(aligned(face_flux) && aligned(U0) && aligned(U), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    UCNS_REQUIRE(int64_t(grid_for(mesh->m->nc)) <= kStaticScratchBlocks, UCNS_EINVAL,
+                 "ucns_residual_rk_final_noalloc: more than 67,108,864 cells (its static scratch holds the "
+                 "partials of 262,144 blocks); use ucns_residual_rk_final with a workspace");
+    double* part = nullptr;
+    const int rc = static_scratch(&part);
+    if (rc != UCNS_OK) return rc;
+    return launch_rk_final(mesh, phys, face_flux, precision, dt_dev, U0, U, cfl, part, dt_next_dev, ke_dev, stream);
 }
 
 int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* scratch, double* ke_dev, ucns_stream stream) {

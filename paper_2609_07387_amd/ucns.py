@@ -30,7 +30,7 @@ EXPORTS = [
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
     "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
     "ucns_residual_ssp54_stage", "ucns_mesh_gradient_weights", "ucns_recon_span_bytes",
-    "ucns_check",
+    "ucns_check", "ucns_residual_rk_final_noalloc",
 ]
 
 
@@ -92,6 +92,7 @@ def lib():
         L.ucns_workspace_elems.argtypes = [vp, vp, vp, vp, vp]
         L.ucns_recon_span_bytes.argtypes = [i64, i32, i32, i32, C.POINTER(C.c_uint64)]
         L.ucns_check.argtypes = [vp, vp]
+        L.ucns_residual_rk_final_noalloc.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, dbl, vp, vp, vp]
         L.ucns_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp, vp, vp]
         L.ucns_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, vp, vp]
         L.ucns_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, i32, vp, vp]
@@ -351,6 +352,12 @@ def residual_rk_final(mesh, ph, ff, precision, dt_dev, U0, U, cfl, scratch, dt_n
     """Last RK stage with the next step's dt and the new state's kinetic energy."""
     check(lib().ucns_residual_rk_final(mesh.h, C.byref(ph), _dp(ff), precision, _dp(dt_dev), _dp(U0), _dp(U),
                                        float(cfl), _dp(scratch), _dp(dt_next), _dp(ke_dev), _stream(stream)))
+
+
+def residual_rk_final_noalloc(mesh, ph, ff, precision, dt_dev, U0, U, cfl, dt_next, ke_dev, stream=None):
+    """residual_rk_final with the library's static reduction scratch (no workspace)."""
+    check(lib().ucns_residual_rk_final_noalloc(mesh.h, C.byref(ph), _dp(ff), precision, _dp(dt_dev), _dp(U0),
+                                               _dp(U), float(cfl), _dp(dt_next), _dp(ke_dev), _stream(stream)))
 
 
 def residual_ssp54_stage(mesh, ff, precision, stage, dt_dev, W, U, stream=None):
