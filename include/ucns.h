@@ -85,12 +85,14 @@ typedef struct {
     const int32_t* bface_tag;
 } ucns_mesh_desc;
 
-/* Reconstruction options.  order r = 2 or 3 (P2, P3); central stencil
- * round(stencil_factor K(r,3)) cells (closed over distance ties); 8 cells per
- * directional (linear) stencil; triangle faces use the 3-point rule,
- * quadrilateral faces r x r Gauss points. */
+/* Reconstruction options.  order r = 2, 3 or 4 (P2, P3, P4 = CWENOZ5);
+ * central stencil round(stencil_factor K(r,3)) cells (closed over distance
+ * ties); one directional stencil per face, linear with 8 cells at P2/P3,
+ * quadratic with 20 cells at P4 (closed over ties; Sec. 2.2); triangle faces
+ * use the 3-point rule, quadrilateral faces r x r Gauss points.  P4 is built
+ * for meshes of quadrilateral faces only (UCNS_EINVAL otherwise). */
 typedef struct {
-    int order;              /* 2 or 3 */
+    int order;              /* 2, 3 or 4 */
     double lambda_c;        /* central linear weight before normalisation, 1000 */
     double eps;             /* epsilon of the nonlinear weights, 1e-12 */
     int max_layers;         /* vertex-neighbour layers searched, 3 */
@@ -167,7 +169,7 @@ void ucns_mesh_free(ucns_mesh* mesh);
  * NFMAX (max faces per cell), padded central stencil, max directional stencils per
  * cell, padded directional stencil, n_boundary_faces, dropped directional
  * stencils, min central stencil size, max central stencil size, order,
- * 0, 0, 0. */
+ * KD (unknowns of a directional polynomial: 3 linear, 9 quadratic), 0, 0. */
 int ucns_mesh_info(const ucns_mesh* mesh, int64_t* info);
 
 /* Bytes of the device arena holding all mesh arrays for one precision. */
@@ -194,8 +196,9 @@ int ucns_mesh_upload(ucns_mesh* mesh, int precision, void* arena, size_t bytes, 
  * c2f[c*6+lf] = 2*face + side (-1 unused); face cells [n_face][2] (-1 - tag
  * on a boundary side); face quadrature points [n_face][QMAX][3] in the
  * owner's frame; face shift [n_face][3] (neighbour frame = owner frame -
- * shift); stencils and FP64 operators of one cell in the same row-major
- * layout as the returned counts. */
+ * shift); stencils and FP64 operators of one cell: central ids (up to 128),
+ * directional ids dir[s*32 + j] (up to 32 per stencil), Bc[K][ncen],
+ * Bd[(s*KD + k)*32 + j], O[K][K], Phi[NFMAX][QMAX][K]. */
 int ucns_mesh_faces(const ucns_mesh* mesh, int32_t* c2f, int64_t* fcell, double* qp, double* shift);
 int ucns_mesh_cell_geometry(const ucns_mesh* mesh, double* vol, double* cen, double* hbasis);
 int ucns_mesh_stencil(const ucns_mesh* mesh, int64_t cell, int64_t* central, int32_t* ncen, int64_t* dir,

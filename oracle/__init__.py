@@ -20,9 +20,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
 _SRC = ["oracle_mesh.c", "oracle_solver.c"]
 
-QM = 9      # max quadrature points per face
+QM = 16     # max quadrature points per face (4 x 4 at P4)
 MAXF = 6    # max faces per cell
-MAXMD = 16  # directional stencil stride
+MAXMD = 32  # directional stencil stride
+MAXC = 128  # central stencil cap
 
 
 def build(verbose: bool = False, out: str | None = None, tuned: bool = False) -> str:
@@ -168,10 +169,10 @@ class OracleMesh:
         h = C.c_void_p()
         _check(L.oracle_build(C.byref(mi), C.byref(op), _p(self._need), 0, C.byref(h)))
         self.h = h
-        info = np.zeros(10, np.int64)
+        info = np.zeros(11, np.int64)
         L.oracle_info(self.h, _p(info))
         (self.n_cell, self.n_face, self.K, self.nq_max, self.nfc_max, self.mc_max, self.md_max, self.mc_min,
-         self.n_bnd, self.n_dropped) = (int(x) for x in info)
+         self.n_bnd, self.n_dropped, self.kd) = (int(x) for x in info)
         self.order = order
 
     def __del__(self):
@@ -199,7 +200,7 @@ class OracleMesh:
         return vol, cen, hb
 
     def stencil(self, cell):
-        cen = np.zeros(64, np.int64)
+        cen = np.zeros(MAXC, np.int64)
         nce = np.zeros(1, np.int32)
         d = np.zeros((MAXF, MAXMD), np.int64)
         nd = np.zeros(MAXF, np.int32)
@@ -213,13 +214,14 @@ class OracleMesh:
         cen, dirs, _ = self.stencil(cell)
         K = self.K
         Bc = np.zeros((K, len(cen)))
-        Bd = np.zeros((MAXF, 3, MAXMD))
+        kd = self.kd
+        Bd = np.zeros((MAXF, kd, MAXMD))
         O = np.zeros((K, K))
         Phi = np.zeros((MAXF, QM, K))
         mean = np.zeros(K)
         _check(lib().oracle_operators(self.h, int(cell), _p(Bc), _p(Bd), _p(O), _p(Phi), _p(mean)))
-        Bd_list = [np.ascontiguousarray(Bd.reshape(-1)[s * 3 * MAXMD: s * 3 * MAXMD + 3 * len(dirs[s])]
-                                        .reshape(3, len(dirs[s]))) for s in range(len(dirs))]
+        Bd_list = [np.ascontiguousarray(Bd.reshape(-1)[s * kd * MAXMD: s * kd * MAXMD + kd * len(dirs[s])]
+                                        .reshape(kd, len(dirs[s]))) for s in range(len(dirs))]
         return dict(Bc=Bc, Bd=Bd_list, O=O, Phi=Phi, mean=mean)
 
     def cell_quadrature(self, cell, cap=4000):

@@ -35,7 +35,7 @@ typedef struct {
 } oracle_mesh_in;
 
 typedef struct {
-    int order;          /* polynomial degree r of the central reconstruction (2 or 3) */
+    int order;          /* polynomial degree r of the central reconstruction (1 .. 4; 4 on hexahedra only) */
     int tri_qp;         /* quadrature points on triangular faces (3) */
     double lambda_c;    /* central linear weight before normalisation (1000) */
     double eps;         /* epsilon of the nonlinear weights (1e-12) */
@@ -68,9 +68,10 @@ int oracle_build(const oracle_mesh_in* in, const oracle_opts* opt, const uint8_t
                  int n_threads, oracle_mesh** out);
 void oracle_free(oracle_mesh* m);
 
-/* info[0..9] = n_cell, n_face, K (unknowns), max QPs per face, max faces per
+/* info[0..10] = n_cell, n_face, K (unknowns), max QPs per face, max faces per
  * cell, max central stencil size, max directional stencil size, min central
- * stencil size, number of boundary faces, number of dropped directional stencils */
+ * stencil size, number of boundary faces, number of dropped directional
+ * stencils, unknowns of a directional polynomial (3 linear, 9 quadratic) */
 int oracle_info(const oracle_mesh* m, int64_t* info);
 /* c2f[c*6+lf] = face id (-1 unused), side[c*6+lf] = 0 owner / 1 neighbour */
 int oracle_cell_faces(const oracle_mesh* m, int64_t* c2f, int8_t* side);
@@ -79,12 +80,12 @@ int oracle_cell_faces(const oracle_mesh* m, int64_t* c2f, int8_t* side);
 int oracle_face_data(const oracle_mesh* m, int64_t* cells, int32_t* nq, double* area, double* nrm,
                      double* qp, double* qw, double* shift);
 int oracle_cell_data(const oracle_mesh* m, double* vol, double* cen, double* hbasis);
-/* Stencil of one cell: central ids (ncen), directional ids [6][16] (ndir[6]),
+/* Stencil of one cell: central ids (ncen, up to 128), directional ids [6][32] (ndir[6]),
  * dface[6] = local face of each directional stencil, returns number of directional stencils */
 int oracle_stencil(const oracle_mesh* m, int64_t cell, int64_t* central, int32_t* ncen,
                    int64_t* dir, int32_t* ndir, int32_t* dface);
-/* Operators of one cell (row-major): Bc[K][ncen], Bd[s][3][16] (stride 16) with
- * O[K][K], Phi[6][QM][K], mean[K] */
+/* Operators of one cell (row-major): Bc[K][ncen], Bd (stencil s's kd x nd[s]
+ * block starting at s * kd * 32), O[K][K], Phi[6][QM][K], mean[K]; QM = 16 */
 int oracle_operators(const oracle_mesh* m, int64_t cell, double* Bc, double* Bd, double* O,
                      double* Phi, double* mean);
 /* Volume quadrature of one cell: up to cap points x[n][3], w[n]; returns n. */

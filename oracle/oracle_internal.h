@@ -4,10 +4,11 @@
 #include "oracle.h"
 
 #define OR_MAXF 6    /* faces per cell */
-#define OR_QM 9      /* quadrature points per face (3x3 at r = 3) */
-#define OR_MAXK 19   /* unknowns at r = 3 */
-#define OR_MAXM 64   /* central stencil size cap */
-#define OR_MAXMD 16  /* directional stencil size cap */
+#define OR_QM 16     /* quadrature points per face (4x4 at r = 4) */
+#define OR_MAXK 34   /* unknowns at r = 4 */
+#define OR_MAXKD 9   /* unknowns of a directional polynomial (quadratic) */
+#define OR_MAXM 128  /* central stencil size cap */
+#define OR_MAXMD 32  /* directional stencil size cap */
 #define OR_VQ 3000   /* volume quadrature points per cell (24 sub-tets x 5^3) */
 
 typedef struct {
@@ -23,7 +24,7 @@ typedef struct {
 typedef struct {
     double mean[OR_MAXK];
     double* Bc;          /* [K][ncen] */
-    double* Bd[OR_MAXF]; /* [3][nd[s]] */
+    double* Bd[OR_MAXF]; /* [kd][nd[s]] */
     double* O;           /* [K][K] */
     double* Phi;         /* [OR_MAXF * OR_QM][K] */
 } oracle_ops_t;
@@ -39,6 +40,7 @@ struct oracle_mesh {
     const int64_t* bface_vtx;
     const int32_t* bface_tag;
     int order, K, max_layers;
+    int kd;          /* unknowns of the directional polynomials: 3 (linear, r <= 3) or 9 (quadratic, r >= 4) */
     double stencil_factor;
     double lambda_c, eps;
     int expo[OR_MAXK][3];

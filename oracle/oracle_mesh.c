@@ -573,6 +573,9 @@ static int build_stencil(const oracle_mesh* m, int64_t c, const int64_t* v2c_ptr
             if (dot3(nrm[j], fc) < 0)
                 for (int a = 0; a < 3; ++a) nrm[j][a] = -nrm[j][a];
         }
+        /* 2 K(d,3) nearest (8 for linear, 20 for quadratic polynomials),
+         * at least K(d,3) (4 / 10) or the sector is dropped */
+        const int target = 2 * (m->kd + 1), least = m->kd + 1;
         int cnt = 0, s = st->ndir;
         int64_t ids[OR_MAXMD];
         double lim = -1.0;
@@ -582,13 +585,13 @@ static int build_stencil(const oracle_mesh* m, int64_t c, const int64_t* v2c_ptr
             for (int j = 0; j < fnv && inside; ++j)
                 if (dot3(d, nrm[j]) < -1e-9 * pool[k].dist * norm3(nrm[j])) inside = 0;
             if (!inside) continue;
-            if (cnt >= 8 && pool[k].dist > lim) break;
+            if (cnt >= target && pool[k].dist > lim) break;
             if (cnt >= OR_MAXMD) return or_fail(-2, "cell %lld: directional stencil overflow", (long long)c);
             ids[cnt] = pool[k].id;
             ++cnt;
-            if (cnt == 8) lim = pool[k].dist * (1.0 + 1e-9);
+            if (cnt == target) lim = pool[k].dist * (1.0 + 1e-9);
         }
-        if (cnt < 4) {
+        if (cnt < least) {
             st->ndropped++;
             continue;
         }
@@ -677,7 +680,7 @@ static void eval_basis(const oracle_mesh* m, int64_t c, const double* x, const d
 static int build_operators(oracle_mesh* m, int64_t c, oracle_stencil_t* st, oracle_ops_t* op) {
     int K = m->K, r = m->order;
     size_t nval = (size_t)K * OR_MAXM + (size_t)K * K + (size_t)OR_MAXF * OR_QM * K;
-    for (int s = 0; s < st->ndir; ++s) nval += 3 * (size_t)st->nd[s];
+    for (int s = 0; s < st->ndir; ++s) nval += (size_t)m->kd * st->nd[s];
     double* blk = calloc(nval, sizeof(double));
     op->Bc = blk;
     blk += (size_t)K * OR_MAXM;
@@ -687,7 +690,7 @@ static int build_operators(oracle_mesh* m, int64_t c, oracle_stencil_t* st, orac
     blk += (size_t)OR_MAXF * OR_QM * K;
     for (int s = 0; s < st->ndir; ++s) {
         op->Bd[s] = blk;
-        blk += 3 * (size_t)st->nd[s];
+        blk += (size_t)m->kd * st->nd[s];
     }
     int nvq = r + 1; /* exact for degree <= 2r-1 on every sub-tetrahedron: covers
                         the means (degree r), A (degree r) and O (degree 2r-2) */
@@ -714,7 +717,7 @@ static int build_operators(oracle_mesh* m, int64_t c, oracle_stencil_t* st, orac
     for (int s = -1; s < st->ndir; ++s) {
     retry:;
         int ns = s < 0 ? st->ncen : st->nd[s];
-        int kk = s < 0 ? K : 3;
+        int kk = s < 0 ? K : m->kd;
         for (int j = 0; j < ns; ++j) {
             int64_t id = s < 0 ? st->cen[j] : st->dir[s][j];
             /* shift of cell id's own frame to its image next to cell c */
@@ -783,6 +786,16 @@ static int build_operators(oracle_mesh* m, int64_t c, oracle_stencil_t* st, orac
     int nb = 0, beta[OR_MAXK][3];
     monomial_exponents(r, beta);
     nb = K;
+    /* D^b phi_k vanishes identically unless every exponent of phi_k reaches
+     * b's: only those k enter the sum for b (the skipped terms are exact
+     * zeros, so the sum is unchanged) */
+    int nzk[OR_MAXK][OR_MAXK], nnz[OR_MAXK];
+    for (int b = 0; b < nb; ++b) {
+        nnz[b] = 0;
+        for (int k = 0; k < K; ++k)
+            if (m->expo[k][0] >= beta[b][0] && m->expo[k][1] >= beta[b][1] && m->expo[k][2] >= beta[b][2])
+                nzk[b][nnz[b]++] = k;
+    }
     for (int q = 0; q < n; ++q) {
         const double* ci = m->cen + 3 * c;
         double h = m->hbasis[c];
@@ -791,22 +804,22 @@ static int build_operators(oracle_mesh* m, int64_t c, oracle_stencil_t* st, orac
             int ord = beta[b][0] + beta[b][1] + beta[b][2];
             double scale = pow(Vi, 2.0 * ord / 3.0 - 1.0) * ipow(1.0 / h, 2 * ord);
             double D[OR_MAXK];
-            for (int k = 0; k < K; ++k) {
+            for (int i = 0; i < nnz[b]; ++i) {
+                int k = nzk[b][i];
                 double v = 1.0;
                 for (int a = 0; a < 3; ++a) {
                     int e = m->expo[k][a], bb = beta[b][a];
-                    if (e < bb) {
-                        v = 0;
-                        break;
-                    }
                     double fac = 1.0;
                     for (int t = 0; t < bb; ++t) fac *= (double)(e - t);
                     v *= fac * ipow(xi[a], e - bb);
                 }
                 D[k] = v;
             }
-            for (int k = 0; k < K; ++k)
-                for (int l = 0; l < K; ++l) op->O[k * K + l] += wq[q] * scale * D[k] * D[l];
+            for (int i = 0; i < nnz[b]; ++i)
+                for (int j = 0; j < nnz[b]; ++j) {
+                    int k = nzk[b][i], l = nzk[b][j];
+                    op->O[k * K + l] += wq[q] * scale * D[k] * D[l];
+                }
         }
     }
 
@@ -832,7 +845,7 @@ int oracle_build(const oracle_mesh_in* in, const oracle_opts* opt, const uint8_t
                  oracle_mesh** out) {
     (void)n_threads;
     if (!in || !opt || !out) return or_fail(-1, "null argument");
-    if (opt->order < 1 || opt->order > 3) return or_fail(-1, "order %d not supported", opt->order);
+    if (opt->order < 1 || opt->order > 4) return or_fail(-1, "order %d not supported", opt->order);
     if (opt->tri_qp != 3) return or_fail(-1, "only the 3-point triangle rule is implemented");
     oracle_mesh* m = calloc(1, sizeof(oracle_mesh));
     m->n_vert = in->n_vert;
@@ -848,6 +861,16 @@ int oracle_build(const oracle_mesh_in* in, const oracle_opts* opt, const uint8_t
     m->bface_tag = in->bface_tag;
     m->order = opt->order;
     m->K = or_K(opt->order) - 1;
+    /* directional polynomials: linear for the third- and fourth-order
+     * schemes, quadratic from the fifth order on (Sec. 2.2) */
+    m->kd = opt->order >= 4 ? or_K(2) - 1 : or_K(1) - 1;
+    if (opt->order >= 4)
+        for (int64_t c = 0; c < in->n_cell; ++c)
+            if (in->type[c] != 8) {
+                free(m);
+                return or_fail(-1, "order %d is built for hexahedral meshes only (the 3-point triangle rule is "
+                                   "exact to degree 2)", opt->order);
+            }
     m->lambda_c = opt->lambda_c;
     m->eps = opt->eps;
     m->max_layers = opt->max_layers;
@@ -979,6 +1002,7 @@ int oracle_info(const oracle_mesh* m, int64_t* info) {
     info[7] = minc;
     info[8] = m->n_bnd;
     info[9] = ndrop;
+    info[10] = m->kd;
     return 0;
 }
 
@@ -1030,7 +1054,8 @@ int oracle_operators(const oracle_mesh* m, int64_t cell, double* Bc, double* Bd,
     int K = m->K;
     if (Bc) memcpy(Bc, op->Bc, sizeof(double) * K * st->ncen);
     if (Bd)
-        for (int s = 0; s < st->ndir; ++s) memcpy(Bd + s * 3 * OR_MAXMD, op->Bd[s], sizeof(double) * 3 * st->nd[s]);
+        for (int s = 0; s < st->ndir; ++s)
+            memcpy(Bd + (size_t)s * m->kd * OR_MAXMD, op->Bd[s], sizeof(double) * m->kd * st->nd[s]);
     if (O) memcpy(O, op->O, sizeof(double) * K * K);
     if (Phi) memcpy(Phi, op->Phi, sizeof(double) * OR_MAXF * OR_QM * K);
     if (mean) memcpy(mean, op->mean, sizeof(double) * K);

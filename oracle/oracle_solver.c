@@ -53,9 +53,10 @@ static void cwenoz_one_var(const oracle_mesh* m, int64_t c, const double* U, int
         memcpy(abar, a_opt, sizeof(double) * K);
         return;
     }
-    double a_s[OR_MAXF][3], SI[OR_MAXF + 1];
+    const int kd = m->kd;
+    double a_s[OR_MAXF][OR_MAXKD], SI[OR_MAXF + 1];
     for (int s = 0; s < nd; ++s)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kd; ++k) {
             double t = 0;
             for (int j = 0; j < st->nd[s]; ++j) t += op->Bd[s][k * st->nd[s] + j] * (U[v * nc + st->dir[s][j]] - ui);
             a_s[s][k] = t;
@@ -68,8 +69,8 @@ static void cwenoz_one_var(const oracle_mesh* m, int64_t c, const double* U, int
     SI[0] = fmax(SI[0], 0.0);
     for (int s = 0; s < nd; ++s) {
         double t = 0;
-        for (int k = 0; k < 3; ++k)
-            for (int l = 0; l < 3; ++l) t += a_s[s][k] * op->O[k * K + l] * a_s[s][l];
+        for (int k = 0; k < kd; ++k)
+            for (int l = 0; l < kd; ++l) t += a_s[s][k] * op->O[k * K + l] * a_s[s][l];
         SI[s + 1] = fmax(t, 0.0);
     }
     double tau = 0;
@@ -91,11 +92,11 @@ static void cwenoz_one_var(const oracle_mesh* m, int64_t c, const double* U, int
     double p1[OR_MAXK];
     memcpy(p1, a_opt, sizeof(double) * K);
     for (int s = 0; s < nd; ++s)
-        for (int k = 0; k < 3; ++k) p1[k] -= lam[s + 1] * a_s[s][k];
+        for (int k = 0; k < kd; ++k) p1[k] -= lam[s + 1] * a_s[s][k];
     for (int k = 0; k < K; ++k) p1[k] /= lam[0];
     for (int k = 0; k < K; ++k) abar[k] = w[0] * p1[k];
     for (int s = 0; s < nd; ++s)
-        for (int k = 0; k < 3; ++k) abar[k] += w[s + 1] * a_s[s][k];
+        for (int k = 0; k < kd; ++k) abar[k] += w[s + 1] * a_s[s][k];
 }
 
 /* Evaluate the cell's polynomials at its own face quadrature points

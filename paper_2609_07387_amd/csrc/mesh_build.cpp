@@ -527,7 +527,7 @@ int build_stencils(Mesh& m, int nt) {
                     bool in = true;
                     for (int j = 0; j < fnv && in; ++j) in = dot(d, pn[j]) >= -1e-9 * p.dist * norm(pn[j]);
                     if (!in) continue;
-                    if (cnt >= kDirTarget && p.dist > cut) break;
+                    if (cnt >= dir_target(m.kd) && p.dist > cut) break;
                     if (cnt >= kMaxDir) {
                         std::lock_guard<std::mutex> g(emu);
                         emsg = "cell " + std::to_string(c) + ": directional stencil overflow";
@@ -535,9 +535,9 @@ int build_stencils(Mesh& m, int nt) {
                         break;
                     }
                     out[cnt++] = p.id;
-                    if (cnt == kDirTarget) cut = p.dist * (1.0 + 1e-9);
+                    if (cnt == dir_target(m.kd)) cut = p.dist * (1.0 + 1e-9);
                 }
-                if (cnt < kDirMin) {
+                if (cnt < dir_min(m.kd)) {
                     for (int k = 0; k < kMaxDir; ++k) out[k] = -1;
                     m.ndropped[c]++;
                     continue;
@@ -666,7 +666,8 @@ int build_operators(Mesh& m, int nt) {
         m.nd_max = std::max(m.nd_max, m.ndir[c]);
         for (int s = 0; s < m.ndir[c]; ++s) m.md_pad = std::max(m.md_pad, m.nds[c * kMaxFaces + s]);
     }
-    m.Bd.assign(size_t(m.nc) * std::max(1, m.nd_max) * 3 * std::max(1, m.md_pad), 0);
+    const int kd = m.kd;
+    m.Bd.assign(size_t(m.nc) * std::max(1, m.nd_max) * kd * std::max(1, m.md_pad), 0);
     std::atomic<int> err{UCNS_OK};
     std::mutex emu;
     std::string emsg;
@@ -719,8 +720,9 @@ int build_operators(Mesh& m, int nt) {
                 std::lock_guard<std::mutex> g(over_mu);
                 Bc_over[c].assign(B, B + size_t(K) * n);
             }
-            // directional stencils (linear basis); one whose members cannot
-            // fix a linear polynomial (all in one plane through the centroid,
+            // directional stencils (the first kd basis functions: linear at
+            // P2/P3, quadratic at P4); one whose members cannot fix a
+            // linear polynomial (all in one plane through the centroid,
             // as on thin boundary-layer cells: a column of A vanishes up to
             // rounding, which the solve's unit-norm column scaling would
             // hide) is dropped like a sector with too few candidates, the
@@ -729,18 +731,18 @@ int build_operators(Mesh& m, int nt) {
                 int nd = m.nds[c * kMaxFaces + s];
                 int64_t* ids = &m.dir[(size_t(c) * kMaxFaces + s) * kMaxDir];
                 for (int j = 0; j < nd; ++j) {
-                    row(ids[j], 3, A + j * 3);
+                    row(ids[j], kd, A + j * kd);
                     w[j] = m.vol[ids[j]];
                 }
                 double cmin = INFINITY, cmax = 0;
                 for (int k = 0; k < 3; ++k) {
                     double cn = 0;
-                    for (int j = 0; j < nd; ++j) cn += A[j * 3 + k] * A[j * 3 + k];
+                    for (int j = 0; j < nd; ++j) cn += A[j * kd + k] * A[j * kd + k];
                     cmin = std::min(cmin, std::sqrt(cn));
                     cmax = std::max(cmax, std::sqrt(cn));
                 }
                 double rc;
-                if (!lsq_pinv(nd, 3, A, w, B, &rc) || rc < 1e-9 || cmin < 1e-8 * cmax) {
+                if (!lsq_pinv(nd, kd, A, w, B, &rc) || rc < 1e-9 || cmin < 1e-8 * cmax) {
                     for (int t = s; t + 1 < m.ndir[c]; ++t) {
                         m.nds[c * kMaxFaces + t] = m.nds[c * kMaxFaces + t + 1];
                         m.dface[c * kMaxFaces + t] = m.dface[c * kMaxFaces + t + 1];
@@ -751,9 +753,9 @@ int build_operators(Mesh& m, int nt) {
                     m.ndropped[c]++;
                     continue;
                 }
-                for (int k = 0; k < 3; ++k)
+                for (int k = 0; k < kd; ++k)
                     for (int j = 0; j < nd; ++j)
-                        m.Bd[((size_t(c) * m.nd_max + s) * 3 + k) * m.md_pad + j] = B[k * nd + j];
+                        m.Bd[((size_t(c) * m.nd_max + s) * kd + k) * m.md_pad + j] = B[k * nd + j];
                 ++s;
             }
             // smoothness-indicator matrix:
@@ -872,8 +874,8 @@ int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads,
         set_error("null argument");
         return UCNS_EINVAL;
     }
-    if (o->order < 2 || o->order > 3) {
-        set_error("order must be 2 or 3");
+    if (o->order < 2 || o->order > 4) {
+        set_error("order must be 2, 3 or 4");
         return UCNS_EINVAL;
     }
     if (d->n_cell <= 0 || d->n_vert <= 0 || !d->xyz || !d->type || !d->cell_ptr || !d->cell_vtx) {
@@ -895,6 +897,9 @@ int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads,
     for (int a = 0; a < 3; ++a) m->period[a] = d->period[a];
     m->order = o->order;
     m->K = (o->order + 1) * (o->order + 2) * (o->order + 3) / 6 - 1;
+    // directional polynomials: linear for the third- and fourth-order
+    // schemes, quadratic for the fifth (Sec. 2.2)
+    m->kd = o->order >= 4 ? 9 : 3;
     m->lambda_c = o->lambda_c;
     m->eps = o->eps;
     m->max_layers = o->max_layers;
@@ -915,6 +920,12 @@ int build_mesh(const ucns_mesh_desc* d, const ucns_recon_opts* o, int n_threads,
             face_verts(t, lf, &fnv);
             (fnv == 3 ? has_tri : has_quad) = true;
         }
+    }
+    if (o->order >= 4 && has_tri) {
+        set_error("order 4 is built for meshes of quadrilateral faces only (the 3-point triangle rule is exact "
+                  "to degree 2)");
+        delete m;
+        return UCNS_EINVAL;
     }
     m->qmax = std::max(has_quad ? o->order * o->order : 0, has_tri ? 3 : 0);
     for (int64_t c = 1; c < m->nc; ++c)
@@ -972,6 +983,7 @@ template <class T>
 void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     const int64_t nc = m.nc, nf = m.nf;
     const int K = m.K, Q = m.qmax, NF = m.nfmax, MC = m.mc_pad, ND = std::max(1, m.nd_max), MD = std::max(1, m.md_pad);
+    const int KD = m.kd;
     auto* sten_c = reinterpret_cast<int32_t*>(base + a.sten_c);
     auto* Bc = reinterpret_cast<T*>(base + a.Bc);
     auto* ndir = reinterpret_cast<uint8_t*>(base + a.ndir);
@@ -1036,9 +1048,9 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
             std::sort(perm.begin(), perm.begin() + nd, [&](int x, int y) { return dids[x] < dids[y]; });
             for (int j = 0; j < MD; ++j) {
                 sten_d[(size_t(s) * MD + j) * nc + c] = j < nd ? int32_t(dids[perm[j]]) : int32_t(c);
-                for (int k = 0; k < 3; ++k)  // member-major rows: (s, j, k) at ((s MD + j) 3 + k) nc
-                    Bd[((size_t(s) * MD + j) * 3 + k) * nc + c] =
-                        j < nd ? T(m.Bd[((size_t(c) * m.nd_max + s) * 3 + k) * m.md_pad + perm[j]]) : T(0);
+                for (int k = 0; k < KD; ++k)  // member-major rows: (s, j, k) at ((s MD + j) kd + k) nc
+                    Bd[((size_t(s) * MD + j) * KD + k) * nc + c] =
+                        j < nd ? T(m.Bd[((size_t(c) * m.nd_max + s) * KD + k) * m.md_pad + perm[j]]) : T(0);
             }
         }
         int t = 0;
@@ -1086,7 +1098,7 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.Bc = take(ts * K * MC * nc);
     a.ndir = take(nc);
     a.sten_d = take(4 * ND * MD * nc);
-    a.Bd = take(ts * ND * 3 * MD * nc);
+    a.Bd = take(ts * ND * m.kd * MD * nc);
     a.O = take(ts * K * (K + 1) / 2 * nc);
     a.xi = take(ts * NF * Q * 3 * nc);
     a.pmean = take(ts * K * nc);

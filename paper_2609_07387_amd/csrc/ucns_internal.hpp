@@ -11,12 +11,16 @@
 namespace ucns {
 
 constexpr int kMaxFaces = 6;     // faces per cell
-constexpr int kMaxQ = 9;         // quadrature points per face (3x3 at P3)
-constexpr int kMaxK = 19;        // unknowns at P3
-constexpr int kMaxCentral = 64;  // central stencil cap
-constexpr int kMaxDir = 16;      // directional stencil cap
-constexpr int kDirTarget = 8;    // directional stencil size before closure
-constexpr int kDirMin = 4;       // fewer candidates drop the sector
+constexpr int kMaxQ = 16;         // quadrature points per face (4x4 at P4)
+constexpr int kMaxK = 34;         // unknowns at P4
+constexpr int kMaxKd = 9;         // unknowns of a directional polynomial (quadratic at P4)
+constexpr int kMaxCentral = 128;  // central stencil cap
+constexpr int kMaxDir = 32;       // directional stencil cap
+// Directional stencils of a polynomial with kd unknowns: the 2 (kd + 1)
+// nearest sector candidates before closure (8 linear, 20 quadratic); fewer
+// than kd + 1 drop the sector (4 linear, 10 quadratic).
+inline int dir_target(int kd) { return 2 * (kd + 1); }
+inline int dir_min(int kd) { return kd + 1; }
 constexpr int kNumVar = 5;
 
 void set_error(const std::string& msg);
@@ -57,6 +61,7 @@ struct Mesh {
     double period[3] = {0, 0, 0};
     // ---- options
     int order = 2, K = 9, qmax = 4, nfmax = 6, max_layers = 3;
+    int kd = 3;  // unknowns of the directional polynomials: 3 (linear, P2/P3), 9 (quadratic, P4)
     bool uniform_type = true;  // every cell of one type
     double lambda_c = 1000.0, eps = 1e-12;
     double stencil_factor = 2.0;  // central stencil = round(stencil_factor K(r,3)) cells
@@ -83,7 +88,7 @@ struct Mesh {
     int mc_pad = 0, md_pad = 0, nd_max = 0, mc_min = 0;
     // ---- operators (FP64, cell-major, for packing and inspection)
     std::vector<double> Bc;       // [nc][K][mc_pad]
-    std::vector<double> Bd;       // [nc][nd_max][3][md_pad]
+    std::vector<double> Bd;       // [nc][nd_max][kd][md_pad]
     std::vector<double> O;        // [nc][K][K]
     std::vector<double> Phi;      // [nc][nfmax][qmax][K]
     std::vector<double> xi;       // [nc][nfmax][qmax][3] face points in the cell's scaled frame

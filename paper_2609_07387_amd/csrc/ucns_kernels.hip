@@ -959,7 +959,7 @@ int ucns_mesh_info(const ucns_mesh* mesh, int64_t* info) {
     UCNS_REQUIRE(mesh && info, UCNS_EINVAL, "null argument");
     const Mesh& m = *mesh->m;
     int64_t v[16] = {m.nc, m.nf, m.K, m.qmax, m.nfmax, m.mc_pad, m.nd_max, m.md_pad, m.nbnd, m.n_dropped_total,
-                     m.mc_min, m.mc_pad, m.order, 0, 0, 0};
+                     m.mc_min, m.mc_pad, m.order, m.kd, 0, 0};
     std::memcpy(info, v, sizeof v);
     return UCNS_OK;
 }
@@ -1045,9 +1045,9 @@ int ucns_mesh_operators(const ucns_mesh* mesh, int64_t cell, double* Bc, double*
             for (int j = 0; j < m.ncen[cell]; ++j) Bc[k * m.ncen[cell] + j] = m.Bc[(size_t(cell) * K + k) * m.mc_pad + j];
     if (Bd)
         for (int s = 0; s < m.ndir[cell]; ++s)
-            for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < m.kd; ++k)
                 for (int j = 0; j < m.nds[cell * kMaxFaces + s]; ++j)
-                    Bd[(s * 3 + k) * kMaxDir + j] = m.Bd[((size_t(cell) * m.nd_max + s) * 3 + k) * m.md_pad + j];
+                    Bd[(s * m.kd + k) * kMaxDir + j] = m.Bd[((size_t(cell) * m.nd_max + s) * m.kd + k) * m.md_pad + j];
     if (O) std::memcpy(O, &m.O[size_t(cell) * K * K], sizeof(double) * K * K);
     if (Phi) std::memcpy(Phi, &m.Phi[size_t(cell) * m.nfmax * m.qmax * K], sizeof(double) * m.nfmax * m.qmax * K);
     return UCNS_OK;

@@ -19,7 +19,7 @@ F64, F32 = 0, 1
 RUSANOV, HLLC = 0, 1
 GRADIENTS = {"green_gauss": 0, "least_squares": 1}  # ucns_phys.grad
 BC_NONE, BC_DIRICHLET, BC_TRANSMISSIVE, BC_WALL, BC_SYMMETRY = 0, 1, 2, 3, 4
-MAX_FACES, MAX_DIR = 6, 16
+MAX_FACES, MAX_DIR, MAX_CENTRAL = 6, 32, 128
 
 # Names declared in include/ucns.h (checked by the test-suite against the
 # library's exports).
@@ -179,7 +179,7 @@ class Mesh:
         info = np.zeros(16, np.int64)
         check(L.ucns_mesh_info(self.h, _np(info)))
         (self.n_cell, self.n_face, self.K, self.qmax, self.nfmax, self.mc_pad, self.nd_max, self.md_pad,
-         self.n_bnd, self.n_dropped, self.mc_min, _, self.order) = (int(x) for x in info[:13])
+         self.n_bnd, self.n_dropped, self.mc_min, _, self.order, self.kd) = (int(x) for x in info[:14])
         fs, ff, gw, rs = (np.zeros(1, np.int64) for _ in range(4))
         check(L.ucns_workspace_elems(self.h, _np(fs), _np(ff), _np(gw), _np(rs)))
         self.n_face_state, self.n_face_flux, self.n_grad, self.n_reduce = int(fs[0]), int(ff[0]), int(gw[0]), int(rs[0])
@@ -210,7 +210,7 @@ class Mesh:
         return vol, cen, hb
 
     def stencil(self, cell):
-        cen = np.zeros(64, np.int64)
+        cen = np.zeros(MAX_CENTRAL, np.int64)
         n = np.zeros(1, np.int32)
         d = np.zeros((MAX_FACES, MAX_DIR), np.int64)
         nd = np.zeros(MAX_FACES, np.int32)
@@ -224,7 +224,7 @@ class Mesh:
         cen, dirs, _ = self.stencil(cell)
         K = self.K
         Bc = np.zeros((K, len(cen)))
-        Bd = np.zeros((MAX_FACES, 3, MAX_DIR))
+        Bd = np.zeros((MAX_FACES, self.kd, MAX_DIR))
         O = np.zeros((K, K))
         Phi = np.zeros((self.nfmax, self.qmax, K))
         check(lib().ucns_mesh_operators(self.h, int(cell), _np(Bc), _np(Bd), _np(O), _np(Phi)))

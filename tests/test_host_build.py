@@ -38,6 +38,8 @@ def _meshes():
         "tetbox": (inputs.kuhn_tet_mesh((4, 3, 3), (4.0, 1.0, 1.0), (False, True, True), 0.15, seed=3), 2),
         "hexbox": (inputs.hex_box_mesh((4, 3, 3), (1.0, 1.0, 1.0), (False, True, False)), 2),
         "mixed": (inputs.mixed_bl_mesh((9, 5, 6), (4.0, 1.0, 0.5), (2, 2), 2, 1.2, 0.05), 2),
+        # P4 (CWENOZ5): 34 unknowns, quadratic directional stencils, 4 x 4 face points
+        "hex98p4": (inputs.hex_box_mesh((9, 8, 8), (2 * math.pi * 9 / 8, 2 * math.pi, 2 * math.pi), (True,) * 3), 4),
     }
 
 
@@ -100,7 +102,7 @@ def test_host_build_matches_oracle(name):
     assert worst < OP_TOL.get(name, 1e-12), worst
 
 
-@pytest.mark.parametrize("name", list(_meshes().keys()))
+@pytest.mark.parametrize("name", [k for k in _meshes().keys() if k != "hex98p4"])
 def test_lsq_gradient_weights_match_oracle(name):
     """The library's least-squares gradient weights (built with the mesh)
     applied on the host to a smooth random field give the oracle's

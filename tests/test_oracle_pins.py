@@ -78,21 +78,28 @@ def test_benchmark_table_counts():
     hexm = inputs.periodic_hex_mesh(6)
     tetm = inputs.kuhn_tet_mesh((3, 3, 3), (1.0,) * 3, (True,) * 3, 0.15, seed=0)
     got = {}
-    for r in (2, 3):
-        om = oracle.OracleMesh(hexm, order=r)
+    for r in (2, 3, 4):
+        # P4 stencils reach three cells out: a periodic cube of 8 cells per side
+        m = inputs.periodic_hex_mesh(8) if r == 4 else hexm
+        need = np.zeros(m.n_cell, np.uint8)
+        need[0] = 1
+        om = oracle.OracleMesh(m, order=r, need=need)
         cen, dirs, _ = om.stencil(0)
-        got[("hex", r)] = (om.K, len(dirs), om.nq_max)
+        got[("hex", r)] = (om.K, len(dirs), om.kd, om.nq_max)
+        if r == 4:
+            # the fifth-order scheme's directional polynomials are quadratic
+            # (Sec. 2.2, Fig. stencils): six of them, 20 nearest closed over
+            # ties = 22 cells on the lattice; central 70 closed to 80
+            assert om.kd == 9 and [len(d) for d in dirs] == [22] * 6 and len(cen) == 80
+            continue
         om = oracle.OracleMesh(tetm, order=r)
         cen, dirs, _ = om.stencil(5)
-        got[("tet", r)] = (om.K, len(dirs), om.nq_max)
+        got[("tet", r)] = (om.K, len(dirs), om.kd, om.nq_max)
     for row in rows:
         r, ctype = row["order"], row["cell_type"]
-        if r == 4:
-            # P4 (next step): 34 central unknowns, quadratic directional (9), 4x4 face points
-            K, nd, kd, nq = 34, 6, 9, 16
-        else:
-            K, nd, nq = got[(ctype, r)]
-            kd = 3  # linear directional polynomials at 3rd/4th order (Sec. 2.2)
+        # linear directional polynomials (kd = 3) at 3rd/4th order, quadratic
+        # (kd = 9) from 5th order on (Sec. 2.2)
+        K, nd, kd, nq = got[(ctype, r)]
         assert row["cells"] * (K + nd * kd) == pytest.approx(row["dof_per_var"], rel=1e-12)
         if ctype == "hex":
             assert row["faces"] * nq == pytest.approx(row["face_qps"], rel=1e-12)
@@ -222,14 +229,20 @@ def test_pseudo_inverse_matches_library_pinv():
 # ------------------------------------------------------------------ Pi 4
 
 
-@pytest.mark.parametrize("ctype,order", [("hex", 2), ("tet", 2), ("tet", 3), ("hex", 3)])
+@pytest.mark.parametrize("ctype,order", [("hex", 2), ("tet", 2), ("tet", 3), ("hex", 3), ("hex", 4)])
 def test_polynomial_reproduction(ctype, order):
     """Linear (central) path reproduces polynomials of degree <= r exactly at
     every face QP (eq. lsq_system is exact for them); full CWENOZ reproduces
-    degree <= 1 exactly (all candidates equal -> tau = 0 -> omega = lambda ->
-    the LPR blend returns p_opt, Sec. 2.2 smooth-region recovery)."""
+    polynomials of the directional degree exactly (degree <= 1 at P2/P3,
+    degree <= 2 at P4): all candidates equal -> tau = 0 -> omega = lambda ->
+    the LPR blend returns p_opt, Sec. 2.2 smooth-region recovery."""
     need = None
-    if ctype == "hex" and order == 3:
+    if ctype == "hex" and order == 4:
+        n = 10
+        m = inputs.hex_box_mesh((n, n, n), (1.0,) * 3, (False,) * 3)
+        ijk = np.stack(np.unravel_index(np.arange(n ** 3), (n, n, n)), axis=1)
+        need = np.all((ijk >= 3) & (ijk <= n - 4), axis=1).astype(np.uint8)
+    elif ctype == "hex" and order == 3:
         # a nearest-centroid stencil of a cell on a flat wall never reaches the
         # third layer normal to it at P3: check cells three layers inside
         n = 8
@@ -248,7 +261,7 @@ def test_polynomial_reproduction(ctype, order):
     fs = om.reconstruct(U, ph, gate_mask=np.ones(om.n_cell, np.uint8))
     scale = np.abs(U).max()
     assert max_face_error(om, fs, f) < 1e-13 * scale * 10
-    f1 = random_poly(1, seed=7)
+    f1 = random_poly(2 if order == 4 else 1, seed=7)
     U1 = poly_cell_averages(om, f1)
     fs1, flags, label = om.reconstruct(U1, ph, with_flags=True)
     assert max_face_error(om, fs1, f1) < 1e-13 * np.abs(U1).max() * 10
@@ -845,10 +858,12 @@ def _si_closed_form_cube(L):
         (2, 0, 0): 4 * L ** 5 / 12 / L + 4 * L ** 3 * L,    # q = x^2: 2x, then 2
         (1, 1, 0): 2 * (L ** 5 / 12) / L + L ** 3 * L,      # q = xy: y and x, then D^(1,1,0) = 1 once
         (3, 0, 0): 9 * L ** 7 / 80 / L + 36 * L ** 5 / 12 * L + 36 * L ** 3 * L ** 3,  # q = x^3: 3x^2, 6x, 6
+        # q = x^4: 4x^3, 12x^2, 24x, 24 (int s^6 = L^7/448), weights L^-1, L, L^3, L^5
+        (4, 0, 0): 16 * L ** 9 / 448 / L + 144 * L ** 7 / 80 * L + 576 * L ** 5 / 12 * L ** 3 + 576 * L ** 3 * L ** 5,
     }
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_smoothness_indicator_closed_form_on_a_cube(order):
     """O6 (Sec. 2.2, eq. cwenoz_weights; indicator reading): for a polynomial
     q = sum_k a_k phi_k, a^T O a = sum over multi-indices 1 <= |beta| <= r,
@@ -856,10 +871,12 @@ def test_smoothness_indicator_closed_form_on_a_cube(order):
     derivatives.  On a cube of side L != 1 the closed forms fix the
     derivative factors, the multi-index count and the volume exponent."""
     L = 0.7
-    m = inputs.periodic_hex_mesh(6, length=6 * L)
-    om = oracle.OracleMesh(m, order=order)
-    vol, cen, hb = om.cell_data()
+    m = inputs.periodic_hex_mesh(8, length=8 * L)
     c = 7
+    need = np.zeros(m.n_cell, np.uint8)
+    need[c] = 1
+    om = oracle.OracleMesh(m, order=order, need=need)
+    vol, cen, hb = om.cell_data()
     O = om.operators(c)["O"]
     h = hb[c]
     ex = _monomial_exponents(order)
@@ -1068,3 +1085,84 @@ def test_p3_jittered_tets_stability_and_stencil_size():
         U, ke, _ = om3.run(U0, ph, 0.5, 100, gate_mask=gm)
         assert np.abs(ke / ke[0] - 1).max() < 0.01
         assert 0.99 < U[0].min() and U[0].max() < 1.01
+
+
+# ------------------------------------------------------------------ P4 (CWENOZ5)
+
+
+def _sampled_face_error(n, order, gate, seed=0, cells=30):
+    """Max point error of the reconstruction of a smooth periodic field at the
+    face points of sampled cells of a periodic n^3 hex cube (only those cells'
+    operators are built)."""
+    m = inputs.periodic_hex_mesh(n)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(m.n_cell, cells, replace=False)
+    need = np.zeros(m.n_cell, np.uint8)
+    need[pick] = 1
+    om = oracle.OracleMesh(m, order=order, need=need)
+
+    def f(x):
+        s = np.sin(x[:, 0]) * np.cos(x[:, 1]) * np.sin(x[:, 2] + 0.3) + 2.0
+        return np.stack([s, 0.5 * s, 0 * s + 1.0, s * s, s + 10.0], axis=1)
+
+    U = np.zeros((5, om.n_cell))
+    # cell averages only where the sampled cells' stencils reach
+    reach = set()
+    for c in pick:
+        cen, dirs, _ = om.stencil(c)
+        reach.update(int(j) for j in cen)
+        for d in dirs:
+            reach.update(int(j) for j in d)
+        reach.add(int(c))
+    for c in reach:
+        x, w = om.cell_quadrature(c)
+        U[:, c] = (w[:, None] * f(x)).sum(0) / w.sum()
+    fs = om.reconstruct(U, oracle.phys(), gate_mask=np.ones(om.n_cell, np.uint8) if gate else None)
+    c2f, side = om.cell_faces()
+    fd = om.face_data()
+    err = 0.0
+    for c in pick:
+        for lf in range(6):
+            fi, s = c2f[c, lf], side[c, lf]
+            q = fd["nq"][fi]
+            pts = fd["qp"][fi, :q] - (fd["shift"][fi] if s == 1 else 0.0)
+            err = max(err, float(np.abs(fs[fi, s, :q] - f(pts)).max()))
+    return err
+
+
+@pytest.mark.slow
+def test_p4_reconstruction_design_order():
+    """P4 CWENOZ5 on smooth data (Sec. 2.2: fifth-order scheme, weights tend
+    to the linear weights in smooth regions): the point error at the face
+    Gauss points falls at the design rate r + 1 = 5 under refinement, for the
+    central polynomial and for the full CWENOZ blend (slope >= 4.5 between
+    16^3 and 24^3; measured about 4.9)."""
+    for gate in (True, False):
+        e = [_sampled_face_error(n, 4, gate) for n in (16, 24)]
+        rate = math.log(e[0] / e[1]) / math.log(24 / 16)
+        assert rate >= 4.5, (gate, e, rate)
+
+
+def test_p4_free_stream_and_conservation():
+    """P4 on a periodic 9 x 8 x 8 hex box: a uniform stream has zero residual
+    (to rounding of the flux scale), and a non-uniform state's volume-weighted
+    residual sums to zero for every conserved variable (single-valued face
+    fluxes)."""
+    m = inputs.hex_box_mesh((9, 8, 8), (2 * math.pi * 9 / 8, 2 * math.pi, 2 * math.pi), (True, True, True))
+    om = oracle.OracleMesh(m, order=4)
+    vol, _, _ = om.cell_data()
+    ph = oracle.phys(flux="hllc")
+    U = inputs.uniform_state(m, 1.3, [0.2, -0.1, 0.3], 2.0)
+    R = om.rhs(U, ph)
+    assert np.abs(R).max() < 1e-12 * (2.0 + 1.3)
+    U = inputs.tgv_initial(m, noise_seed=5)
+    R = om.rhs(U, ph)
+    tot = (R * vol[None, :]).sum(axis=1)
+    assert np.abs(tot).max() < 1e-12 * (np.abs(R) * vol[None, :]).sum(axis=1).max()
+    # near a jump the nonlinear weights leave the linear ones; smooth cells keep them
+    U = inputs.tgv_initial(m)
+    cx = inputs.cell_averages(m, lambda x: np.stack([x[..., 0]] * 5, axis=-1))[:, 0]
+    U[0] = np.where(cx < math.pi, 1.0, 0.5)
+    U[4] = np.where(cx < math.pi, 2.5 / 0.4, 1.0 / 0.4) + 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2)
+    _, _, label = om.reconstruct(U, ph, with_flags=True)
+    assert label.max() > 0.3
