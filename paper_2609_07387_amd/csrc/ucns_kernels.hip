@@ -117,6 +117,7 @@ __device__ __forceinline__ int tri_index(int K, int k, int l) { return k * K - (
 
 #include "mlp_kernels.hpp"
 #include "recon_kernel.hpp"
+#include "recon_p4.hpp"
 
 // ------------------------------------------------------------------ physics
 
@@ -864,12 +865,29 @@ int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
     return UCNS_OK;
 }
 
+// P4: one lane per (cell, variable), 12 cells per wave; full CWENOZ only
+// (the gate's network is trained on P2 features).
+template <class T>
+int launch_recon_p4(const ReconArgs<T>& A, hipStream_t st) {
+    if (A.Q > kP4Q || A.NF > kMaxFaces || A.mlp || A.gate) return UCNS_EINVAL;
+    if (recon_span_bytes(A.nc, int(sizeof(T)), kP4K, A.NF) > kMaxDescriptorBytes) return UCNS_EINVAL;
+    const int64_t per_block = int64_t(kBlock / 64) * kP4Cells;
+    const dim3 grid(unsigned((A.nc + per_block - 1) / per_block)), block(kBlock);
+    if (A.label)
+        hipLaunchKernelGGL((reconstruct_p4_kernel<T, true>), grid, block, 0, st, A);
+    else
+        hipLaunchKernelGGL((reconstruct_p4_kernel<T, false>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((reconstruct_p4_fallback_kernel<T>), dim3(grid_for(A.nc)), block, 0, st, A);
+    return UCNS_OK;
+}
+
 template <class T>
 int launch_recon(const Mesh& m, const Arena& ar, double gm1, const double* U, const ucns_gate* gate, void* fs,
                  uint8_t* flags, float* label, hipStream_t st) {
     const ReconArgs<T> A = make_recon_args<T>(m, ar, gm1, U, gate, fs, flags, label);
     if (m.K == 9) return launch_recon_k<T, 9>(A, st);
     if (m.K == 19) return launch_recon_k<T, 19>(A, st);
+    if (m.K == kP4K) return launch_recon_p4<T>(A, st);
     return UCNS_EINVAL;
 }
 
@@ -1106,8 +1124,8 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
     const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
                                          : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);
     if (rc != UCNS_OK) {
-        set_error("unsupported reconstruction order, face-point count, or a mesh beyond the 4 GiB span of one "
-                  "buffer descriptor (ucns_recon_span_bytes)");
+        set_error("unsupported reconstruction order or face-point count, a gate at P4 (its network is trained "
+                  "at P2), or a mesh beyond the 4 GiB span of one buffer descriptor (ucns_recon_span_bytes)");
         return rc;
     }
     return hip_check("ucns_reconstruct");

@@ -63,7 +63,16 @@ CASES = {
                                                          seed=8), 2,
                             dict(flux="hllc", viscous=True, mach=0.5, reynolds=20.0, gradients="least_squares"),
                             "slab", "sym"),
+    # P4 (CWENOZ5): 9 x 8 x 8 periodic hexahedra (576 cells: two 256-cell
+    # blocks and a ragged tail; the Taylor-Green field is not periodic over
+    # the box's x length, so the seam is a jump and the weights move)
+    "hex98_p4_hllc": (lambda: _p4_box(), 4, dict(flux="hllc"), "tgv", None),
+    "hex98_p4_hllc_ns": (lambda: _p4_box(), 4, dict(flux="hllc", viscous=True), "tgv", None),
 }
+
+
+def _p4_box():
+    return inputs.hex_box_mesh((9, 8, 8), (2 * math.pi * 9 / 8, 2 * math.pi, 2 * math.pi), (True, True, True))
 
 
 def _slab_state(x):
@@ -143,7 +152,8 @@ def test_stage_intermediates_fp64(torch_cuda, name):
 
 
 @pytest.mark.parametrize("name,steps", [("hex16_p2_rusanov", 10), ("hex7_p2_hllc_ns", 10), ("tet4_p2_hllc", 5),
-                                        ("tet3_p3_hllc", 3), ("tet_shock_box", 5), ("mixed_bl_ns", 5),
+                                        ("tet3_p3_hllc", 3), ("hex98_p4_hllc", 10), ("tet_shock_box", 5),
+                                        ("mixed_bl_ns", 5),
                                         ("tet4_p2_hllc_ns_lsq", 5), ("mixed_bl_ns_lsq", 5), ("tet_slab_sym_ns", 5),
                                         ("tet_slab_sym_ns_lsq", 5)])
 def test_steps_fp64(torch_cuda, name, steps):
@@ -423,3 +433,24 @@ def test_check_flags_a_bad_state(torch_cuda):
     with pytest.raises(ucns.UcnsError) as e:
         s2.run(Ub, 1)
     assert "error -7" in str(e.value)
+
+
+def test_p4_fp32_and_positivity(torch_cuda):
+    """P4 FP32: 10 steps within single-precision error of the FP64 oracle;
+    a near-vacuum cell next to a jump takes the first-order fallback on the
+    GPU exactly where the oracle does (FP64)."""
+    m, order, ph, U, bcs = _setup("hex98_p4_hllc")
+    lm = ucns.Mesh(m, order=order)
+    om = oracle.OracleMesh(m, order=order)
+    Ug, _, _ = gpu_run(lm, ph, U, ucns.F32, 10, 0.5)
+    Uo, _, _ = om.run(U, as_oracle_phys(ph), 0.5, 10)
+    err = grouped_rel_linf(Ug, Uo)
+    print(f"[gpu] P4 FP32 10-step rel Linf {err:.2e}", flush=True)
+    assert err < 1e-4
+    Ub = inputs.uniform_state(m, 1.0, [0, 0, 0], 1.0)
+    Ub[0, 10], Ub[4, 10] = 1e-3, 1e-3 / 0.4
+    Ub[0, 11], Ub[4, 11] = 50.0, 50.0 / 0.4
+    fs, _, _, R, flags = gpu_stage(lm, ph, Ub, ucns.F64)
+    ofs, _, _, oR, oflags, _ = oracle_stage(om, as_oracle_phys(ph), Ub)
+    assert np.array_equal(flags, oflags) and (flags & 4).any()
+    assert grouped_rel_linf(R, oR) < 1e-11
