@@ -49,7 +49,8 @@ def recon_bytes_per_cell(lm, precision, linear=False, gate=False):
     ids and offsets, basis scale, stencil size) and its mask output."""
     t = 8 if precision == 0 else 4
     K, MC, MD, ND, NF, Q = lm.K, lm.mc_pad, max(1, lm.md_pad), max(1, lm.nd_max), lm.nfmax, lm.qmax
-    ops = K * MC + NF * Q * 3 + K + (0 if linear else K * (K + 1) // 2 + ND * 3 * MD)
+    KD = getattr(lm, "kd", 3)  # terms of a directional polynomial (3 linear, 9 quadratic at P4)
+    ops = K * MC + NF * Q * 3 + K + (0 if linear else K * (K + 1) // 2 + ND * KD * MD)
     idx = MC + (0 if linear else ND * MD)
     extra = (4 * NF + 3 * NF * t + t + 1 + 1) if gate else 0
     return t * ops + 4 * idx + NF + 1 + 40 + t * 5 * NF * Q + 1 + extra
@@ -205,10 +206,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-lattice", default="650,36,128",
                     help="mixed_bl: lattice cubes along x, y, z (650,36,128 gives about 8M cells)")
-    ap.add_argument("--workload", choices=("tgv_hex_p2", "tgv_tet_p3", "mixed_bl"), default="tgv_hex_p2",
+    ap.add_argument("--workload", choices=("tgv_hex_p2", "tgv_tet_p3", "tgv_hex_p4", "mixed_bl"),
+                    default="tgv_hex_p2",
                     help="tgv_hex_p2: the headline (FP64 plain vs FP32 + gate); tgv_tet_p3: the 48^3 x 6 "
-                         "jittered-tet P3 Euler case, FP64 and FP32 throughput; mixed_bl: the 8M-cell mixed-"
-                         "element boundary-layer box, FP64 plain and FP32 + gate throughput and memory")
+                         "jittered-tet P3 Euler case, FP64 and FP32 throughput; tgv_hex_p4: the 64^3 hex TGV "
+                         "with P4 CWENOZ5 (the paper's profiled scheme), Euler, FP64 and FP32 throughput; "
+                         "mixed_bl: the 8M-cell mixed-element boundary-layer box, FP64 plain and FP32 + gate "
+                         "throughput and memory")
     ap.add_argument("--gradients", choices=("green_gauss", "least_squares"), default="green_gauss",
                     help="viscous cell gradients of the Navier-Stokes workloads")
     ap.add_argument("--runs", type=int, default=1,
@@ -225,8 +229,8 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload == "tgv_tet_p3":
-        return main_tet_p3(args)
+    if args.workload in ("tgv_tet_p3", "tgv_hex_p4"):
+        return main_tet_p3(args) if args.workload == "tgv_tet_p3" else main_hex_p4(args)
     if args.workload == "mixed_bl":
         return main_mixed_bl(args, tuple(int(a) for a in args.mixed_lattice.split(",")))
 
@@ -374,6 +378,66 @@ def main_tet_p3(args, n=48):
         "fp64_value": variants["fp64"]["value"],
         "speedup_vs_fp64": hv["value"] / variants["fp64"]["value"],
         "roofline": {"kernel": "ucns_reconstruct call (FP32, K = 19)", "bound": "hbm", "achieved": hv["recon_GBs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hv["recon_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,
+                     "bytes_per_cell": hv["recon_bytes_per_cell"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main_hex_p4(args, n=64):
+    """P4 CWENOZ5 (34-term central polynomial, six quadratic sector
+    polynomials, 4 x 4 face points) on the n^3 periodic hex TGV, HLLC, Euler:
+    FP64 and FP32 cell-stage updates/s and the reconstruction call against
+    its byte model.  The paper profiles this scheme on its TGV (Sec. 5.2).
+    No gate (the network is trained at P2) and no CPU baseline (the oracle's
+    P4 operator build alone takes minutes at this size)."""
+    import torch
+
+    from paper_2609_07387_amd import inputs, ucns
+
+    torch.cuda.set_device(0)
+    m = inputs.periodic_hex_mesh(n)
+    U0 = inputs.tgv_initial(m)
+    ph = ucns.phys(flux="hllc", viscous=False)
+    t0 = time.perf_counter()
+    lm = ucns.Mesh(m, order=4)
+    print(f"[bench] mesh build {time.perf_counter() - t0:.1f} s, {lm.n_cell} cells, {lm.n_face} faces", file=sys.stderr,
+          flush=True)
+    nc = lm.n_cell
+    variants = {}
+    for name, prec in (("fp64", ucns.F64), ("fp32", ucns.F32)):
+        solver = ucns.Solver(lm, ph, prec, cfl=0.5)
+        U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+        ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
+        solver.check()
+        rate = nc * 3 * args.steps / (ms / 1e3)
+        rms, _ = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
+        rbc = recon_bytes_per_cell(lm, prec)
+        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall, "recon_ms": rms,
+                          "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
+                          "arena_GB": lm.arena_bytes(prec) / 1e9,
+                          "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, viscous=False),
+                          "path_GBs": step_bytes_per_cell(lm, prec, viscous=False) * rate / 1e9}
+        print(f"[bench] {name}: {rate:.3e} cell-stage/s, {ms / args.steps:.3f} ms/step, recon {rms:.3f} ms "
+              f"({variants[name]['recon_GBs']:.0f} GB/s algorithmic)", file=sys.stderr, flush=True)
+        del solver
+        lm.release()
+        torch.cuda.empty_cache()
+    hv = variants["fp32"]
+    out = {
+        "metric": "cell-stage updates/s, P4 CWENOZ5 + HLLC on hexahedra", "value": hv["value"],
+        "unit": "cell-stage updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hv["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"TGV {n}^3 periodic hex, P4 CWENOZ5 (34-term central, 6 quadratic sector "
+                               "polynomials, 4 x 4 face points), HLLC, Euler, SSP-RK3 CFL 0.5, per-step KE",
+                   "cells": nc, "faces": lm.n_face, "central_stencil": lm.mc_pad, "sector_stencil": lm.md_pad,
+                   "variant": "fp32 (FP32 reconstruction/flux, FP64 state/RK/reductions)"},
+        "variants": variants,
+        "fp64_value": variants["fp64"]["value"],
+        "speedup_vs_fp64": hv["value"] / variants["fp64"]["value"],
+        "roofline": {"kernel": "ucns_reconstruct call (P4, FP32)", "bound": "hbm", "achieved": hv["recon_GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hv["recon_GBs"] / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,
                      "bytes_per_cell": hv["recon_bytes_per_cell"]},

@@ -192,6 +192,13 @@ int ucns_recon_span_bytes(int64_t n_cell, int precision, int n_unknowns, int n_f
  * with that precision. */
 int ucns_mesh_upload(ucns_mesh* mesh, int precision, void* arena, size_t bytes, ucns_stream stream);
 
+/* The handle forgets the device arena of one precision (no device work), so
+ * that the caller may free it; calls that need that precision then return
+ * UCNS_ESTATE until the next upload.  The precision-independent calls
+ * (ucns_dt, ucns_diag_ke) read the FP64 arena while one is uploaded, else the
+ * FP32 one: release an arena before freeing it. */
+int ucns_mesh_release(ucns_mesh* mesh, int precision);
+
 /* Host-side inspection (for verification): cell-to-face table
  * c2f[c*6+lf] = 2*face + side (-1 unused); face cells [n_face][2] (-1 - tag
  * on a boundary side); face quadrature points [n_face][QMAX][3] in the

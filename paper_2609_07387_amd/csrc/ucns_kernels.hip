@@ -1019,6 +1019,13 @@ int ucns_mesh_upload(ucns_mesh* mesh, int precision, void* arena, size_t bytes, 
     return UCNS_OK;
 }
 
+int ucns_mesh_release(ucns_mesh* mesh, int precision) {
+    UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    mesh->m->arena[precision].dev = nullptr;
+    return UCNS_OK;
+}
+
 int ucns_mesh_faces(const ucns_mesh* mesh, int32_t* c2f, int64_t* fcell, double* qp, double* shift) {
     UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
     const Mesh& m = *mesh->m;

@@ -30,7 +30,7 @@ EXPORTS = [
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
     "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
     "ucns_residual_ssp54_stage", "ucns_mesh_gradient_weights", "ucns_recon_span_bytes",
-    "ucns_check", "ucns_residual_rk_final_noalloc",
+    "ucns_check", "ucns_residual_rk_final_noalloc", "ucns_mesh_release",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
         L.ucns_mesh_info.argtypes = [vp, vp]
         L.ucns_mesh_arena_bytes.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
         L.ucns_mesh_upload.argtypes = [vp, i32, vp, C.c_size_t, vp]
+        L.ucns_mesh_release.argtypes = [vp, i32]
         L.ucns_mesh_faces.argtypes = [vp, vp, vp, vp, vp]
         L.ucns_mesh_cell_geometry.argtypes = [vp, vp, vp, vp]
         L.ucns_mesh_stencil.argtypes = [vp, i64, vp, vp, vp, vp, vp]
@@ -245,6 +246,13 @@ class Mesh:
         check(lib().ucns_mesh_upload(self.h, precision, _dp(arena), nbytes, _stream()))
         self.arenas[precision] = arena
         return arena
+
+    def release(self, precision=None):
+        """Forget the device arena of one precision (both if None) in the
+        library, then drop it (the library must never keep a freed arena)."""
+        for p in ([F64, F32] if precision is None else [precision]):
+            check(lib().ucns_mesh_release(self.h, p))
+            self.arenas.pop(p, None)
 
 
 def _t(precision):

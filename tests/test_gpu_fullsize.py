@@ -96,7 +96,7 @@ def test_tet48_p3_full_size_stage_sampled(torch_cuda):
 
         _, _, ff, R, _ = gpu_stage(lm, ph, U, prec)
         res[prec] = (ff, R)
-        lm.arenas.clear()
+        lm.release()
     rng = np.random.default_rng(9)
     sample = np.unique(np.concatenate([rng.choice(m.n_cell, 150, replace=False), [0, m.n_cell - 1]]))
     c2f, fcell, _, _ = lm.faces()

@@ -52,7 +52,7 @@ def test_large_hex_mesh_fp64_point_states_sampled():
     NF, Q = lm.nfmax, lm.qmax
     g = fs.view(NF, Q, 5, nc)[:, :, :, torch.as_tensor(sample, device="cuda")].cpu().numpy()  # [NF][Q][5][s]
     del fs, Ud
-    lm.arenas.clear()
+    lm.release()
     torch.cuda.empty_cache()
     print("[gpu]   oracle at the sampled cells", flush=True)
     ofs = om.reconstruct(U, as_oracle_phys(ph))  # [n_face][2][QM][5]

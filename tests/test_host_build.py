@@ -176,6 +176,8 @@ def test_entry_points_reject_null_arguments():
         L.ucns_gradients(lm.h, C.byref(ph), None, None, ucns.F64, None, None),
         L.ucns_mesh_gradient_weights(lm.h, 0, None),
         L.ucns_check(None, None),
+        L.ucns_mesh_release(None, ucns.F64),
+        L.ucns_mesh_release(lm.h, 7),
     ]
     assert rcs == [-1] * len(rcs), rcs
     # an unknown gradient method is refused before any device state is looked at
