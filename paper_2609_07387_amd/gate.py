@@ -50,8 +50,8 @@ def shock_box_case(seed, n=(148, 37, 37), lengths=(4.0, 1.0, 1.0)):
     return m, U0, ph, bcs
 
 
-SMOOTH_CASES = ("tgv_hex32", "tgv_tet24", "tgv_hex40", "tgv_hex48")  # the last is held out
-SMOOTH_STEPS = (1, 2, 5, 10, 20, 50, 100, 150, 200, 300, 400)
+SMOOTH_CASES = ("tgv_hex32", "tgv_tet24", "tgv_hex40", "tgv_hex56", "tgv_hex48")  # the last is held out
+SMOOTH_STEPS = (1, 2, 5, 10, 20, 50, 100, 150, 200, 250, 300, 350, 400)
 
 
 def smooth_case(name):
@@ -131,13 +131,18 @@ def init_params(mu, sd, seed=0):
     return p
 
 
-def train(F, Y, epochs=30, batch=1024, lr=1e-3, seed=0, log=print):
-    """Adam training of the gate on the GPU with the library's kernels."""
+def train(F, Y, epochs=30, batch=1024, lr=1e-3, seed=0, log=print, balance="full"):
+    """Adam training of the gate on the GPU with the library's kernels.
+    balance: weight of the troubled class, the negative/positive count ratio
+    ("full") or its square root ("sqrt", which keeps more precision on
+    smooth cells)."""
     import torch
 
     mu, sd = standardisation(F)
     pos = max(float(Y.sum()), 1.0)
     pos_weight = float((len(Y) - pos) / pos)
+    if balance == "sqrt":
+        pos_weight = math.sqrt(pos_weight)
     params = torch.tensor(init_params(mu, sd, seed), device="cuda")
     grads = torch.zeros_like(params)
     adam = torch.zeros(2 * ucns.MLP_NPARAM, dtype=torch.float32, device="cuda")
@@ -185,6 +190,9 @@ def calibrate_theta(params, F, Y, recall=0.995):
     return float(pt[k]), prob
 
 
+_EVAL_CACHE = {}  # built meshes of the evaluation cases, by (seed, lattice) or tag
+
+
 def evaluate(params, seed=6, steps=500, n=(148, 37, 37), cfl=0.5, precision=ucns.F32, case=None, tag=None,
              log=print):
     """Full CWENOZ against the gated solver from the same start: relative L1
@@ -192,9 +200,15 @@ def evaluate(params, seed=6, steps=500, n=(148, 37, 37), cfl=0.5, precision=ucns
     The case is the shocked box of `seed` unless `case` is given."""
     import torch
 
-    m, U0, ph, bcs = shock_box_case(seed, n) if case is None else case
+    key = (seed, tuple(n)) if case is None else tag
+    if key is not None and key in _EVAL_CACHE:
+        m, U0, ph, bcs, lm = _EVAL_CACHE[key]
+    else:
+        m, U0, ph, bcs = shock_box_case(seed, n) if case is None else case
+        lm = ucns.Mesh(m, order=2)
+        if key is not None:
+            _EVAL_CACHE[key] = (m, U0, ph, bcs, lm)
     tag = f"seed {seed}" if tag is None else tag
-    lm = ucns.Mesh(m, order=2)
     vol = torch.tensor(lm.cell_geometry()[0], device="cuda")
     out = {}
     P = torch.tensor(params, device="cuda")
@@ -230,9 +244,15 @@ def evaluate(params, seed=6, steps=500, n=(148, 37, 37), cfl=0.5, precision=ucns
 
 def main():
     """Dataset from shocked-box seeds 1-5 (train 1-4, validate 5) and the
-    smooth cases (train hex32, tet24, hex40; hold out hex48), train, calibrate,
-    save the parameters next to this module, evaluate on seed 6 and on the
-    64^3 hex Taylor-Green vortex."""
+    smooth cases (train hex32, tet24, hex40, hex56; hold out hex48); two
+    networks (class weight n_neg/n_pos and its square root); for each, the
+    threshold of every recall target on the validation seed, the gated
+    shocked-box run on the validation seed against full CWENOZ (500 steps),
+    and the held-out hex48 cells let through.  The network and threshold
+    kept: the one that lets the most held-out smooth cells through among
+    those whose validation run stays within a third of the 1e-3 relative-L1
+    target.  Saved next to this module, then evaluated on the test seed 6
+    and on the 64^3 hex Taylor-Green vortex."""
     import argparse
     import json
 
@@ -242,8 +262,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=None)
-    ap.add_argument("--recall", type=float, default=0.99,
-                    help="troubled-cell recall the threshold keeps on the validation seed")
+    ap.add_argument("--recalls", type=float, nargs="+", default=[0.995, 0.99, 0.98, 0.97, 0.95, 0.93, 0.9],
+                    help="troubled-cell recall targets on the validation seed")
+    ap.add_argument("--l1-bound", type=float, default=3.3e-4,
+                    help="largest relative L1 of the gated validation run a threshold may give")
     args = ap.parse_args()
     n = tuple(args.n)
     data = {s: collect(s, steps=args.steps, first=args.steps // 10, every=args.steps // 10, n=n) for s in range(1, 6)}
@@ -251,22 +273,35 @@ def main():
     Ftr = np.concatenate([data[s][0] for s in range(1, 5)] + [smooth[c][0] for c in SMOOTH_CASES[:-1]])
     Ytr = np.concatenate([data[s][1] for s in range(1, 5)] + [smooth[c][1] for c in SMOOTH_CASES[:-1]])
     Fva, Yva = data[5]
-    params, hist, pw = train(Ftr, Ytr, epochs=args.epochs)
-    theta, prob = calibrate_theta(params, Fva, Yva, recall=args.recall)
-    params[ucns.MLP_OFF["theta"]] = theta
-    smooth_val = float((prob < theta).mean())
     Fho, Yho = smooth[SMOOTH_CASES[-1]]
-    prob_ho = predict(params, Fho)
+    candidates = []
+    for balance in ("full", "sqrt"):
+        params, hist, pw = train(Ftr, Ytr, epochs=args.epochs, balance=balance)
+        prob = predict(params, Fva)
+        prob_ho = predict(params, Fho)
+        for rec in args.recalls:
+            theta, _ = calibrate_theta(params, Fva, Yva, recall=rec)
+            p = params.copy()
+            p[ucns.MLP_OFF["theta"]] = theta
+            ev = evaluate(p, seed=5, steps=args.steps, n=n, log=print)
+            row = {"balance": balance, "pos_weight": pw, "recall_target": rec, "theta": theta,
+                   "val_recall": float((prob[Yva > 0.5] >= theta).mean()) if Yva.sum() else 1.0,
+                   "val_fraction_smooth": float((prob < theta).mean()),
+                   "holdout_smooth_let_through": float((prob_ho[Yho < 0.5] < theta).mean()),
+                   "holdout_troubled_caught": float((prob_ho[Yho > 0.5] >= theta).mean()) if Yho.sum() else 1.0,
+                   "val_rel_L1": ev["rel_L1_gated_vs_full"], "val_fraction_gated": ev["gated"]["fraction_gated"],
+                   "loss_history": hist}
+            print(json.dumps({k: v for k, v in row.items() if k != "loss_history"}), flush=True)
+            candidates.append((row, p))
+    ok = [c for c in candidates if c[0]["val_rel_L1"] <= args.l1_bound]
+    row, params = max(ok or candidates, key=lambda c: (c[0]["holdout_smooth_let_through"], c[0]["theta"]))
     np.save(args.out, params)
-    ev = evaluate(params, steps=args.steps, n=n)
+    ev = evaluate(params, seed=6, steps=args.steps, n=n)
     ev_tgv = evaluate(params, steps=200, case=smooth_case("tgv_hex64"), tag="tgv_hex64")
-    rep = {"recall_target": args.recall, "train_samples": int(len(Ytr)), "val_samples": int(len(Yva)), "train_troubled": float(Ytr.mean()),
-           "pos_weight": pw, "loss_history": hist, "theta": theta, "val_fraction_smooth": smooth_val,
-           "val_recall": float((prob[Yva > 0.5] >= theta).mean()) if Yva.sum() else 1.0,
-           "holdout_" + SMOOTH_CASES[-1]: {"troubled": float(Yho.mean()),
-                                            "fraction_smooth": float((prob_ho < theta).mean())},
-           "eval": ev, "eval_tgv_hex64": ev_tgv}
-    print(json.dumps(rep))
+    rep = {"chosen": row, "train_samples": int(len(Ytr)), "val_samples": int(len(Yva)),
+           "train_troubled": float(Ytr.mean()), "holdout_" + SMOOTH_CASES[-1] + "_troubled": float(Yho.mean()),
+           "candidates": [c[0] for c in candidates], "eval_test_seed6": ev, "eval_tgv_hex64": ev_tgv}
+    print(json.dumps({k: v for k, v in rep.items() if k != "candidates"}), flush=True)
     if args.report:
         with open(args.report, "w") as f:
             json.dump(rep, f, indent=1)
