@@ -701,7 +701,10 @@ int build_operators(Mesh& m, int nt) {
                 }
                 double rc;
                 bool ok = lsq_pinv(n, K, A, w, B, &rc);
-                if (ok && rc >= 1e-9) break;
+                // extended until well conditioned (|R_jj| / |R_11| >= 1e-6):
+                // thin boundary-layer prism stencils otherwise reach
+                // condition numbers near 1e7
+                if (ok && rc >= 1e-6) break;
                 if (n >= m.navail[c]) {
                     std::lock_guard<std::mutex> g(emu);
                     emsg = "cell " + std::to_string(c) + ": central stencil rank deficient";

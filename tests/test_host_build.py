@@ -44,11 +44,13 @@ def _meshes():
 
 
 # Least-squares operators of the two codes agree to rounding times the
-# stencil's condition number: at most 1e-12 on the lattice meshes; on the
-# mixed boundary-layer mesh the thin prism layers under the tetrahedra give
-# stencils with condition numbers near 1e9, where two correct QR solves
-# (Householder against Gram-Schmidt) agree to about 1e-7.
-OP_TOL = {"mixed": 1e-6}
+# stencil's condition number: at most 1e-12 on the lattice meshes.  On the
+# mixed boundary-layer mesh, central stencils are extended until their QR
+# ratio |R_jj|/|R_11| reaches 1e-6 (both codes), which keeps the thin prism
+# layers' stencils at condition numbers below about 2e4 (2.5e7 with the
+# earlier rank-only threshold of 1e-9, where the codes agreed to 1e-7); the
+# two codes' integrals (moments against quadrature) then agree to 1e-11.
+OP_TOL = {"mixed": 3e-11}
 
 
 @pytest.mark.parametrize("name", list(_meshes().keys()))
