@@ -69,16 +69,23 @@ def step_bytes_per_cell(lm, precision, viscous=True, recon=None):
     return recon + flux + grad + resid
 
 
-def time_steps(solver, U, steps, warmup, torch):
+def time_steps(solver, U, steps, warmup, torch, graph=False):
+    """Wall time of `steps` steps after `warmup` untimed ones; with graph, the
+    step is captured once (after the warm-up) and replayed."""
     for _ in range(warmup):
         solver.step(U, ke=True)
+    if graph:
+        solver.capture(U)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(s)
     for _ in range(steps):
-        solver.step(U, ke=True)
+        if graph:
+            solver.step_graph(U)
+        else:
+            solver.step(U, ke=True)
     e1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -220,6 +227,9 @@ def main():
     ap.add_argument("--stencil-factor", type=float, default=2.0,
                     help="tgv_tet_p3: central stencil size over K(r,3) (2: the workload's; 3: the size that is "
                          "stable at P3 on jittered tetrahedra)")
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=False,
+                    help="tgv_hex_p2: time the step as one captured HIP graph replayed (the other mode is "
+                         "reported beside it)")
     ap.add_argument("--integrator", choices=("ssp3", "ssp54"), default="ssp3",
                     help="tgv_hex_p2: SSP-RK3 (3 stages) or the five-stage fourth-order SSP-RK")
     if len(sys.argv) > 1 and sys.argv[1] == "--cpu-baseline-child":
@@ -263,8 +273,14 @@ def main():
         per_run = []
         for _ in range(args.runs):
             U = torch.tensor(U0, dtype=torch.float64, device="cuda")
-            per_run.append(time_steps(solver, U, args.steps, args.warmup, torch))
+            per_run.append(time_steps(solver, U, args.steps, args.warmup, torch, graph=args.graph))
         solver.check()   # the final state is finite with positive density and pressure (host round trip)
+        # the other launch mode, same window (eager launches vs one captured step replayed)
+        U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+        other_solver = ucns.Solver(lm, ph, prec, cfl=0.5, mlp=net, integrator=args.integrator)
+        other_ms, _ = time_steps(other_solver, U, args.steps, args.warmup, torch,
+                                 graph=not args.graph and args.integrator == "ssp3")
+        del other_solver
         ms = sum(r[0] for r in per_run) / len(per_run)
         wall = sum(r[1] for r in per_run) / len(per_run)
         rate = nc * STAGES[args.integrator] * args.steps / (ms / 1e3)
@@ -281,6 +297,7 @@ def main():
         rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate)
                + frac * recon_bytes_per_cell(lm, prec, linear=True, gate=gate))
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
+                          ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps,
                           "ms_per_step_runs": [r[0] / args.steps for r in per_run],
                           "recon_ms": rms, "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
                           "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, recon=rbc),
@@ -357,7 +374,8 @@ def main_tet_p3(args, n=48):
         rate = nc * 3 * args.steps / (ms / 1e3)
         rms, _ = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         rbc = recon_bytes_per_cell(lm, prec)
-        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall, "recon_ms": rms,
+        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
+                          ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps, "recon_ms": rms,
                           "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
                           "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, viscous=False),
                           "path_GBs": step_bytes_per_cell(lm, prec, viscous=False) * rate / 1e9}
@@ -414,7 +432,8 @@ def main_hex_p4(args, n=64):
         rate = nc * 3 * args.steps / (ms / 1e3)
         rms, _ = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         rbc = recon_bytes_per_cell(lm, prec)
-        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall, "recon_ms": rms,
+        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
+                          ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps, "recon_ms": rms,
                           "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
                           "arena_GB": lm.arena_bytes(prec) / 1e9,
                           "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, viscous=False),
@@ -485,6 +504,7 @@ def main_mixed_bl(args, n=(650, 36, 128)):
         rate = nc * 3 * args.steps / (ms / 1e3)
         frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
+                          ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps,
                           "arena_GB": lm.arena_bytes(prec) / 1e9,
                           "device_peak_GB": torch.cuda.max_memory_allocated() / 1e9,
                           "finite": bool(torch.isfinite(U).all())}

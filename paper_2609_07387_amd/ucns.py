@@ -457,18 +457,52 @@ class Solver:
             diag_ke(self.mesh, U, ws.reduce, ws.ke)
             self._dt_key = None  # the next step takes its own dt pass
             return
+        self._step_ssp3(U)
+        self._dt_key = (U.data_ptr(), U._version)
+
+    def _step_ssp3(self, U):
+        """The three stages; the last also leaves the next dt and the kinetic
+        energy in ws.dt and ws.ke (launches only: no host logic that a graph
+        capture would freeze)."""
+        ws = self.ws
         for s in range(2):  # stage 0 stores U^n into U0
             self.rhs_stage(U)
             residual_rk_stage(self.mesh, ws.face_flux, self.precision, s, ws.dt, self.U0, U)
         self.rhs_stage(U)
         residual_rk_final(self.mesh, self.ph, ws.face_flux, self.precision, ws.dt, self.U0, U, self.cfl, ws.reduce,
                           ws.dt, ws.ke)
-        self._dt_key = (U.data_ptr(), U._version)
 
     def check(self):
         """Raises UcnsError if the last computed time step flags a NaN/Inf or
         non-positive state (one host round trip)."""
         check_state(self.ws.dt)
+
+    def capture(self, U):
+        """Records one SSP-RK3 step of U (this tensor, in place) as a HIP
+        graph: the same library calls on the capture stream, replayed by
+        step_graph() with one launch.  The step reads the time step the
+        previous step's last stage left in ws.dt, so U must be the state the
+        solver last stepped (or one whose dt was just computed); capture
+        itself runs no kernel.  SSP-RK3 only; no reconstruction timing
+        events inside the graph."""
+        import torch
+
+        assert self.integrator == "ssp3" and self.recon_events is None
+        self.ensure_dt(U)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=side):
+            self._step_ssp3(U)
+        torch.cuda.current_stream().wait_stream(side)
+        self._graph, self._graph_U = g, U
+        return g
+
+    def step_graph(self, U):
+        """One step by replaying the captured graph (same U tensor)."""
+        assert U is self._graph_U, "the graph steps the tensor it was captured with"
+        self._graph.replay()
+        self._dt_key = (U.data_ptr(), U._version)
 
     def run(self, U, n_steps, ke_history=False, check_every=0):
         """n_steps steps of U in place; with check_every > 0 the state is
