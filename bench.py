@@ -371,11 +371,11 @@ def main_tet_p3(args, n=48):
         solver = ucns.Solver(lm, ph, prec, cfl=0.5)
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
+        solver.check()
         rate = nc * 3 * args.steps / (ms / 1e3)
         rms, _ = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         rbc = recon_bytes_per_cell(lm, prec)
-        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
-                          ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps, "recon_ms": rms,
+        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall, "recon_ms": rms,
                           "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
                           "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, viscous=False),
                           "path_GBs": step_bytes_per_cell(lm, prec, viscous=False) * rate / 1e9}
@@ -432,8 +432,7 @@ def main_hex_p4(args, n=64):
         rate = nc * 3 * args.steps / (ms / 1e3)
         rms, _ = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         rbc = recon_bytes_per_cell(lm, prec)
-        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
-                          ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps, "recon_ms": rms,
+        variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall, "recon_ms": rms,
                           "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
                           "arena_GB": lm.arena_bytes(prec) / 1e9,
                           "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, viscous=False),
@@ -501,10 +500,10 @@ def main_mixed_bl(args, n=(650, 36, 128)):
         solver = ucns.Solver(lm, ph, prec, bcs, cfl=0.5, mlp=net)
         U = torch.tensor(U0, dtype=torch.float64, device="cuda")
         ms, wall = time_steps(solver, U, args.steps, args.warmup, torch)
+        solver.check()   # finite, positive density and pressure (UCNS_ENUM otherwise)
         rate = nc * 3 * args.steps / (ms / 1e3)
         frac = float(solver.ws.mask_out.float().mean()) if net is not None else 0.0
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
-                          ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps,
                           "arena_GB": lm.arena_bytes(prec) / 1e9,
                           "device_peak_GB": torch.cuda.max_memory_allocated() / 1e9,
                           "finite": bool(torch.isfinite(U).all())}
