@@ -75,78 +75,54 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
     // idle lanes shadow the wave's first cell (every load stays in range)
     const int64_t c = valid ? c0 + slot : (c0 < nc ? c0 : nc - 1);
     const int vv = valid ? v : 0;
-    // Every access is a raw buffer load: the array row's base in a scalar
-    // descriptor (row_rsrc, 64-bit scalar arithmetic) and the lane's byte
-    // offset in one 32-bit register, so no load needs per-lane 64-bit
-    // address arithmetic (the launcher bounds every span below 4 GiB).
-    const uint32_t cT = uint32_t(c) * uint32_t(sizeof(T)), c4 = uint32_t(c) * 4u;
-    const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
-    const auto rU = rsrc(A.U, uint64_t(5) * rowU);
-    const uint32_t vrow = uint32_t(vv) * rowU;  // this lane's variable row of U
-    const double ui = bld<double>(rU, c * 8u + vrow, 0u);
-    auto state = [&](int32_t j) { return bld<double>(rU, uint32_t(j) * 8u + vrow, 0u); };
+    const double ui = A.U[vv * nc + c];
+    const double* Uv = A.U + int64_t(vv) * nc;
 
     // (ii) central coefficients; member m's id at sten_c[m][c], its K
-    // operator rows at Bc[m][k][c].  Operators and states load DEPTH members
-    // ahead of the arithmetic, ids one further (a state load waits only for
-    // an id loaded an iteration earlier).
+    // operator rows at Bc[m][k][c].  Operators and states load one member
+    // ahead of the arithmetic, ids two ahead (a state load waits only for an
+    // id loaded an iteration earlier).
     T a[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = T(0);
     const int MC = A.MC;
     {
-        constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
         auto last = [&](int m) { return m < MC ? m : MC - 1; };
-        auto id = [&](int m) { return bld<int32_t>(row_rsrc(A.sten_c, m, nc), c4, 0u); };
-        auto load_b = [&](int m, T* b) {
-            const auto rB = row_rsrc(A.Bc, int64_t(m) * K, nc, K);
+        double un = Uv[A.sten_c[c]];
+        int32_t j2 = A.sten_c[int64_t(last(1)) * nc + c];
+        T bn[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) b[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
-        };
-        double u[DEPTH + 1];
-        T b[DEPTH + 1][K];
-        int32_t jn[DEPTH + 1];
-#pragma unroll
-        for (int d = 0; d <= DEPTH; ++d) jn[d] = id(last(d));
-#pragma unroll
-        for (int d = 0; d < DEPTH; ++d) {
-            u[d] = state(jn[d]);
-            load_b(last(d), b[d]);
-        }
-        int32_t jnext = jn[DEPTH];
+        for (int k = 0; k < K; ++k) bn[k] = A.Bc[int64_t(k) * nc + c];
 #pragma unroll 1
         for (int m = 0; m < MC; ++m) {
-            const int32_t jf = id(last(m + DEPTH + 1));
-            u[DEPTH] = state(jnext);
-            load_b(last(m + DEPTH), b[DEPTH]);
-            const T bv = T(u[0] - ui);
+            const T bv = T(un - ui);
+            T b[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) a[k] += b[0][k] * bv;
+            for (int k = 0; k < K; ++k) b[k] = bn[k];
+            const int mf = last(m + 1);
+            un = Uv[j2];
+            j2 = A.sten_c[int64_t(last(m + 2)) * nc + c];
 #pragma unroll
-            for (int d = 0; d < DEPTH; ++d) {
-                u[d] = u[d + 1];
+            for (int k = 0; k < K; ++k) bn[k] = A.Bc[(int64_t(mf) * K + k) * nc + c];
 #pragma unroll
-                for (int k = 0; k < K; ++k) b[d][k] = b[d + 1][k];
-            }
-            jnext = jf;
+            for (int k = 0; k < K; ++k) a[k] += b[k] * bv;
         }
     }
 
     // (iii) SI_1 = a^T O a, O as its upper triangle (sum of squares: a
     // rounded value below zero is clamped)
-    auto Oval = [&](int k, int l) { return bld<T>(row_rsrc(A.O, tri_index(K, k, l), nc), cT, 0u); };
     T SI1 = T(0);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        T t = Oval(k, k) * a[k];
+        T t = A.O[int64_t(tri_index(K, k, k)) * nc + c] * a[k];
 #pragma unroll
-        for (int l = k + 1; l < K; ++l) t += T(2) * Oval(k, l) * a[l];
+        for (int l = k + 1; l < K; ++l) t += T(2) * A.O[int64_t(tri_index(K, k, l)) * nc + c] * a[l];
         SI1 += a[k] * t;
     }
     SI1 = fmax(SI1, T(0));
 
     // (iv) directional stencils
-    const int nd = int(__builtin_amdgcn_raw_buffer_load_b8(rsrc(A.ndir, uint64_t(nc)), int(uint32_t(c)), 0, 0));
+    const int nd = int(A.ndir[c]);
     const T lam_s = T(1) / (A.lam_c + T(nd > 0 ? nd : 1)), lam_1 = A.lam_c * lam_s;
     const T r1 = T(1) / (A.eps + SI1);
     T G[KD], tsum = T(0), Lam = lam_1 * r1;
@@ -163,40 +139,25 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
 #pragma unroll
             for (int k = 0; k < KD; ++k) as[k] = T(0);
             const int64_t r0 = int64_t(s) * MD;
-            constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
             auto row = [&](int j) { return r0 + (j < MD ? j : MD - 1); };
-            auto id = [&](int j) { return bld<int32_t>(row_rsrc(A.sten_d, row(j), nc), c4, 0u); };
-            auto load_b = [&](int j, T* b) {
-                const auto rB = row_rsrc(A.Bd, row(j) * KD, nc, KD);
+            double un = Uv[A.sten_d[r0 * nc + c]];
+            int32_t j2 = A.sten_d[row(1) * nc + c];
+            T bn[KD];
 #pragma unroll
-                for (int k = 0; k < KD; ++k) b[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
-            };
-            double u[DEPTH + 1];
-            T b[DEPTH + 1][KD];
-            int32_t jn[DEPTH + 1];
-#pragma unroll
-            for (int d = 0; d <= DEPTH; ++d) jn[d] = id(d);
-#pragma unroll
-            for (int d = 0; d < DEPTH; ++d) {
-                u[d] = state(jn[d]);
-                load_b(d, b[d]);
-            }
-            int32_t jnext = jn[DEPTH];
+            for (int k = 0; k < KD; ++k) bn[k] = A.Bd[(r0 * KD + k) * nc + c];
 #pragma unroll 1
             for (int j = 0; j < MD; ++j) {
-                const int32_t jf = id(j + DEPTH + 1);
-                u[DEPTH] = state(jnext);
-                load_b(j + DEPTH, b[DEPTH]);
-                const T bv = T(u[0] - ui);
+                const T bv = T(un - ui);
+                T b[KD];
 #pragma unroll
-                for (int k = 0; k < KD; ++k) as[k] += b[0][k] * bv;
+                for (int k = 0; k < KD; ++k) b[k] = bn[k];
+                const int64_t rf = row(j + 1);
+                un = Uv[j2];
+                j2 = A.sten_d[row(j + 2) * nc + c];
 #pragma unroll
-                for (int d = 0; d < DEPTH; ++d) {
-                    u[d] = u[d + 1];
+                for (int k = 0; k < KD; ++k) bn[k] = A.Bd[(rf * KD + k) * nc + c];
 #pragma unroll
-                    for (int k = 0; k < KD; ++k) b[d][k] = b[d + 1][k];
-                }
-                jnext = jf;
+                for (int k = 0; k < KD; ++k) as[k] += b[k] * bv;
             }
             if (s < nd) {
                 // SI_s with the block of O on the first KD terms (its upper
@@ -204,9 +165,9 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
                 T SIs = T(0);
 #pragma unroll
                 for (int k = 0; k < KD; ++k) {
-                    T t = Oval(k, k) * as[k];
+                    T t = A.O[int64_t(tri_index(K, k, k)) * nc + c] * as[k];
 #pragma unroll
-                    for (int l = k + 1; l < KD; ++l) t += T(2) * Oval(k, l) * as[l];
+                    for (int l = k + 1; l < KD; ++l) t += T(2) * A.O[int64_t(tri_index(K, k, l)) * nc + c] * as[l];
                     SIs += as[k] * t;
                 }
                 SIs = fmax(SIs, T(0));
@@ -243,29 +204,26 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
 
     // (vi) point values at the cell's face points, slots [lf][q][v][cell]
     T pm[K];
-    {
-        const auto rM = row_rsrc(A.pmean, 0, nc, K);
 #pragma unroll
-        for (int k = 0; k < K; ++k) pm[k] = bld<T>(rM, cT, uint32_t(k) * rowT);
-    }
+    for (int k = 0; k < K; ++k) pm[k] = A.pmean[int64_t(k) * nc + c];
     const int base = slot < kP4Cells ? 5 * slot : 0;
     bool ok = true;
     const int NF = A.NF, Q = A.Q;
 #pragma unroll 1
     for (int lf = 0; lf < NF; ++lf) {
-        const int nq = int(__builtin_amdgcn_raw_buffer_load_b8(row_rsrc(A.cnq, lf, nc), int(uint32_t(c)), 0, 0));
+        const int nq = A.cnq[int64_t(lf) * nc + c];
 #pragma unroll 1
         for (int q = 0; q < Q; ++q) {
             if (q >= nq) break;  // uniform within a cell's five lanes
-            const auto rX = row_rsrc(A.xi, (int64_t(lf) * Q + q) * 3, nc, 3);
-            const T x = bld<T>(rX, cT, 0u), y = bld<T>(rX, cT, rowT), z = bld<T>(rX, cT, 2u * rowT);
+            const int64_t row = (int64_t(lf) * Q + q) * 3;
+            const T x = A.xi[row * nc + c], y = A.xi[(row + 1) * nc + c], z = A.xi[(row + 2) * nc + c];
             T ph[K];
             basis_p4<T>(x, y, z, pm, ph);
             T d = T(0);
 #pragma unroll
             for (int k = 0; k < K; ++k) d += ph[k] * a[k];
             const T val = T(ui + double(d));
-            if (valid) bst<T>(val, row_rsrc(A.fs, (int64_t(lf) * Q + q) * 5, nc, 5), cT + uint32_t(v) * rowT, 0u);
+            if (valid) A.fs[((int64_t(lf) * Q + q) * 5 + v) * nc + c] = val;
             // the point's five variables from the cell's lanes
             const T r = p4_from(val, base), mx = p4_from(val, base + 1), my = p4_from(val, base + 2),
                     mz = p4_from(val, base + 3), E = p4_from(val, base + 4);
