@@ -371,7 +371,11 @@ int ucns_gate_mask(const float* params, const float* features, int64_t n, uint8_
  * (beta 0.9/0.999, eps 1e-8, FP32 master weights in params, step t >= 1).
  * grads receives the batch gradient (parameter layout), adam_state holds m
  * then v (2 x UCNS_MLP_NPARAM floats), loss_dev the mean loss.  Only the
- * slots W1 .. b3 are trained; mu, isig and theta are the caller's. */
+ * slots W1 .. b3 are trained; mu, isig and theta are the caller's.  The
+ * batch is split over up to 64 one-wave blocks whose gradient partials are
+ * summed in block order, so the result depends on n and the data only.  The
+ * partials live in a fixed 1.3 MiB device array per GPU: steps on one GPU
+ * must be ordered (one stream); overlapping steps race. */
 int ucns_mlp_train_step(float* params, float* grads, float* adam_state, const float* features,
                         const float* labels, int64_t n, float pos_weight, float lr, int t, float* loss_dev,
                         ucns_stream stream);

@@ -315,12 +315,19 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restric
 
 // ----------------------------------------------------------------- training
 //
-// One wave trains on a batch in chunks of 64 samples (lane = sample):
+// The batch is cut into chunks of 64 samples (lane = sample); block b (one
+// wave) takes chunks b, b + nblk, ... and writes its gradient partial:
 //   x = bf16((f - mu) isig); H1 = relu(x W1 + b1); H2 = relu(bf16(H1) W2 + b2)
 //   z = H2 . w3 + b3; loss = mean_w BCE(z, y); dz = w (sigmoid(z) - y) / B
 //   dH2 = dz w3 [H2 > 0]; dW2 = bf16(H1)^T bf16(dH2); dw3 = H2^T dz
 //   dH1 = bf16(dH2) W2^T [H1 > 0]; dW1 = x^T bf16(dH1); db = column sums
-// then Adam (FP32 master weights) on the trainable slots.
+// mlp_adam_kernel then sums the partials in block order (the result depends
+// on n only, not on scheduling) and applies Adam (FP32 master weights) on the
+// trainable slots.
+namespace mlp {
+constexpr int kTrainMaxBlocks = 64;
+constexpr int kTrainStride = 5376;  // floats per partial row: kNParam slots, then the loss
+}  // namespace mlp
 struct TrainLds {
     MlpWeights S;
     uint16_t W2r[64 * mlp::kHS];   // [k_in][n_out] (row-major W2) for dH1
@@ -334,10 +341,9 @@ struct TrainLds {
     float red[64];
 };
 
-__global__ __launch_bounds__(64) void mlp_train_kernel(float* __restrict__ P, float* __restrict__ G,
-                                                       float* __restrict__ Am, float* __restrict__ Av,
+__global__ __launch_bounds__(64) void mlp_train_kernel(const float* __restrict__ P, float* __restrict__ part,
                                                        const float* __restrict__ feat, const float* __restrict__ lab,
-                                                       int64_t n, float pos_w, float lr, int t, float* loss_out) {
+                                                       int64_t n, float pos_w) {
     __shared__ TrainLds L;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
     mlp_stage(P, L.S, lane, 64);
@@ -358,7 +364,7 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(float* __restrict__ P, fl
     float gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f, lsum = 0.f;  // lane = column index
     const float inv_b = 1.f / float(n);
     const int64_t nch = (n + 63) / 64;
-    for (int64_t ch = 0; ch < nch; ++ch) {
+    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         const int64_t i = ch * 64 + lane;
         const bool valid = i < n;
         // ---- inputs
@@ -517,15 +523,14 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(float* __restrict__ P, fl
         }
         __builtin_amdgcn_wave_barrier();
     }
-    // ---- gradients to global (same layout as the parameters)
-    for (int i = lane; i < mlp::kNParam; i += 64) G[i] = 0.f;
-    __syncthreads();
+    // ---- this block's partial (parameter layout; every trainable slot written)
+    float* G = part + int64_t(blockIdx.x) * mlp::kTrainStride;
 #pragma unroll
     for (int it = 0; it < 4; ++it)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int k = 4 * g + j;  // input row of W1
-            if (k < 12) G[mlp::kOffW1 + k * 64 + 16 * it + r] = gW1[it][j];
+            const int k = 4 * g + j;  // input row of W1 (rows 12..15 are padding)
+            G[mlp::kOffW1 + k * 64 + 16 * it + r] = k < 12 ? gW1[it][j] : 0.f;
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) G[mlp::kOffW2 + (16 * it + 4 * g + j) * 64 + 16 * nt + r] = gW2[it][nt][j];
         }
@@ -541,17 +546,35 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(float* __restrict__ P, fl
     }
     if (lane == 0) {
         G[mlp::kOffB3] = s3;
+        G[mlp::kNParam] = sl;
+    }
+}
+
+// Sums the nblk partials of mlp_train_kernel in block order into G (zero on
+// the untrained slots) and the mean loss, then one Adam step on [W1 .. b3].
+__global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ P, float* __restrict__ G,
+                                                       float* __restrict__ Am, float* __restrict__ Av,
+                                                       const float* __restrict__ part, int nblk, float inv_b, float lr,
+                                                       int t, float* loss_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == mlp::kNParam) {
+        float sl = 0.f;
+        for (int b = 0; b < nblk; ++b) sl += part[int64_t(b) * mlp::kTrainStride + mlp::kNParam];
         if (loss_out) *loss_out = sl * inv_b;
+        return;
     }
-    __syncthreads();
-    // ---- Adam on the trainable slots [W1 .. b3]
+    if (i > mlp::kNParam) return;
+    if (i < mlp::kOffW1 || i >= mlp::kOffTheta) {
+        G[i] = 0.f;
+        return;
+    }
+    float gi = 0.f;
+    for (int b = 0; b < nblk; ++b) gi += part[int64_t(b) * mlp::kTrainStride + i];
+    G[i] = gi;
     const float b1c = 1.f - powf(0.9f, float(t)), b2c = 1.f - powf(0.999f, float(t));
-    for (int i = mlp::kOffW1 + lane; i < mlp::kOffTheta; i += 64) {
-        const float gi = G[i];
-        const float m = 0.9f * Am[i] + 0.1f * gi;
-        const float v = 0.999f * Av[i] + 0.001f * gi * gi;
-        Am[i] = m;
-        Av[i] = v;
-        P[i] -= lr * (m / b1c) / (sqrtf(v / b2c) + 1e-8f);
-    }
+    const float m = 0.9f * Am[i] + 0.1f * gi;
+    const float v = 0.999f * Av[i] + 0.001f * gi * gi;
+    Am[i] = m;
+    Av[i] = v;
+    P[i] -= lr * (m / b1c) / (sqrtf(v / b2c) + 1e-8f);
 }

@@ -916,14 +916,19 @@ int launch_features(const Mesh& m, const Arena& ar, const double* U, float* out,
 constexpr int64_t kStaticScratchBlocks = int64_t(1) << 18;
 static __device__ __align__(256) double scratch[2 * kStaticScratchBlocks];
 
+// Per-block gradient partials of ucns_mlp_train_step (1.3 MiB per GPU), in
+// the same kind of fixed array: training steps on one GPU run in stream order.
+static __device__ __align__(256) float train_part[mlp::kTrainMaxBlocks * mlp::kTrainStride];
+
 namespace {
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
-double* g_scratch_ptr[kMaxDevices] = {};
+void* g_scratch_ptr[kMaxDevices] = {};
+void* g_train_part_ptr[kMaxDevices] = {};
 
-// Device address of `scratch` on the current device (resolved on the first
-// call per device).
-int static_scratch(double** out) {
+// Device address of a file-scope device array on the current device, looked
+// up once per device and kept in table.
+int symbol_address(const void* symbol, void** table, const char* name, void** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) {
@@ -935,17 +940,24 @@ int static_scratch(double** out) {
         return UCNS_EINVAL;
     }
     std::lock_guard<std::mutex> lock(g_scratch_mutex);
-    if (!g_scratch_ptr[dev]) {
+    if (!table[dev]) {
         void* p = nullptr;
-        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        e = hipGetSymbolAddress(&p, symbol);
         if (e != hipSuccess || !p) {
-            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            set_error(std::string("hipGetSymbolAddress(") + name + "): " + hipGetErrorString(e));
             return UCNS_EHIP;
         }
-        g_scratch_ptr[dev] = static_cast<double*>(p);
+        table[dev] = p;
     }
-    *out = g_scratch_ptr[dev];
+    *out = table[dev];
     return UCNS_OK;
+}
+
+int static_scratch(double** out) {
+    void* p = nullptr;
+    const int rc = symbol_address(HIP_SYMBOL(scratch), g_scratch_ptr, "scratch", &p);
+    *out = static_cast<double*>(p);
+    return rc;
 }
 }  // namespace
 
@@ -1407,8 +1419,15 @@ int ucns_gate_mask(const float* params, const float* features, int64_t n, uint8_
 int ucns_mlp_train_step(float* params, float* grads, float* adam_state, const float* features, const float* labels,
                         int64_t n, float pos_weight, float lr, int t, float* loss_dev, ucns_stream stream) {
     UCNS_REQUIRE(params && grads && adam_state && features && labels && n > 0 && t >= 1, UCNS_EINVAL, "bad argument");
-    hipLaunchKernelGGL(mlp_train_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), params, grads,
-                       adam_state, adam_state + mlp::kNParam, features, labels, n, pos_weight, lr, t, loss_dev);
+    void* p = nullptr;
+    const int rc = symbol_address(HIP_SYMBOL(train_part), g_train_part_ptr, "train_part", &p);
+    if (rc != UCNS_OK) return rc;
+    float* part = static_cast<float*>(p);
+    const int nblk = int(std::min<int64_t>((n + 63) / 64, mlp::kTrainMaxBlocks));
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(mlp_train_kernel, dim3(nblk), dim3(64), 0, s, params, part, features, labels, n, pos_weight);
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((mlp::kNParam + 256) / 256), dim3(256), 0, s, params, grads, adam_state,
+                       adam_state + mlp::kNParam, part, nblk, 1.f / float(n), lr, t, loss_dev);
     return hip_check("ucns_mlp_train_step");
 }
 

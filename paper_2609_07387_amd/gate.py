@@ -154,16 +154,16 @@ def train(F, Y, epochs=30, batch=1024, lr=1e-3, seed=0, log=print, balance="full
     hist = []
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(len(Y))).cuda()
-        tot = 0.0
+        tot = torch.zeros(1, dtype=torch.float64, device="cuda")  # read once per epoch
         nb = 0
         for s in range(0, len(Y) - batch + 1, batch):
             idx = perm[s:s + batch]
             fb, yb = Fd[idx].contiguous(), Yd[idx].contiguous()
             t += 1
             ucns.mlp_train_step(params, grads, adam, fb, yb, pos_weight, lr, t, loss)
-            tot += float(loss.item())
+            tot += loss
             nb += 1
-        hist.append(tot / max(nb, 1))
+        hist.append(float(tot.item()) / max(nb, 1))
         if ep % 5 == 0 or ep == epochs - 1:
             log(f"[gate] epoch {ep}: mean loss {hist[-1]:.4f}")
     return params.cpu().numpy(), hist, pos_weight

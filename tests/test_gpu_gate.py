@@ -80,14 +80,16 @@ def test_mlp_forward_parity(torch_cuda):
     assert np.abs(got - omlp.sigmoid(z64)).max() < 0.05
 
 
-def test_mlp_train_step_parity(torch_cuda):
+@pytest.mark.parametrize("n", [200, 5000])
+def test_mlp_train_step_parity(torch_cuda, n):
     """One training step: loss and gradient against the oracle's backward with
     the same bf16 rounding points; the Adam update against the oracle's Adam
-    applied to the device gradient."""
+    applied to the device gradient.  n = 200 is 4 blocks of one chunk (the
+    last ragged); n = 5000 is 79 chunks over the 64 blocks, 15 of them taking
+    two."""
     torch = torch_cuda
     p = _random_params(3)
     rng = np.random.default_rng(4)
-    n = 200  # ragged: 3 full chunks of 64 and a partial one
     F = (rng.normal(size=(n, 12)) - 3.0).astype(np.float32)
     Y = (rng.random(n) < 0.3).astype(np.float32)
     P = torch.tensor(p, device="cuda")
@@ -106,6 +108,15 @@ def test_mlp_train_step_parity(torch_cuda):
     m, v = np.zeros(omlp.N_PARAM), np.zeros(omlp.N_PARAM)
     p_ref = omlp.adam_step(p.astype(np.float64).copy(), g, m, v, 1, 1e-3)
     assert np.abs(P.cpu().numpy() - p_ref).max() < 1e-6
+    # the partials are summed in block order: a second step from the same
+    # state gives the same bits
+    P2 = torch.tensor(p, device="cuda")
+    G2 = torch.zeros_like(P2)
+    A2 = torch.zeros_like(A)
+    L2 = torch.zeros_like(L)
+    ucns.mlp_train_step(P2, G2, A2, torch.tensor(F, device="cuda"), torch.tensor(Y, device="cuda"), 2.5, 1e-3, 1, L2)
+    torch.cuda.synchronize()
+    assert torch.equal(G, G2) and torch.equal(P, P2) and torch.equal(L, L2)
 
 
 def test_training_learns_separable_labels(torch_cuda):

@@ -19,10 +19,11 @@ pytestmark = pytest.mark.gpu
 TOL_STAGE = 1e-12
 TOL_STEPS = 1e-12   # relative L-inf after the stated steps
 # The mixed boundary-layer mesh has least-squares stencils with condition
-# numbers near 1e9 (thin prism layers under tetrahedra): the library's and the
-# oracle's operators, both correct, agree to about 1e-7 there (host-build
-# test), and so do the states built from them.
-TOL_CASE = {"mixed_bl_ns": 1e-6, "mixed_bl_ns_lsq": 1e-6}
+# numbers up to about 2e4 (thin prism layers under tetrahedra, after the
+# central stencils are extended until well conditioned): the library's and
+# the oracle's operators, built independently, agree to about 1e-11 there
+# (host-build test), and the face states built from them to 1.1e-12.
+TOL_CASE = {"mixed_bl_ns": 3e-12, "mixed_bl_ns_lsq": 3e-12}
 
 
 @pytest.fixture(scope="module")
