@@ -11,6 +11,7 @@ the record no longer applies and the benchmark reports no traffic.
 
   python -m paper_2609_07387_amd.prof stats KERNEL_STATS_CSV TITLE COMMAND [TRACE_CSV LABEL=K1|K2=N ...] > profiles/NAME.md
   python -m paper_2609_07387_amd.prof traffic FETCH_CSV WRITE_CSV K1[|K2...] COPY_BYTES COMMAND OUT_MD [N_LAST]
+      [--sizes READREQ_CSV,WRITEREQ_CSV] [--exclude FILE[,FILE...]]
 """
 from __future__ import annotations
 
@@ -50,11 +51,15 @@ def _code_only(text: str) -> str:
     return " ".join("".join(out).split())
 
 
-def source_digest() -> str:
+def source_digest(exclude=()) -> str:
     """sha256 over the code (comments and spacing removed) of the device and
-    host sources of libucns."""
+    host sources of libucns.  exclude: file names left out, for a record whose
+    kernels take no code from them (a header that only defines other
+    kernels)."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if os.path.basename(p) in exclude:
+            continue
         if p.endswith((".hip", ".hpp", ".cpp", ".h")):
             with open(p, encoding="utf-8") as f:
                 h.update(os.path.basename(p).encode())
@@ -98,10 +103,47 @@ def _pick(d, sub):
     return hits[0], d[hits[0]]
 
 
-def traffic(fetch_csv, write_csv, kernel, copy_bytes, command, n_last=0):
+# Request counters of the memory side of L2 (one run for reads, one for
+# writes; each within the four-counter limit of that block).
+READ_REQ = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum", "TCC_EA0_RDREQ_DRAM_sum")
+WRITE_REQ = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_WRREQ_DRAM_sum")
+
+
+def _sum_means(path, counter, kernel, n_last):
+    d = _mean_by_kernel(path, counter, n_last)
+    return sum(_pick(d, sub)[1][0] for sub in kernel.split("|"))
+
+
+def request_sizes(read_csv, write_csv, kernel, copy_bytes, n_last=0):
+    """Read and write bytes from request counts by size: 32-byte reads
+    (RDREQ_32B) count 32 B; every other read request counts the bytes one
+    request moved in the calibration copy (copy bytes / its read requests);
+    64-byte writes (WRREQ_64B) count 64 B and the other writes 32 B, checked
+    against the copy's known write size.  Also the share of read requests that
+    went to DRAM."""
+    r = {c: _sum_means(read_csv, c, kernel, n_last) for c in READ_REQ}
+    w = {c: _sum_means(write_csv, c, kernel, n_last) for c in WRITE_REQ}
+    cr = {c: _copy_reading(read_csv, c) for c in READ_REQ}
+    cw = {c: _copy_reading(write_csv, c) for c in WRITE_REQ}
+    big = cr["TCC_EA0_RDREQ_sum"] - cr["TCC_EA0_RDREQ_32B_sum"]
+    per_req = (copy_bytes - 32.0 * cr["TCC_EA0_RDREQ_32B_sum"]) / big
+    read_b = 32.0 * r["TCC_EA0_RDREQ_32B_sum"] + per_req * (r["TCC_EA0_RDREQ_sum"] - r["TCC_EA0_RDREQ_32B_sum"])
+
+    def wbytes(d):
+        return 64.0 * d["TCC_EA0_WRREQ_64B_sum"] + 32.0 * (d["TCC_EA0_WRREQ_sum"] - d["TCC_EA0_WRREQ_64B_sum"])
+
+    return {"read_requests": r, "write_requests": w, "copy_read_requests": cr, "copy_write_requests": cw,
+            "copy_bytes_per_read_request": per_req, "copy_write_bytes_from_sizes": wbytes(cw),
+            "read_bytes": read_b, "write_bytes": wbytes(w), "bytes_per_launch": read_b + wbytes(w),
+            "dram_read_share": r["TCC_EA0_RDREQ_DRAM_sum"] / max(r["TCC_EA0_RDREQ_sum"], 1.0)}
+
+
+def traffic(fetch_csv, write_csv, kernel, copy_bytes, command, n_last=0, exclude=(), sizes=None):
     """kernel: one name substring, or several joined by '|' (the kernels of
     one library call; their per-dispatch means are summed).  n_last: average
-    the last n dispatches only (the window a benchmark times)."""
+    the last n dispatches only (the window a benchmark times).  sizes: the
+    (read, write) request-counter CSVs of the same command, for a second
+    estimate from request sizes."""
     fe = _mean_by_kernel(fetch_csv, "FETCH_SIZE", n_last)
     wr = _mean_by_kernel(write_csv, "WRITE_SIZE", n_last)
     names, f_kib, w_kib, nf, nw = [], 0.0, 0.0, [], []
@@ -124,7 +166,8 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes, command, n_last=0):
             "copy_bytes": copy_bytes, "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib,
             "fetch_scale": f_scale, "write_scale": w_scale, "fetch_bytes": fetch_b, "write_bytes": write_b,
             "bytes_per_launch": fetch_b + write_b, "window_last_dispatches": n_last,
-            "source_digest": source_digest(), "command": command}
+            "by_request_size": request_sizes(sizes[0], sizes[1], kernel, copy_bytes, n_last) if sizes else None,
+            "digest_exclude": list(exclude), "source_digest": source_digest(exclude), "command": command}
 
 
 def traffic_md(rec):
@@ -140,8 +183,25 @@ def traffic_md(rec):
         f"{rec['write_bytes']:.4g} |", "",
         f"Total per launch: {rec['bytes_per_launch']:.4g} bytes"
         + (f" (mean of the last {rec['window_last_dispatches']} dispatches of each kernel)."
-           if rec.get("window_last_dispatches") else " (mean over all dispatches)."), "",
-        "```json", json.dumps(rec, indent=1), "```", ""])
+           if rec.get("window_last_dispatches") else " (mean over all dispatches)."), ""]
+        + (_sizes_md(rec["by_request_size"]) if rec.get("by_request_size") else [])
+        + ["```json", json.dumps(rec, indent=1), "```", ""])
+
+
+def _sizes_md(z):
+    r, w = z["read_requests"], z["write_requests"]
+    return [
+        "By request size (separate runs: " + ", ".join(READ_REQ) + "; then " + ", ".join(WRITE_REQ) + "):", "",
+        "| | requests / launch | of which 32 B (reads) or 64 B (writes) | to DRAM | bytes / launch |",
+        "|---|---|---|---|---|",
+        f"| reads | {r['TCC_EA0_RDREQ_sum']:.4g} | {r['TCC_EA0_RDREQ_32B_sum']:.4g} | "
+        f"{r['TCC_EA0_RDREQ_DRAM_sum']:.4g} | {z['read_bytes']:.4g} |",
+        f"| writes | {w['TCC_EA0_WRREQ_sum']:.4g} | {w['TCC_EA0_WRREQ_64B_sum']:.4g} | "
+        f"{w['TCC_EA0_WRREQ_DRAM_sum']:.4g} | {z['write_bytes']:.4g} |", "",
+        f"Other read requests are counted at the calibration copy's {z['copy_bytes_per_read_request']:.1f} B per "
+        f"request; the copy's writes by size come to {z['copy_write_bytes_from_sizes']:.4g} B. "
+        f"Total by request size: {z['bytes_per_launch']:.4g} bytes per launch "
+        f"(TCC_BUBBLE {r['TCC_BUBBLE_sum']:.4g} per launch).", ""]
 
 
 def load_traffic(path):
@@ -154,7 +214,7 @@ def load_traffic(path):
     if i < 0:
         return None
     rec = json.loads(text[i + 7:text.index("```", i + 7)])
-    return rec if rec.get("source_digest") == source_digest() else None
+    return rec if rec.get("source_digest") == source_digest(tuple(rec.get("digest_exclude", ()))) else None
 
 
 def last_calls_us(trace_csv, kernel, n):
@@ -194,8 +254,18 @@ def main(argv):
         wins = [(lab, ker, int(n)) for lab, ker, n in wins]
         sys.stdout.write(stats_md(argv[1], argv[2], argv[3], trace_csv=trace, windows=wins))
     elif len(argv) >= 7 and argv[0] == "traffic":
-        rec = traffic(argv[1], argv[2], argv[3], float(argv[4]), argv[5], int(argv[7]) if len(argv) > 7 else 0)
-        with open(argv[6], "w") as f:
+        opts, pos = {}, []
+        it = iter(argv[1:])
+        for a in it:
+            if a in ("--exclude", "--sizes"):
+                opts[a] = next(it)
+            else:
+                pos.append(a)
+        excl = tuple(x for x in opts.get("--exclude", "").split(",") if x)
+        sizes = tuple(opts["--sizes"].split(",")) if "--sizes" in opts else None
+        rec = traffic(pos[0], pos[1], pos[2], float(pos[3]), pos[4], int(pos[6]) if len(pos) > 6 else 0,
+                      exclude=excl, sizes=sizes)
+        with open(pos[5], "w") as f:
             f.write(traffic_md(rec))
         print(json.dumps(rec))
     else:
