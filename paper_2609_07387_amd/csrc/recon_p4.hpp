@@ -7,53 +7,174 @@
 // blend (eq. cwenoz_poly, Levy-Puppo-Russo form) and the point values at the
 // cell's 6 x 16 face Gauss points.
 //
-// One lane per (cell, conserved variable): 12 cells per wave, five lanes
-// each (lanes 60-63 idle).  A cell's 34 x 5 coefficients do not fit one lane
-// in FP64, and the weights are per variable (component-wise CWENOZ), so each
-// lane runs the whole scheme for one variable; the five lanes of a cell load
-// the same operator values (one request per cell, served by the same cache
-// lines), and each gathers its own variable's row of the stencil states.
-// Positivity needs all five variables of a point: the cell's lanes exchange
-// them with ds_bpermute.
+// A quad of lanes per cell, 16 cells per wave.  Lane h of the quad owns the
+// basis terms g = 4 i + h (i = 0..8; terms 34 and 35 of lanes 2 and 3 are
+// padding held at zero) for all five variables: 45 coefficients per lane,
+// and every operator row a lane loads is its own (the four lanes of a quad
+// read four different rows of the cell's operator, so no value is fetched
+// twice).  The lanes' shares of a quadratic form or of a point value meet
+// through quad DPP moves; each lane loads two of the five variables of a
+// stencil member's state and the quad broadcasts the other three.  Sums over
+// the quad are formed as (l0 + l1) + (l2 + l3) in every lane, so all four
+// lanes hold the same bits and take the same decisions.
 
 constexpr int kP4K = 34;        // basis terms of the degree-4 polynomial
 constexpr int kP4KD = 9;        // basis terms of a quadratic directional polynomial
-constexpr int kP4Cells = 12;    // cells per wave
+constexpr int kP4Cells = 16;    // cells per wave
 constexpr int kP4Q = 16;        // Gauss points per quadrilateral face (4 x 4)
+constexpr int kP4T = 9;         // central terms per lane
+constexpr int kP4TD = 3;        // directional terms per lane (g = 4 i + h < 9)
+constexpr int kP4NO = kP4K * (kP4K + 1) / 2;  // rows of the upper triangle of O
 #ifndef P4_WAVES
 #define P4_WAVES 2
 #endif
 
 // The 34 monomials of degree 1..4 in graded-lex order (x exponent
-// descending, then y) at a face point's scaled offset, minus their cell
-// means.
+// descending, then y) at a face point's scaled offset.
 template <class T>
-__device__ __forceinline__ void basis_p4(T x, T y, T z, const T* pm, T* ph) {
+__device__ __forceinline__ void monomials_p4(T x, T y, T z, T* t) {
     const T xx = x * x, yy = y * y, zz = z * z;
-    const T t[kP4K] = {x, y, z,
+    const T m[kP4K] = {x, y, z,
                        xx, x * y, x * z, yy, y * z, zz,
                        xx * x, xx * y, xx * z, x * yy, x * y * z, x * zz, yy * y, yy * z, y * zz, zz * z,
                        xx * xx, xx * x * y, xx * x * z, xx * yy, xx * y * z, xx * zz, x * yy * y, x * yy * z,
                        x * y * zz, x * zz * z, yy * yy, yy * y * z, yy * zz, y * zz * z, zz * zz};
 #pragma unroll
-    for (int k = 0; k < kP4K; ++k) ph[k] = t[k] - pm[k];
+    for (int k = 0; k < kP4K; ++k) t[k] = m[k];
 }
 
-// value of x in lane src of the wave (per-lane source)
-template <class T>
-__device__ __forceinline__ T p4_from(T x, int src) {
+// Quad DPP move: lane l of each group of four reads lane sel_l of the same
+// group; CTRL is the quad_perm control (two bits per destination lane).
+template <int CTRL>
+__device__ __forceinline__ int quad_mov(int x) {
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL, class T>
+__device__ __forceinline__ T quad_mov(T x) {
     if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, x)));
+        return __builtin_bit_cast(T, quad_mov<CTRL>(__builtin_bit_cast(int, x)));
     } else {
         const uint64_t u = __builtin_bit_cast(uint64_t, x);
-        const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(src << 2, int(uint32_t(u))));
-        const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(src << 2, int(uint32_t(u >> 32))));
+        const uint32_t lo = uint32_t(quad_mov<CTRL>(int(uint32_t(u))));
+        const uint32_t hi = uint32_t(quad_mov<CTRL>(int(uint32_t(u >> 32))));
         return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
     }
 }
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadXor3 = 0x1B;  // [1,0,3,2] [2,3,0,1] [3,2,1,0]
+constexpr int kQuadLane0 = 0x00, kQuadLane1 = 0x55, kQuadLane2 = 0xAA, kQuadLane3 = 0xFF;
 
-// Steps per lane (cell c, variable v):
-//  (i)   jumps b_m = U_m,v - U_c,v in FP64, rounded to T
+template <int X, class T>
+__device__ __forceinline__ T quad_xor(T x) {
+    if constexpr (X == 1)
+        return quad_mov<kQuadXor1>(x);
+    else if constexpr (X == 2)
+        return quad_mov<kQuadXor2>(x);
+    else
+        return quad_mov<kQuadXor3>(x);
+}
+
+// (l0 + l1) + (l2 + l3) in every lane of the quad (the same bits everywhere:
+// each addition is commutative)
+template <class T>
+__device__ __forceinline__ T quad_sum(T x) {
+    const T p = x + quad_xor<1>(x);
+    return p + quad_xor<2>(p);
+}
+
+// Row of O (upper triangle, row-major) of the term pair (p, q), p <= q;
+// rows past the last (padding terms) are clamped into the array.
+__device__ __forceinline__ int p4_tri(int p, int q) {
+    const int r = p * kP4K - (p * (p - 1)) / 2 + (q - p);
+    return r < kP4NO ? r : kP4NO - 1;
+}
+
+// Jumps of a stencil member's five variables, U_m - U_c in FP64 rounded to
+// T: lane k of the quad loaded variable k (broadcast to the quad), every
+// lane loaded variable 4.
+template <class T>
+__device__ __forceinline__ void p4_jumps(double uh, double u4, const double* ui, T* bv) {
+    bv[0] = T(quad_mov<kQuadLane0>(uh) - ui[0]);
+    bv[1] = T(quad_mov<kQuadLane1>(uh) - ui[1]);
+    bv[2] = T(quad_mov<kQuadLane2>(uh) - ui[2]);
+    bv[3] = T(quad_mov<kQuadLane3>(uh) - ui[3]);
+    bv[4] = T(u4 - ui[4]);
+}
+
+// One lane's share of the quadratic forms a_v^T O a_v (v = 0..4) over the
+// lane's NT terms g_i = 4 i + h, with tbase[i] the row of the pair (g_i, g_i):
+//  own pairs (i <= j): weight 1 on the diagonal, 2 off it, row
+//  tbase[i] + 4 (j - i);
+//  with lane h ^ X (partner term g'_j = 4 j + (h ^ X)): pairs i < j with
+//  weight 2 (g_i < g'_j, row tbase[i] + 4 (j - i) + (h ^ X) - h) and the
+//  diagonal pairs i = j with weight 2 in the lower lane of the two only.
+//  Summed over the quad every ordered pair of distinct terms counts once and
+//  each term's square once.
+template <class T, int NT>
+__device__ __forceinline__ void p4_form_own(const T* __restrict__ O, int64_t nc, int64_t c, const int* tbase,
+                                            const T (*a)[NT], T* s) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        T t[5];
+        const T od = O[int64_t(tbase[i]) * nc + c];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) t[v] = od * a[v][i];
+#pragma unroll
+        for (int j = i + 1; j < NT; ++j) {
+            const T o = T(2) * O[int64_t(min(tbase[i] + 4 * (j - i), kP4NO - 1)) * nc + c];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) t[v] += o * a[v][j];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) s[v] += a[v][i] * t[v];
+    }
+}
+
+template <int X, class T, int NT>
+__device__ __forceinline__ void p4_form_cross(const T* __restrict__ O, int64_t nc, int64_t c, int h, const int* tbase,
+                                              const T (*a)[NT], T* s) {
+    const int dh = (h ^ X) - h;
+    const T wdiag = dh > 0 ? T(2) : T(0);
+    const int ddiag = dh > 0 ? dh : 0;  // the upper lane reads a valid row it weights by zero
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        T ap[5];  // the partner's coefficients of its term j
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ap[v] = quad_xor<X>(a[v][j]);
+        T t[5];
+        {
+            const T o = wdiag * O[int64_t(min(tbase[j] + ddiag, kP4NO - 1)) * nc + c];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) t[v] = o * a[v][j];
+        }
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            const T o = T(2) * O[int64_t(min(tbase[i] + 4 * (j - i) + dh, kP4NO - 1)) * nc + c];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) t[v] += o * a[v][i];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) s[v] += ap[v] * t[v];
+    }
+}
+
+// a_v^T O a_v for the five variables, complete in every lane of the quad
+// (a sum of squares: a rounded value below zero is clamped).
+template <class T, int NT>
+__device__ __forceinline__ void p4_forms(const T* __restrict__ O, int64_t nc, int64_t c, int h, const int* tbase,
+                                         const T (*a)[NT], T* out) {
+    T s[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) s[v] = T(0);
+    p4_form_own<T, NT>(O, nc, c, tbase, a, s);
+    p4_form_cross<1, T, NT>(O, nc, c, h, tbase, a, s);
+    p4_form_cross<2, T, NT>(O, nc, c, h, tbase, a, s);
+    p4_form_cross<3, T, NT>(O, nc, c, h, tbase, a, s);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v] = fmax(quad_sum(s[v]), T(0));
+}
+
+// Steps per quad (cell c; lane h owns the terms g = 4 i + h of all variables):
+//  (i)   jumps b_m = U_m - U_c in FP64, rounded to T
 //  (ii)  a = B_c b (34 terms)
 //  (iii) SI_1 = a^T O a
 //  (iv)  per directional stencil s: a_s = B_s b_s (9 terms), SI_s = a_s^T O_9 a_s
@@ -61,152 +182,232 @@ __device__ __forceinline__ T p4_from(T x, int src) {
 //  (v)   tau = mean_s |SI_1 - SI_s|; LPR blend
 //        abar = s1 a + (tau/W) G on the first 9 terms, s1 = (1 + tau/(eps+SI_1))/W,
 //        W = 1 + tau sum_s lambda_s/(eps+SI_s), G = sum_s lambda_s (r_s - r_1) a_s
-//  (vi)  point values U_c,v + Phi_q . abar; positivity of rho and p at each point.
-// LABEL: also max over stencils and variables of |omega - lambda| per cell.
+//  (vi)  point values U_c + Phi_q . abar; positivity of rho and p at each point.
+// Every step per variable (component-wise).  LABEL: also the max over
+// stencils and variables of |omega - lambda| per cell.
 template <class T, bool LABEL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P4_WAVES)))
 void reconstruct_p4_kernel(ReconArgs<T> A) {
-    constexpr int K = kP4K, KD = kP4KD;
+    constexpr int K = kP4K, KD = kP4KD, NT = kP4T, NTD = kP4TD;
     const int64_t nc = A.nc;
     const int lane = int(threadIdx.x & 63u);
-    const int slot = lane / 5, v = lane - 5 * slot;
+    const int slot = lane >> 2, h = lane & 3;
     const int64_t c0 = (xcd_block() * (kBlock / 64) + int64_t(threadIdx.x >> 6)) * kP4Cells;
-    const bool valid = slot < kP4Cells && c0 + slot < nc;
-    // idle lanes shadow the wave's first cell (every load stays in range)
+    const bool valid = c0 + slot < nc;
+    // quads past the last cell shadow the wave's first cell (every load stays in range)
     const int64_t c = valid ? c0 + slot : (c0 < nc ? c0 : nc - 1);
-    const int vv = valid ? v : 0;
-    const double ui = A.U[vv * nc + c];
-    const double* Uv = A.U + int64_t(vv) * nc;
+    double ui[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ui[v] = A.U[v * nc + c];
+    const double* Uh = A.U + int64_t(h) * nc;
+    const double* U4 = A.U + 4 * nc;
+    // operator rows of the lane's terms (padding terms read the last row)
+    // and their diagonal rows of O
+    int trow[NT], tbase[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int g = 4 * i + h < K ? 4 * i + h : K;
+        trow[i] = g < K ? g : K - 1;
+        tbase[i] = p4_tri(g, g);
+    }
 
     // (ii) central coefficients; member m's id at sten_c[m][c], its K
-    // operator rows at Bc[m][k][c].  Operators and states load one member
-    // ahead of the arithmetic, ids two ahead (a state load waits only for an
-    // id loaded an iteration earlier).
-    T a[K];
+    // operator rows at Bc[m][k][c].  Operators and states load DEPTH members
+    // ahead of the arithmetic, ids one further.
+    T a[5][NT];
 #pragma unroll
-    for (int k = 0; k < K; ++k) a[k] = T(0);
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int i = 0; i < NT; ++i) a[v][i] = T(0);
     const int MC = A.MC;
     {
+        constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
         auto last = [&](int m) { return m < MC ? m : MC - 1; };
-        double un = Uv[A.sten_c[c]];
-        int32_t j2 = A.sten_c[int64_t(last(1)) * nc + c];
-        T bn[K];
+        auto id = [&](int m) { return A.sten_c[int64_t(last(m)) * nc + c]; };
+        auto load_b = [&](int m, T* b) {
+            const T* Bm = A.Bc + int64_t(last(m)) * K * nc + c;
 #pragma unroll
-        for (int k = 0; k < K; ++k) bn[k] = A.Bc[int64_t(k) * nc + c];
+            for (int i = 0; i < NT; ++i) b[i] = Bm[int64_t(trow[i]) * nc];
+        };
+        double uh[DEPTH + 1], u4[DEPTH + 1];
+        T b[DEPTH + 1][NT];
+        int32_t jn[DEPTH + 1];
+#pragma unroll
+        for (int d = 0; d <= DEPTH; ++d) jn[d] = id(d);
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            uh[d] = Uh[jn[d]];
+            u4[d] = U4[jn[d]];
+            load_b(d, b[d]);
+        }
+        int32_t jnext = jn[DEPTH];
 #pragma unroll 1
         for (int m = 0; m < MC; ++m) {
-            const T bv = T(un - ui);
-            T b[K];
+            const int32_t jf = id(m + DEPTH + 1);
+            uh[DEPTH] = Uh[jnext];
+            u4[DEPTH] = U4[jnext];
+            load_b(m + DEPTH, b[DEPTH]);
+            T bv[5];
+            p4_jumps<T>(uh[0], u4[0], ui, bv);
 #pragma unroll
-            for (int k = 0; k < K; ++k) b[k] = bn[k];
-            const int mf = last(m + 1);
-            un = Uv[j2];
-            j2 = A.sten_c[int64_t(last(m + 2)) * nc + c];
+            for (int v = 0; v < 5; ++v)
 #pragma unroll
-            for (int k = 0; k < K; ++k) bn[k] = A.Bc[(int64_t(mf) * K + k) * nc + c];
+                for (int i = 0; i < NT; ++i) a[v][i] += b[0][i] * bv[v];
 #pragma unroll
-            for (int k = 0; k < K; ++k) a[k] += b[k] * bv;
+            for (int d = 0; d < DEPTH; ++d) {
+                uh[d] = uh[d + 1];
+                u4[d] = u4[d + 1];
+#pragma unroll
+                for (int i = 0; i < NT; ++i) b[d][i] = b[d + 1][i];
+            }
+            jnext = jf;
         }
     }
-
-    // (iii) SI_1 = a^T O a, O as its upper triangle (sum of squares: a
-    // rounded value below zero is clamped)
-    T SI1 = T(0);
+    if (4 * (NT - 1) + h >= K) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        T t = A.O[int64_t(tri_index(K, k, k)) * nc + c] * a[k];
-#pragma unroll
-        for (int l = k + 1; l < K; ++l) t += T(2) * A.O[int64_t(tri_index(K, k, l)) * nc + c] * a[l];
-        SI1 += a[k] * t;
+        for (int v = 0; v < 5; ++v) a[v][NT - 1] = T(0);
     }
-    SI1 = fmax(SI1, T(0));
 
-    // (iv) directional stencils
+    // (iii) SI_1 = a^T O a
+    T SI1[5];
+    p4_forms<T, NT>(A.O, nc, c, h, tbase, a, SI1);
+    // the terms of degree 3 and 4 (i >= 3) take no part in the directional
+    // step: parked in LDS (each lane its own slots) until the blend
+    __shared__ T park[kBlock / 64][5 * (NT - NTD)][64];
+    const int wv = int(threadIdx.x >> 6);
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int i = NTD; i < NT; ++i) park[wv][v * (NT - NTD) + i - NTD][lane] = a[v][i];
+
+    // (iv) directional stencils: the lane's terms g = 4 i + h < 9 (i < 3)
     const int nd = int(A.ndir[c]);
     const T lam_s = T(1) / (A.lam_c + T(nd > 0 ? nd : 1)), lam_1 = A.lam_c * lam_s;
-    const T r1 = T(1) / (A.eps + SI1);
-    T G[KD], tsum = T(0), Lam = lam_1 * r1;
-    T rs[kMaxFaces];
+    T r1[5], G[5][NTD], tsum[5], Lam[5];
+    T rs[LABEL ? kMaxFaces : 1][5];
 #pragma unroll
-    for (int k = 0; k < KD; ++k) G[k] = T(0);
+    for (int v = 0; v < 5; ++v) {
+        r1[v] = T(1) / (A.eps + SI1[v]);
+        tsum[v] = T(0);
+        Lam[v] = lam_1 * r1[v];
 #pragma unroll
-    for (int s = 0; s < kMaxFaces; ++s) rs[s] = r1;
-    if (nd > 0) {
+        for (int i = 0; i < NTD; ++i) G[v][i] = T(0);
+        if constexpr (LABEL) {
+#pragma unroll
+            for (int s = 0; s < kMaxFaces; ++s) rs[s][v] = r1[v];
+        }
+    }
+    if (nd > 0) {  // uniform within a quad
+        int drow[NTD];
+#pragma unroll
+        for (int i = 0; i < NTD; ++i) drow[i] = 4 * i + h < KD ? 4 * i + h : KD - 1;
         const int MD = A.MD;
 #pragma unroll 1
         for (int s = 0; s < A.ND; ++s) {
-            T as[KD];
+            T as[5][NTD];
 #pragma unroll
-            for (int k = 0; k < KD; ++k) as[k] = T(0);
+            for (int v = 0; v < 5; ++v)
+#pragma unroll
+                for (int i = 0; i < NTD; ++i) as[v][i] = T(0);
             const int64_t r0 = int64_t(s) * MD;
+            constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
             auto row = [&](int j) { return r0 + (j < MD ? j : MD - 1); };
-            double un = Uv[A.sten_d[r0 * nc + c]];
-            int32_t j2 = A.sten_d[row(1) * nc + c];
-            T bn[KD];
+            auto id = [&](int j) { return A.sten_d[row(j) * nc + c]; };
+            auto load_b = [&](int j, T* b) {
+                const T* Bj = A.Bd + row(j) * KD * nc + c;
 #pragma unroll
-            for (int k = 0; k < KD; ++k) bn[k] = A.Bd[(r0 * KD + k) * nc + c];
+                for (int i = 0; i < NTD; ++i) b[i] = Bj[int64_t(drow[i]) * nc];
+            };
+            double uh[DEPTH + 1], u4[DEPTH + 1];
+            T b[DEPTH + 1][NTD];
+            int32_t jn[DEPTH + 1];
+#pragma unroll
+            for (int d = 0; d <= DEPTH; ++d) jn[d] = id(d);
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+                uh[d] = Uh[jn[d]];
+                u4[d] = U4[jn[d]];
+                load_b(d, b[d]);
+            }
+            int32_t jnext = jn[DEPTH];
 #pragma unroll 1
             for (int j = 0; j < MD; ++j) {
-                const T bv = T(un - ui);
-                T b[KD];
+                const int32_t jf = id(j + DEPTH + 1);
+                uh[DEPTH] = Uh[jnext];
+                u4[DEPTH] = U4[jnext];
+                load_b(j + DEPTH, b[DEPTH]);
+                T bv[5];
+                p4_jumps<T>(uh[0], u4[0], ui, bv);
 #pragma unroll
-                for (int k = 0; k < KD; ++k) b[k] = bn[k];
-                const int64_t rf = row(j + 1);
-                un = Uv[j2];
-                j2 = A.sten_d[row(j + 2) * nc + c];
+                for (int v = 0; v < 5; ++v)
 #pragma unroll
-                for (int k = 0; k < KD; ++k) bn[k] = A.Bd[(rf * KD + k) * nc + c];
+                    for (int i = 0; i < NTD; ++i) as[v][i] += b[0][i] * bv[v];
 #pragma unroll
-                for (int k = 0; k < KD; ++k) as[k] += b[k] * bv;
+                for (int d = 0; d < DEPTH; ++d) {
+                    uh[d] = uh[d + 1];
+                    u4[d] = u4[d + 1];
+#pragma unroll
+                    for (int i = 0; i < NTD; ++i) b[d][i] = b[d + 1][i];
+                }
+                jnext = jf;
+            }
+            if (4 * (NTD - 1) + h >= KD) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) as[v][NTD - 1] = T(0);
             }
             if (s < nd) {
-                // SI_s with the block of O on the first KD terms (its upper
-                // triangle read per stencil: cache hits after the first)
-                T SIs = T(0);
+                // SI_s with the block of O on the first KD terms
+                T SIs[5];
+                p4_forms<T, NTD>(A.O, nc, c, h, tbase, as, SIs);
 #pragma unroll
-                for (int k = 0; k < KD; ++k) {
-                    T t = A.O[int64_t(tri_index(K, k, k)) * nc + c] * as[k];
+                for (int v = 0; v < 5; ++v) {
+                    tsum[v] += fabs(SI1[v] - SIs[v]);
+                    const T r = T(1) / (A.eps + SIs[v]);
+                    Lam[v] += lam_s * r;
+                    if constexpr (LABEL) {
 #pragma unroll
-                    for (int l = k + 1; l < KD; ++l) t += T(2) * A.O[int64_t(tri_index(K, k, l)) * nc + c] * as[l];
-                    SIs += as[k] * t;
+                        for (int t = 0; t < kMaxFaces; ++t)
+                            if (t == s) rs[t][v] = r;
+                    }
+                    const T coef = lam_s * (r - r1[v]);
+#pragma unroll
+                    for (int i = 0; i < NTD; ++i) G[v][i] += coef * as[v][i];
                 }
-                SIs = fmax(SIs, T(0));
-                tsum += fabs(SI1 - SIs);
-                const T r = T(1) / (A.eps + SIs);
-                Lam += lam_s * r;
-#pragma unroll
-                for (int t = 0; t < kMaxFaces; ++t)
-                    if (t == s) rs[t] = r;
-                const T coef = lam_s * (r - r1);
-#pragma unroll
-                for (int k = 0; k < KD; ++k) G[k] += coef * as[k];
             }
         }
     }
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int i = NTD; i < NT; ++i) a[v][i] = park[wv][v * (NT - NTD) + i - NTD][lane];
     // (v) blend
     float lab = 0.f;
     if (nd > 0) {
-        const T tau = tsum / T(nd);
-        const T W = T(1) + tau * Lam;
-        const T s1 = (T(1) + tau * r1) / W;
-        const T tw = tau / W;
 #pragma unroll
-        for (int k = 0; k < K; ++k) a[k] *= s1;
+        for (int v = 0; v < 5; ++v) {
+            const T tau = tsum[v] / T(nd);
+            const T W = T(1) + tau * Lam[v];
+            const T s1 = (T(1) + tau * r1[v]) / W;
+            const T tw = tau / W;
 #pragma unroll
-        for (int k = 0; k < KD; ++k) a[k] += tw * G[k];
-        if constexpr (LABEL) {
-            lab = float(fabs(lam_1 * (s1 - T(1))));
+            for (int i = 0; i < NT; ++i) a[v][i] *= s1;
 #pragma unroll
-            for (int s = 0; s < kMaxFaces; ++s)
-                if (s < nd) lab = fmaxf(lab, float(fabs(lam_s * ((T(1) + tau * rs[s]) / W - T(1)))));
+            for (int i = 0; i < NTD; ++i)
+                if (4 * i + h < KD) a[v][i] += tw * G[v][i];
+            if constexpr (LABEL) {
+                lab = fmaxf(lab, float(fabs(lam_1 * (s1 - T(1)))));
+#pragma unroll
+                for (int s = 0; s < kMaxFaces; ++s)
+                    if (s < nd) lab = fmaxf(lab, float(fabs(lam_s * ((T(1) + tau * rs[s][v]) / W - T(1)))));
+            }
         }
     }
 
-    // (vi) point values at the cell's face points, slots [lf][q][v][cell]
-    T pm[K];
+    // (vi) point values at the cell's face points, slots [lf][q][v][cell]:
+    // lane h writes variable h, lane 0 also variable 4
+    T pm[NT];
 #pragma unroll
-    for (int k = 0; k < K; ++k) pm[k] = A.pmean[int64_t(k) * nc + c];
-    const int base = slot < kP4Cells ? 5 * slot : 0;
+    for (int i = 0; i < NT; ++i) pm[i] = A.pmean[int64_t(trow[i]) * nc + c];
     bool ok = true;
     const int NF = A.NF, Q = A.Q;
 #pragma unroll 1
@@ -214,28 +415,36 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
         const int nq = A.cnq[int64_t(lf) * nc + c];
 #pragma unroll 1
         for (int q = 0; q < Q; ++q) {
-            if (q >= nq) break;  // uniform within a cell's five lanes
+            if (q >= nq) break;  // uniform within a quad
             const int64_t row = (int64_t(lf) * Q + q) * 3;
             const T x = A.xi[row * nc + c], y = A.xi[(row + 1) * nc + c], z = A.xi[(row + 2) * nc + c];
-            T ph[K];
-            basis_p4<T>(x, y, z, pm, ph);
-            T d = T(0);
+            T t[K];
+            monomials_p4<T>(x, y, z, t);
+            T d[5];
 #pragma unroll
-            for (int k = 0; k < K; ++k) d += ph[k] * a[k];
-            const T val = T(ui + double(d));
-            if (valid) A.fs[((int64_t(lf) * Q + q) * 5 + v) * nc + c] = val;
-            // the point's five variables from the cell's lanes
-            const T r = p4_from(val, base), mx = p4_from(val, base + 1), my = p4_from(val, base + 2),
-                    mz = p4_from(val, base + 3), E = p4_from(val, base + 4);
-            const T p = A.gm1 * (E - T(0.5) * (mx * mx + my * my + mz * mz) / r);
-            ok = ok && (r > T(1e-10)) && (p > T(1e-10));
+            for (int v = 0; v < 5; ++v) d[v] = T(0);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                // the lane's term 4 i + h (padding terms carry zero coefficients)
+                const T t0 = t[4 * i], t1 = t[min(4 * i + 1, K - 1)], t2 = t[min(4 * i + 2, K - 1)],
+                        t3 = t[min(4 * i + 3, K - 1)];
+                const T ph = (h == 0 ? t0 : h == 1 ? t1 : h == 2 ? t2 : t3) - pm[i];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) d[v] += ph * a[v][i];
+            }
+            T val[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(quad_sum(d[v])));
+            T* out = A.fs + (int64_t(lf) * Q + q) * 5 * nc + c;
+            if (valid) {
+                out[int64_t(h) * nc] = h == 0 ? val[0] : h == 1 ? val[1] : h == 2 ? val[2] : val[3];
+                if (h == 0) out[4 * nc] = val[4];
+            }
+            const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+            ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
         }
     }
-    if constexpr (LABEL) {
-#pragma unroll
-        for (int t = 1; t < 5; ++t) lab = fmaxf(lab, p4_from(lab, base + t));
-    }
-    if (valid && v == 0) {
+    if (valid && h == 0) {
         A.flags[c] = uint8_t(ok ? 0 : 0x80);
         if constexpr (LABEL) A.label[c] = lab;
     }

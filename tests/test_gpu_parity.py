@@ -64,17 +64,18 @@ CASES = {
                                                          seed=8), 2,
                             dict(flux="hllc", viscous=True, mach=0.5, reynolds=20.0, gradients="least_squares"),
                             "slab", "sym"),
-    # P4 (CWENOZ5): 10 x 8 x 8 periodic hexahedra (640 cells: 13 blocks of
-    # 48 cells and a ragged tail, the last wave holding 4 of its 12 cells;
-    # the Taylor-Green field is not periodic over the box's x length, so the
-    # seam is a jump and the weights move)
+    # P4 (CWENOZ5): 10 x 9 x 7 periodic hexahedra (630 cells: 9 blocks of
+    # 64 cells and a ragged tail, the last wave holding 6 of its 16 cells;
+    # the Taylor-Green field is not periodic over the box's lengths, so the
+    # seams are jumps and the weights move)
     "hex98_p4_hllc": (lambda: _p4_box(), 4, dict(flux="hllc"), "tgv", None),
     "hex98_p4_hllc_ns": (lambda: _p4_box(), 4, dict(flux="hllc", viscous=True), "tgv", None),
 }
 
 
 def _p4_box():
-    return inputs.hex_box_mesh((10, 8, 8), (2 * math.pi * 10 / 8, 2 * math.pi, 2 * math.pi), (True, True, True))
+    return inputs.hex_box_mesh((10, 9, 7), (2 * math.pi * 10 / 8, 2 * math.pi * 9 / 8, 2 * math.pi * 7 / 8),
+                               (True, True, True))
 
 
 def _slab_state(x):
