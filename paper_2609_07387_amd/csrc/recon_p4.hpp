@@ -29,6 +29,7 @@ constexpr int kP4NO = kP4K * (kP4K + 1) / 2;  // rows of the upper triangle of O
 #define P4_WAVES 2
 #endif
 
+
 // The 34 monomials of degree 1..4 in graded-lex order (x exponent
 // descending, then y) at a face point's scaled offset.
 template <class T>
@@ -409,40 +410,51 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
 #pragma unroll
     for (int i = 0; i < NT; ++i) pm[i] = A.pmean[int64_t(trow[i]) * nc + c];
     bool ok = true;
-    const int NF = A.NF, Q = A.Q;
+    // the face points as one sequence p = lf Q + q; the next point's offsets
+    // and its face's point count load during the current point
+    const int Q = A.Q, NP = A.NF * A.Q;
+    auto point_in = [&](int p, T* xo, int& nq) {
+        const int pp = p < NP ? p : NP - 1;
+        const T* X = A.xi + int64_t(pp) * 3 * nc + c;
+        xo[0] = X[0];
+        xo[1] = X[nc];
+        xo[2] = X[2 * nc];
+        nq = A.cnq[int64_t(pp / Q) * nc + c];
+    };
+    T xn[3];
+    int nqn;
+    point_in(0, xn, nqn);
 #pragma unroll 1
-    for (int lf = 0; lf < NF; ++lf) {
-        const int nq = A.cnq[int64_t(lf) * nc + c];
-#pragma unroll 1
-        for (int q = 0; q < Q; ++q) {
-            if (q >= nq) break;  // uniform within a quad
-            const int64_t row = (int64_t(lf) * Q + q) * 3;
-            const T x = A.xi[row * nc + c], y = A.xi[(row + 1) * nc + c], z = A.xi[(row + 2) * nc + c];
-            T t[K];
-            monomials_p4<T>(x, y, z, t);
-            T d[5];
+    for (int p = 0; p < NP; ++p) {
+        const T x = xn[0], y = xn[1], z = xn[2];
+        const int nq = nqn;
+        point_in(p + 1, xn, nqn);
+        const int lf = p / Q, q = p - lf * Q;
+        if (q >= nq) continue;  // uniform within a quad
+        T t[K];
+        monomials_p4<T>(x, y, z, t);
+        T d[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) d[v] = T(0);
+        for (int v = 0; v < 5; ++v) d[v] = T(0);
 #pragma unroll
-            for (int i = 0; i < NT; ++i) {
-                // the lane's term 4 i + h (padding terms carry zero coefficients)
-                const T t0 = t[4 * i], t1 = t[min(4 * i + 1, K - 1)], t2 = t[min(4 * i + 2, K - 1)],
-                        t3 = t[min(4 * i + 3, K - 1)];
-                const T ph = (h == 0 ? t0 : h == 1 ? t1 : h == 2 ? t2 : t3) - pm[i];
+        for (int i = 0; i < NT; ++i) {
+            // the lane's term 4 i + h (padding terms carry zero coefficients)
+            const T t0 = t[4 * i], t1 = t[min(4 * i + 1, K - 1)], t2 = t[min(4 * i + 2, K - 1)],
+                    t3 = t[min(4 * i + 3, K - 1)];
+            const T ph = (h == 0 ? t0 : h == 1 ? t1 : h == 2 ? t2 : t3) - pm[i];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) d[v] += ph * a[v][i];
-            }
-            T val[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(quad_sum(d[v])));
-            T* out = A.fs + (int64_t(lf) * Q + q) * 5 * nc + c;
-            if (valid) {
-                out[int64_t(h) * nc] = h == 0 ? val[0] : h == 1 ? val[1] : h == 2 ? val[2] : val[3];
-                if (h == 0) out[4 * nc] = val[4];
-            }
-            const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-            ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
+            for (int v = 0; v < 5; ++v) d[v] += ph * a[v][i];
         }
+        T val[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(quad_sum(d[v])));
+        T* out = A.fs + int64_t(p) * 5 * nc + c;
+        if (valid) {
+            out[int64_t(h) * nc] = h == 0 ? val[0] : h == 1 ? val[1] : h == 2 ? val[2] : val[3];
+            if (h == 0) out[4 * nc] = val[4];
+        }
+        const T pr = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+        ok = ok && (val[0] > T(1e-10)) && (pr > T(1e-10));
     }
     if (valid && h == 0) {
         A.flags[c] = uint8_t(ok ? 0 : 0x80);
