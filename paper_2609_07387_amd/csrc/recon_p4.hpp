@@ -25,9 +25,11 @@ constexpr int kP4Q = 16;        // Gauss points per quadrilateral face (4 x 4)
 constexpr int kP4T = 9;         // central terms per lane
 constexpr int kP4TD = 3;        // directional terms per lane (g = 4 i + h < 9)
 constexpr int kP4NO = kP4K * (kP4K + 1) / 2;  // rows of the upper triangle of O
-#ifndef P4_WAVES
-#define P4_WAVES 2
-#endif
+// Waves per SIMD the kernel is built for (FP64: 256 VGPRs; FP32: 168, a
+// few values spilled, measured faster than 2 waves without spills) and how
+// many members ahead of the arithmetic the operator rows load.
+constexpr int kP4Waves64 = 2, kP4Waves32 = 3;
+constexpr int kP4OpAhead64 = 1, kP4OpAhead32 = 1;
 
 
 // The 34 monomials of degree 1..4 in graded-lex order (x exponent
@@ -99,6 +101,71 @@ __device__ __forceinline__ void p4_jumps(double uh, double u4, const double* ui,
     bv[2] = T(quad_mov<kQuadLane2>(uh) - ui[2]);
     bv[3] = T(quad_mov<kQuadLane3>(uh) - ui[3]);
     bv[4] = T(u4 - ui[4]);
+}
+
+// The member stream of a list of stencils: member q (q = 0 .. n-1) has its
+// id at row q of `sten` and its KR operator rows at rows q KR .. of `op`
+// (each [row][cell]); the lane loads the rows at its byte offsets off[].
+// body(q, bv, b) receives the member's five jumps and the lane's operator
+// values.  Loads run ahead of the arithmetic in 8-member trips with
+// compile-time register slots (no register is copied while its load is in
+// flight, and the DPP moves keep the compiler from unrolling a runtime loop
+// itself):
+//  ids: one load per 4 members, lane h of the quad taking member 4g + h
+//       (broadcast to the quad when used), 5 to 8 members ahead;
+//  states: 3 members ahead (4 slots of 2 values);
+//  operators: DB members ahead (DB + 1 slots, DB + 1 divides 8).
+// Rows past the last member read the last one, so every step issues the
+// same loads.
+template <class T, int NTL, int DB, class Body>
+__device__ __forceinline__ void p4_stream(const int32_t* sten, const T* op, int KR, int n, int64_t nc, uint32_t c4,
+                                          const uint32_t* off, __amdgpu_buffer_rsrc_t rU, uint32_t hrow, uint32_t rowU,
+                                          const double* ui, int h, Body&& body) {
+    constexpr int RB = DB + 1;
+    static_assert(8 % RB == 0, "operator slots must divide the trip");
+    const uint32_t rowI = uint32_t(nc) * 4u;
+    auto group = [&](int g) {
+        const int r0 = min(4 * g, n - 1);
+        const int o = min(4 * g + h, n - 1) - r0;
+        return bld<int32_t>(row_rsrc(sten, r0, nc, 4), c4 + uint32_t(o) * rowI, 0u);
+    };
+    auto load_b = [&](int q, T* b) {
+        const auto rB = row_rsrc(op, int64_t(min(q, n - 1)) * KR, nc, KR);
+#pragma unroll
+        for (int i = 0; i < NTL; ++i) b[i] = bld<T>(rB, off[i], 0u);
+    };
+    auto load_u = [&](int32_t j, double& uh, double& u4) {
+        uh = bld<double>(rU, uint32_t(j) * 8u + hrow, 0u);
+        u4 = bld<double>(rU, uint32_t(j) * 8u, 4u * rowU);
+    };
+    int32_t gA = group(0), gB = group(1);  // members 0..3 and 4..7
+    double uh[4], u4[4];
+    T b[RB][NTL];
+    load_u(quad_mov<kQuadLane0>(gA), uh[0], u4[0]);
+    load_u(quad_mov<kQuadLane1>(gA), uh[1], u4[1]);
+    load_u(quad_mov<kQuadLane2>(gA), uh[2], u4[2]);
+#pragma unroll
+    for (int d = 0; d < DB; ++d) load_b(d, b[d]);
+#pragma unroll 1
+    for (int q0 = 0; q0 < n; q0 += 8) {
+        static_for<0, 8>([&](auto S) {
+            constexpr int s = decltype(S)::value;
+            constexpr int L = (s + 3) % 4, CTRL = 0x55 * L;
+            const int q = q0 + s;
+            // member q + 3: slot A's lane 3 at s = 0, slot B's lanes at
+            // s = 1..4, the next A group's lanes 0..2 at s = 5..7
+            const int32_t j = quad_mov<CTRL>((s == 0 || s >= 5) ? gA : gB);
+            load_u(j, uh[(s + 3) % 4], u4[(s + 3) % 4]);
+            if constexpr (s == 0) gA = group(q0 / 4 + 2);  // members q0 + 8 .. q0 + 11
+            if constexpr (s == 4) gB = group(q0 / 4 + 3);  // members q0 + 12 .. q0 + 15
+            load_b(q + DB, b[(s + DB) % RB]);
+            if (q < n) {  // uniform
+                T bv[5];
+                p4_jumps<T>(uh[s % 4], u4[s % 4], ui, bv);
+                body(q, bv, b[s % RB]);
+            }
+        });
+    }
 }
 
 // One lane's share of the quadratic forms a_v^T O a_v (v = 0..4) over the
@@ -187,7 +254,7 @@ __device__ __forceinline__ void p4_forms(const T* __restrict__ O, int64_t nc, in
 // Every step per variable (component-wise).  LABEL: also the max over
 // stencils and variables of |omega - lambda| per cell.
 template <class T, bool LABEL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P4_WAVES)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? kP4Waves32 : kP4Waves64)))
 void reconstruct_p4_kernel(ReconArgs<T> A) {
     constexpr int K = kP4K, KD = kP4KD, NT = kP4T, NTD = kP4TD;
     const int64_t nc = A.nc;
@@ -200,70 +267,39 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
     double ui[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) ui[v] = A.U[v * nc + c];
-    const double* Uh = A.U + int64_t(h) * nc;
-    const double* U4 = A.U + 4 * nc;
-    // operator rows of the lane's terms (padding terms read the last row)
-    // and their diagonal rows of O
+    // Stencil streams are buffer loads: the member's rows in a scalar
+    // descriptor, the lane's byte offset in a 32-bit register (the launcher
+    // bounds every such span below 4 GiB).
+    const uint32_t cT = uint32_t(c) * uint32_t(sizeof(T)), c4 = uint32_t(c) * 4u;
+    const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
+    const auto rU = rsrc(A.U, uint64_t(5) * rowU);
+    const uint32_t hrow = uint32_t(h) * rowU;  // the lane's variable row of U
+    // operator rows of the lane's terms (padding terms read the last row),
+    // as byte offsets, and their diagonal rows of O
     int trow[NT], tbase[NT];
+    uint32_t toff[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
         const int g = 4 * i + h < K ? 4 * i + h : K;
         trow[i] = g < K ? g : K - 1;
         tbase[i] = p4_tri(g, g);
+        toff[i] = cT + uint32_t(trow[i]) * rowT;
     }
 
     // (ii) central coefficients; member m's id at sten_c[m][c], its K
-    // operator rows at Bc[m][k][c].  Operators and states load DEPTH members
-    // ahead of the arithmetic, ids one further.
+    // operator rows at Bc[m][k][c].
     T a[5][NT];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int i = 0; i < NT; ++i) a[v][i] = T(0);
-    const int MC = A.MC;
-    {
-        constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
-        auto last = [&](int m) { return m < MC ? m : MC - 1; };
-        auto id = [&](int m) { return A.sten_c[int64_t(last(m)) * nc + c]; };
-        auto load_b = [&](int m, T* b) {
-            const T* Bm = A.Bc + int64_t(last(m)) * K * nc + c;
+    p4_stream<T, NT, sizeof(T) == 4 ? kP4OpAhead32 : kP4OpAhead64>(A.sten_c, A.Bc, K, A.MC, nc, c4, toff, rU, hrow, rowU, ui, h,
+                                             [&](int, const T* bv, const T* b) {
 #pragma unroll
-            for (int i = 0; i < NT; ++i) b[i] = Bm[int64_t(trow[i]) * nc];
-        };
-        double uh[DEPTH + 1], u4[DEPTH + 1];
-        T b[DEPTH + 1][NT];
-        int32_t jn[DEPTH + 1];
+                                                 for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int d = 0; d <= DEPTH; ++d) jn[d] = id(d);
-#pragma unroll
-        for (int d = 0; d < DEPTH; ++d) {
-            uh[d] = Uh[jn[d]];
-            u4[d] = U4[jn[d]];
-            load_b(d, b[d]);
-        }
-        int32_t jnext = jn[DEPTH];
-#pragma unroll 1
-        for (int m = 0; m < MC; ++m) {
-            const int32_t jf = id(m + DEPTH + 1);
-            uh[DEPTH] = Uh[jnext];
-            u4[DEPTH] = U4[jnext];
-            load_b(m + DEPTH, b[DEPTH]);
-            T bv[5];
-            p4_jumps<T>(uh[0], u4[0], ui, bv);
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-#pragma unroll
-                for (int i = 0; i < NT; ++i) a[v][i] += b[0][i] * bv[v];
-#pragma unroll
-            for (int d = 0; d < DEPTH; ++d) {
-                uh[d] = uh[d + 1];
-                u4[d] = u4[d + 1];
-#pragma unroll
-                for (int i = 0; i < NT; ++i) b[d][i] = b[d + 1][i];
-            }
-            jnext = jf;
-        }
-    }
+                                                     for (int i = 0; i < NT; ++i) a[v][i] += b[i] * bv[v];
+                                             });
     if (4 * (NT - 1) + h >= K) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) a[v][NT - 1] = T(0);
@@ -299,9 +335,9 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
         }
     }
     if (nd > 0) {  // uniform within a quad
-        int drow[NTD];
+        uint32_t doff[NTD];  // the lane's directional operator rows as byte offsets
 #pragma unroll
-        for (int i = 0; i < NTD; ++i) drow[i] = 4 * i + h < KD ? 4 * i + h : KD - 1;
+        for (int i = 0; i < NTD; ++i) doff[i] = cT + uint32_t(4 * i + h < KD ? 4 * i + h : KD - 1) * rowT;
         const int MD = A.MD;
 #pragma unroll 1
         for (int s = 0; s < A.ND; ++s) {
@@ -310,48 +346,14 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
             for (int v = 0; v < 5; ++v)
 #pragma unroll
                 for (int i = 0; i < NTD; ++i) as[v][i] = T(0);
-            const int64_t r0 = int64_t(s) * MD;
-            constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
-            auto row = [&](int j) { return r0 + (j < MD ? j : MD - 1); };
-            auto id = [&](int j) { return A.sten_d[row(j) * nc + c]; };
-            auto load_b = [&](int j, T* b) {
-                const T* Bj = A.Bd + row(j) * KD * nc + c;
+            p4_stream<T, NTD, sizeof(T) == 4 ? kP4OpAhead32 : kP4OpAhead64>(A.sten_d + int64_t(s) * MD * nc, A.Bd + int64_t(s) * MD * KD * nc,
+                                                      KD, MD, nc, c4, doff, rU, hrow, rowU, ui, h,
+                                                      [&](int, const T* bv, const T* b) {
 #pragma unroll
-                for (int i = 0; i < NTD; ++i) b[i] = Bj[int64_t(drow[i]) * nc];
-            };
-            double uh[DEPTH + 1], u4[DEPTH + 1];
-            T b[DEPTH + 1][NTD];
-            int32_t jn[DEPTH + 1];
+                                                          for (int v = 0; v < 5; ++v)
 #pragma unroll
-            for (int d = 0; d <= DEPTH; ++d) jn[d] = id(d);
-#pragma unroll
-            for (int d = 0; d < DEPTH; ++d) {
-                uh[d] = Uh[jn[d]];
-                u4[d] = U4[jn[d]];
-                load_b(d, b[d]);
-            }
-            int32_t jnext = jn[DEPTH];
-#pragma unroll 1
-            for (int j = 0; j < MD; ++j) {
-                const int32_t jf = id(j + DEPTH + 1);
-                uh[DEPTH] = Uh[jnext];
-                u4[DEPTH] = U4[jnext];
-                load_b(j + DEPTH, b[DEPTH]);
-                T bv[5];
-                p4_jumps<T>(uh[0], u4[0], ui, bv);
-#pragma unroll
-                for (int v = 0; v < 5; ++v)
-#pragma unroll
-                    for (int i = 0; i < NTD; ++i) as[v][i] += b[0][i] * bv[v];
-#pragma unroll
-                for (int d = 0; d < DEPTH; ++d) {
-                    uh[d] = uh[d + 1];
-                    u4[d] = u4[d + 1];
-#pragma unroll
-                    for (int i = 0; i < NTD; ++i) b[d][i] = b[d + 1][i];
-                }
-                jnext = jf;
-            }
+                                                              for (int i = 0; i < NTD; ++i) as[v][i] += b[i] * bv[v];
+                                                      });
             if (4 * (NTD - 1) + h >= KD) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) as[v][NTD - 1] = T(0);
@@ -410,27 +412,20 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
 #pragma unroll
     for (int i = 0; i < NT; ++i) pm[i] = A.pmean[int64_t(trow[i]) * nc + c];
     bool ok = true;
-    // the face points as one sequence p = lf Q + q; the next point's offsets
-    // and its face's point count load during the current point
+    // The face points as one sequence p = lf Q + q, in trips of 8 points.
+    // Offsets load four points per instruction (lane h of the quad takes
+    // point 4g + h, broadcast to the quad when used) and 5 to 8 points
+    // ahead, with the point count of each point's face.
     const int Q = A.Q, NP = A.NF * A.Q;
-    auto point_in = [&](int p, T* xo, int& nq) {
-        const int pp = p < NP ? p : NP - 1;
+    auto group = [&](int g, T* xo, int& nq) {
+        const int pp = min(4 * g + h, NP - 1);
         const T* X = A.xi + int64_t(pp) * 3 * nc + c;
         xo[0] = X[0];
         xo[1] = X[nc];
         xo[2] = X[2 * nc];
         nq = A.cnq[int64_t(pp / Q) * nc + c];
     };
-    T xn[3];
-    int nqn;
-    point_in(0, xn, nqn);
-#pragma unroll 1
-    for (int p = 0; p < NP; ++p) {
-        const T x = xn[0], y = xn[1], z = xn[2];
-        const int nq = nqn;
-        point_in(p + 1, xn, nqn);
-        const int lf = p / Q, q = p - lf * Q;
-        if (q >= nq) continue;  // uniform within a quad
+    auto point = [&](int p, T x, T y, T z) {
         T t[K];
         monomials_p4<T>(x, y, z, t);
         T d[5];
@@ -455,6 +450,23 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
         }
         const T pr = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
         ok = ok && (val[0] > T(1e-10)) && (pr > T(1e-10));
+    };
+    T xa[3], xb[3];
+    int na, nb;
+    group(0, xa, na);
+    group(1, xb, nb);
+#pragma unroll 1
+    for (int p0 = 0; p0 < NP; p0 += 8) {
+        static_for<0, 8>([&](auto S) {
+            constexpr int s = decltype(S)::value, CTRL = 0x55 * (s % 4);
+            const int p = p0 + s;
+            const T* xg = s < 4 ? xa : xb;
+            const T x = quad_mov<CTRL>(xg[0]), y = quad_mov<CTRL>(xg[1]), z = quad_mov<CTRL>(xg[2]);
+            const int nq = quad_mov<CTRL>(s < 4 ? na : nb);
+            if constexpr (s == 3) group(p0 / 4 + 2, xa, na);  // points p0 + 8 .. p0 + 11
+            if constexpr (s == 7) group(p0 / 4 + 3, xb, nb);  // points p0 + 12 .. p0 + 15
+            if (p < NP && p - (p / Q) * Q < nq) point(p, x, y, z);  // uniform within a quad
+        });
     }
     if (valid && h == 0) {
         A.flags[c] = uint8_t(ok ? 0 : 0x80);

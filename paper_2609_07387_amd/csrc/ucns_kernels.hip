@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <mutex>
 #include <vector>
 
