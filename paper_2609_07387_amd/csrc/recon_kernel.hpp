@@ -77,62 +77,122 @@ __device__ __forceinline__ void central_coeffs(const ReconArgs<T>& A, int64_t c,
 #pragma unroll
         for (int v = 0; v < 5; ++v) a[k][v] = T(0);
     if constexpr (FEAT) js[0] = js[1] = js[2] = js[3] = T(0);
-    // Loads run DEPTH members ahead of the arithmetic (three in FP32, two in
-    // FP64: the kernels' register peak is in the directional phase, so this
-    // costs no occupancy) and member ids R = DEPTH + 1 members further still,
-    // so a state load finds its id loaded a whole trip earlier.  Member m
-    // sits in slot m % R; the loop advances R members per trip with
-    // compile-time slots (no register is copied while its load is in flight)
-    // and a scheduling barrier after each member (the scheduler would
-    // otherwise gather the trip's arithmetic at its top and wait there for
-    // every load in flight).
-    constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
-    constexpr int R = DEPTH + 1;
-    auto last = [&](int m) { return m < MC ? m : MC - 1; };
-    double u[R][5];
-    T b[R][K];
-    int32_t jr[R];  // id slot s: member m + DEPTH with (m + DEPTH) % R == s
-    auto load_member = [&](int m, int32_t j, double* uu, T* bb) {
+    if constexpr (K <= 9) {
+        // Loads run DEPTH members ahead of the arithmetic (three in FP32, two in
+        // FP64: the kernels' register peak is in the directional phase, so this
+        // costs no occupancy) and member ids R = DEPTH + 1 members further still,
+        // so a state load finds its id loaded a whole trip earlier.  Member m
+        // sits in slot m % R; the loop advances R members per trip with
+        // compile-time slots (no register is copied while its load is in flight)
+        // and a scheduling barrier after each member (the scheduler would
+        // otherwise gather the trip's arithmetic at its top and wait there for
+        // every load in flight).
+        constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
+        constexpr int R = DEPTH + 1;
+        auto last = [&](int m) { return m < MC ? m : MC - 1; };
+        double u[R][5];
+        T b[R][K];
+        int32_t jr[R];  // id slot s: member m + DEPTH with (m + DEPTH) % R == s
+        auto load_member = [&](int m, int32_t j, double* uu, T* bb) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) uu[v] = bld<double>(rU, uint32_t(j) * 8u, uint32_t(v) * rowU);
-        const auto rB = row_rsrc(A.Bc, int64_t(last(m)) * K, nc, K);
+            for (int v = 0; v < 5; ++v) uu[v] = bld<double>(rU, uint32_t(j) * 8u, uint32_t(v) * rowU);
+            const auto rB = row_rsrc(A.Bc, int64_t(last(m)) * K, nc, K);
 #pragma unroll
-        for (int k = 0; k < K; ++k) bb[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
-    };
+            for (int k = 0; k < K; ++k) bb[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+        };
 #pragma unroll
-    for (int d = 0; d < DEPTH + R; ++d) {
-        const int32_t j = member_id(last(d));
-        if (d < DEPTH)
-            load_member(d, j, u[d], b[d]);
-        else
-            jr[d % R] = j;
-    }
+        for (int d = 0; d < DEPTH + R; ++d) {
+            const int32_t j = member_id(last(d));
+            if (d < DEPTH)
+                load_member(d, j, u[d], b[d]);
+            else
+                jr[d % R] = j;
+        }
 #pragma unroll 1
-    for (int m0 = 0; m0 < MC; m0 += R) {
-        static_for<0, R>([&](auto S) {
-            constexpr int SL = decltype(S)::value, SD = (SL + DEPTH) % R;
-            const int m = m0 + SL;
-            // issue member m+DEPTH (operands) and the id of member m+DEPTH+R
-            const int32_t j = jr[SD];
-            jr[SD] = member_id(last(m + DEPTH + R));
-            load_member(m + DEPTH, j, u[SD], b[SD]);
-            if (m < MC) {  // uniform
-                T bv[5];
+        for (int m0 = 0; m0 < MC; m0 += R) {
+            static_for<0, R>([&](auto S) {
+                constexpr int SL = decltype(S)::value, SD = (SL + DEPTH) % R;
+                const int m = m0 + SL;
+                // issue member m+DEPTH (operands) and the id of member m+DEPTH+R
+                const int32_t j = jr[SD];
+                jr[SD] = member_id(last(m + DEPTH + R));
+                load_member(m + DEPTH, j, u[SD], b[SD]);
+                if (m < MC) {  // uniform
+                    T bv[5];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) bv[v] = T(u[SL][v] - ui[v]);
-                if constexpr (FEAT) {
-                    js[0] = fmax(js[0], fabs(bv[0]));
-                    js[1] += fabs(bv[0]);
-                    js[2] = fmax(js[2], fabs(bv[4]));
-                    js[3] += fabs(bv[4]);
+                    for (int v = 0; v < 5; ++v) bv[v] = T(u[SL][v] - ui[v]);
+                    if constexpr (FEAT) {
+                        js[0] = fmax(js[0], fabs(bv[0]));
+                        js[1] += fabs(bv[0]);
+                        js[2] = fmax(js[2], fabs(bv[4]));
+                        js[3] += fabs(bv[4]);
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) a[k][v] += b[SL][k] * bv[v];
                 }
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        }
+    } else {
+        // P3 (19 terms, one wave per SIMD in FP64): the loop unrolled by the
+        // compiler with the register ring shifted each member measured faster
+        // than fixed slots with a barrier per member.
+        // Loads run DEPTH members ahead of the arithmetic (member ids one further):
+        // three in FP32, two in FP64 (the kernels' register peak is in the
+        // directional phase, so this costs no occupancy).
+        constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
+        auto last = [&](int m) { return m < MC ? m : MC - 1; };
+        double u[DEPTH + 1][5];
+        T b[DEPTH + 1][K];
+        int32_t jn[DEPTH + 1];  // ids of members m+1 .. m+DEPTH+1 (jn[0] unused after the prologue)
 #pragma unroll
-                for (int k = 0; k < K; ++k)
+        for (int d = 0; d <= DEPTH; ++d) jn[d] = member_id(last(d));
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) a[k][v] += b[SL][k] * bv[v];
+        for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
+            const auto rB = row_rsrc(A.Bc, int64_t(last(d)) * K, nc, K);
+#pragma unroll
+            for (int k = 0; k < K; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+        }
+        int32_t jnext = jn[DEPTH];  // id of member DEPTH
+#pragma unroll DEPTH + 1
+        for (int m = 0; m < MC; ++m) {
+            // issue member m+DEPTH (operands) and the id of member m+DEPTH+1
+            const int mf = last(m + DEPTH);
+            const int32_t jf = member_id(last(m + DEPTH + 1));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
+            {
+                const auto rB = row_rsrc(A.Bc, int64_t(mf) * K, nc, K);
+#pragma unroll
+                for (int k = 0; k < K; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
             }
-            __builtin_amdgcn_sched_barrier(0);
-        });
+            // member m
+            T bv[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) bv[v] = T(u[0][v] - ui[v]);
+            if constexpr (FEAT) {
+                js[0] = fmax(js[0], fabs(bv[0]));
+                js[1] += fabs(bv[0]);
+                js[2] = fmax(js[2], fabs(bv[4]));
+                js[3] += fabs(bv[4]);
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) a[k][v] += b[0][k] * bv[v];
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) u[d][v] = u[d + 1][v];
+#pragma unroll
+                for (int k = 0; k < K; ++k) b[d][k] = b[d + 1][k];
+            }
+            jnext = jf;
+        }
     }
 }
 
@@ -477,66 +537,132 @@ __device__ __forceinline__ void dir_blend_lane(const ReconArgs<T>& A, int64_t c,
     const uint32_t c4 = uint32_t(c) * 4u, cT = uint32_t(c) * uint32_t(sizeof(T));
     const auto rU = rsrc(A.U, uint64_t(5) * rowU);
     auto member_id = [&](int t) { return bld<int32_t>(row_rsrc(A.sten_d, t, nc), c4, 0u); };
-    // loads DEPTH members ahead and ids R = DEPTH + 1 further, in trips of R
-    // members with compile-time slots, as in central_coeffs
-    constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
-    constexpr int R = DEPTH + 1;
-    auto last = [&](int t) { return t < total ? t : total - 1; };
-    double u[R][5];
-    T b[R][3];
-    int32_t jr[R];
-    auto load_member = [&](int t, int32_t j, double* uu, T* bb) {
+    if constexpr (K <= 9) {
+        // loads DEPTH members ahead and ids R = DEPTH + 1 further, in trips of R
+        // members with compile-time slots, as in central_coeffs
+        constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+        constexpr int R = DEPTH + 1;
+        auto last = [&](int t) { return t < total ? t : total - 1; };
+        double u[R][5];
+        T b[R][3];
+        int32_t jr[R];
+        auto load_member = [&](int t, int32_t j, double* uu, T* bb) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) uu[v] = bld<double>(rU, uint32_t(j) * 8u, uint32_t(v) * rowU);
-        const auto rB = row_rsrc(A.Bd, int64_t(last(t)) * 3, nc, 3);
+            for (int v = 0; v < 5; ++v) uu[v] = bld<double>(rU, uint32_t(j) * 8u, uint32_t(v) * rowU);
+            const auto rB = row_rsrc(A.Bd, int64_t(last(t)) * 3, nc, 3);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) bb[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
-    };
+            for (int k = 0; k < 3; ++k) bb[k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+        };
 #pragma unroll
-    for (int d = 0; d < DEPTH + R; ++d) {
-        const int32_t j = member_id(last(d));
-        if (d < DEPTH)
-            load_member(d, j, u[d], b[d]);
-        else
-            jr[d % R] = j;
-    }
-    T as[3][5];
+        for (int d = 0; d < DEPTH + R; ++d) {
+            const int32_t j = member_id(last(d));
+            if (d < DEPTH)
+                load_member(d, j, u[d], b[d]);
+            else
+                jr[d % R] = j;
+        }
+        T as[3][5];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) as[k][v] = T(0);
-    int m = 0, s = 0;
+            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+        int m = 0, s = 0;
 #pragma unroll 1
-    for (int t0 = 0; t0 < total; t0 += R) {
-        static_for<0, R>([&](auto S) {
-            constexpr int SL = decltype(S)::value, SD = (SL + DEPTH) % R;
-            const int t = t0 + SL;
-            const int32_t j = jr[SD];
-            jr[SD] = member_id(last(t + DEPTH + R));
-            load_member(t + DEPTH, j, u[SD], b[SD]);
-            if (t < total) {  // uniform
-                T bv[5];
+        for (int t0 = 0; t0 < total; t0 += R) {
+            static_for<0, R>([&](auto S) {
+                constexpr int SL = decltype(S)::value, SD = (SL + DEPTH) % R;
+                const int t = t0 + SL;
+                const int32_t j = jr[SD];
+                jr[SD] = member_id(last(t + DEPTH + R));
+                load_member(t + DEPTH, j, u[SD], b[SD]);
+                if (t < total) {  // uniform
+                    T bv[5];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) bv[v] = T(u[SL][v] - ui[v]);
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) as[k][v] += b[SL][k] * bv[v];
-                if (m + 1 == MD) {
-                    // stencil s complete
-                    if (s < nd) blend_add<T>(A, B, as);
+                    for (int v = 0; v < 5; ++v) bv[v] = T(u[SL][v] - ui[v]);
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) as[k][v] = T(0);
-                    m = 0;
-                    ++s;
-                } else {
-                    ++m;
+                        for (int v = 0; v < 5; ++v) as[k][v] += b[SL][k] * bv[v];
+                    if (m + 1 == MD) {
+                        // stencil s complete
+                        if (s < nd) blend_add<T>(A, B, as);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+#pragma unroll
+                            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+                        m = 0;
+                        ++s;
+                    } else {
+                        ++m;
+                    }
                 }
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        }
+    } else {
+        // P3: the compiler-unrolled ring, as in central_coeffs
+        // loads DEPTH members ahead (ids one further), as in central_coeffs
+        constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+        auto last = [&](int t) { return t < total ? t : total - 1; };
+        double u[DEPTH + 1][5];
+        T b[DEPTH + 1][3];
+        int32_t jn[DEPTH + 1];
+#pragma unroll
+        for (int d = 0; d <= DEPTH; ++d) jn[d] = member_id(last(d));
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u[d][v] = bld<double>(rU, uint32_t(jn[d]) * 8u, uint32_t(v) * rowU);
+            const auto rB = row_rsrc(A.Bd, int64_t(last(d)) * 3, nc, 3);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[d][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
+        }
+        int32_t jnext = jn[DEPTH];
+        T as[3][5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+        int m = 0, s = 0;
+#pragma unroll 1
+        for (int t = 0; t < total; ++t) {
+            const int tf = last(t + DEPTH);
+            const int32_t jf = member_id(last(t + DEPTH + 1));
+#pragma unroll
+            for (int v = 0; v < 5; ++v) u[DEPTH][v] = bld<double>(rU, uint32_t(jnext) * 8u, uint32_t(v) * rowU);
+            {
+                const auto rB = row_rsrc(A.Bd, int64_t(tf) * 3, nc, 3);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b[DEPTH][k] = bld<T>(rB, cT, uint32_t(k) * rowT);
             }
-            __builtin_amdgcn_sched_barrier(0);
-        });
+            T bv[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) bv[v] = T(u[0][v] - ui[v]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) as[k][v] += b[0][k] * bv[v];
+            if (m + 1 == MD) {
+                // stencil s complete
+                if (s < nd) blend_add<T>(A, B, as);
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) as[k][v] = T(0);
+                m = 0;
+                ++s;
+            } else {
+                ++m;
+            }
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) u[d][v] = u[d + 1][v];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b[d][k] = b[d + 1][k];
+            }
+            jnext = jf;
+        }
     }
     blend_finish<T, K, LABEL>(B, nd, lab, a);
 }
