@@ -340,6 +340,18 @@ int ucns_residual_rk_final_noalloc(const ucns_mesh* mesh, const ucns_phys* phys,
 int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* reduce_scratch, double* ke_dev,
                  ucns_stream stream);
 
+/* Solenoidal and dilatational dissipation rates of the Taylor-Green
+ * diagnostics (Sec. 4.2; the histories compared in Sec. 5.1), from the cell
+ * velocity gradients of a preceding ucns_gradients call in the same
+ * precision (gradW [12][n_cell], rows 3*var + dir):
+ *   eps_s = (mu/|Omega|) sum |V| |curl u|^2,
+ *   eps_d = (4 mu / (3 |Omega|)) sum |V| (div u)^2,   mu = 1/Re,
+ * each a deterministic two-pass sum in a fixed order (reduce_scratch as for
+ * ucns_diag_ke).  Writes eps_dev[0] = eps_s, eps_dev[1] = eps_d (device
+ * doubles).  UCNS_EINVAL without a Reynolds number. */
+int ucns_diag_dissipation(const ucns_mesh* mesh, const ucns_phys* phys, const void* gradW, int precision,
+                          double* reduce_scratch, double* eps_dev, ucns_stream stream);
+
 /* ---------------------------------------------------------------- gate */
 
 /* The gate is this library's addition to the paper's method: a learned

@@ -784,6 +784,43 @@ __global__ __launch_bounds__(kBlock) void ke_final_kernel(int nb, const double* 
     if (threadIdx.x == 0) *out = t * inv_vol;
 }
 
+// Solenoidal and dilatational dissipation (TGV diagnostics): per-block sums
+// of |V| |curl u|^2 and |V| (div u)^2 from the cell velocity gradients
+// (gradW rows 3 var + dir), then a fixed-order final sum.
+template <class T>
+__global__ __launch_bounds__(kBlock) void diss_partial_kernel(int64_t nc, const T* __restrict__ g,
+                                                              const double* __restrict__ vol, double* part) {
+    double ss = 0.0, sd = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < nc; c += int64_t(gridDim.x) * blockDim.x) {
+        auto G = [&](int var, int a) { return double(g[(3 * var + a) * nc + c]); };
+        const double wx = G(2, 1) - G(1, 2), wy = G(0, 2) - G(2, 0), wz = G(1, 0) - G(0, 1);
+        const double dv = G(0, 0) + G(1, 1) + G(2, 2);
+        ss += vol[c] * (wx * wx + wy * wy + wz * wz);
+        sd += vol[c] * dv * dv;
+    }
+    const double ts = block_reduce<false>(ss);
+    const double td = block_reduce<false>(sd);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = ts;
+        part[gridDim.x + blockIdx.x] = td;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void diss_final_kernel(int nb, const double* part, double mu_over_vol,
+                                                            double* out) {
+    double ss = 0.0, sd = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        ss += part[i];
+        sd += part[nb + i];
+    }
+    const double ts = block_reduce<false>(ss);
+    const double td = block_reduce<false>(sd);
+    if (threadIdx.x == 0) {
+        out[0] = mu_over_vol * ts;
+        out[1] = 4.0 / 3.0 * mu_over_vol * td;
+    }
+}
+
 // ----------------------------------------------------------------- helpers
 
 inline unsigned grid_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
@@ -1353,6 +1390,28 @@ int ucns_diag_ke(const ucns_mesh* mesh, const double* U, double* scratch, double
     hipLaunchKernelGGL(ke_partial_kernel, dim3(nb), dim3(kBlock), 0, st, m.nc, U, arena_ptr<double>(a, a.vol), scratch);
     hipLaunchKernelGGL(ke_final_kernel, dim3(1), dim3(kBlock), 0, st, int(nb), scratch, 1.0 / tv, ke_dev);
     return hip_check("ucns_diag_ke");
+}
+
+int ucns_diag_dissipation(const ucns_mesh* mesh, const ucns_phys* phys, const void* gradW, int precision,
+                          double* scratch, double* eps_dev, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && gradW && scratch && eps_dev, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
+    UCNS_REQUIRE(phys->reynolds > 0, UCNS_EINVAL, "dissipation needs a Reynolds number");
+    const Mesh& m = *mesh->m;
+    const Arena& a = m.arena[precision];
+    UCNS_REQUIRE(a.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const unsigned nb = std::min<unsigned>(kRedBlocks, grid_for(m.nc));
+    const double* vol = arena_ptr<double>(a, a.vol);
+    if (precision == UCNS_F64)
+        hipLaunchKernelGGL(diss_partial_kernel<double>, dim3(nb), dim3(kBlock), 0, st, m.nc,
+                           static_cast<const double*>(gradW), vol, scratch);
+    else
+        hipLaunchKernelGGL(diss_partial_kernel<float>, dim3(nb), dim3(kBlock), 0, st, m.nc,
+                           static_cast<const float*>(gradW), vol, scratch);
+    hipLaunchKernelGGL(diss_final_kernel, dim3(1), dim3(kBlock), 0, st, int(nb), scratch,
+                       1.0 / (phys->reynolds * m.total_vol), eps_dev);
+    return hip_check("ucns_diag_dissipation");
 }
 
 int ucns_check(const double* dt_dev, ucns_stream stream) {

@@ -30,7 +30,7 @@ EXPORTS = [
     "ucns_rk_stage", "ucns_residual_rk_stage", "ucns_diag_ke", "ucns_gate_features", "ucns_mlp_forward",
     "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
     "ucns_residual_ssp54_stage", "ucns_mesh_gradient_weights", "ucns_recon_span_bytes",
-    "ucns_check", "ucns_residual_rk_final_noalloc", "ucns_mesh_release",
+    "ucns_check", "ucns_residual_rk_final_noalloc", "ucns_mesh_release", "ucns_diag_dissipation",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
         L.ucns_rk_stage.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ucns_residual_rk_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
         L.ucns_diag_ke.argtypes = [vp, vp, vp, vp, vp]
+        L.ucns_diag_dissipation.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp]
         L.ucns_residual_ssp54_stage.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
         L.ucns_residual_rk_final.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.ucns_gate_features.argtypes = [vp, vp, i32, vp, vp]
@@ -385,6 +386,13 @@ def diag_ke(mesh, U, scratch, ke_dev, stream=None):
     check(lib().ucns_diag_ke(mesh.h, _dp(U), _dp(scratch), _dp(ke_dev), _stream(stream)))
 
 
+def diag_dissipation(mesh, ph, gradW, precision, scratch, eps_dev, stream=None):
+    """eps_dev (device double [2]) <- (solenoidal, dilatational) dissipation
+    from the cell gradients gradW of a preceding gradients() call."""
+    check(lib().ucns_diag_dissipation(mesh.h, C.byref(ph), _dp(gradW), precision, _dp(scratch), _dp(eps_dev),
+                                      _stream(stream)))
+
+
 class Solver:
     """SSP-RK3 driver over the C-ABI calls (one stream, no host syncs)."""
 
@@ -476,6 +484,21 @@ class Solver:
         """Raises UcnsError if the last computed time step flags a NaN/Inf or
         non-positive state (one host round trip)."""
         check_state(self.ws.dt)
+
+    def dissipation(self, U, eps_dev=None):
+        """Device double [2]: solenoidal and dilatational dissipation of U
+        (cell gradients by the solver's gradient method, then the reduction);
+        stays on the device."""
+        import torch
+
+        if eps_dev is None:
+            eps_dev = torch.empty(2, dtype=torch.float64, device=U.device)
+        gw = self.ws.gradW
+        if gw is None:
+            gw = self.ws.gradW = torch.empty(self.mesh.n_grad, dtype=_t(self.precision), device=U.device)
+        gradients(self.mesh, self.ph, self.bcs, U, self.precision, gw)
+        diag_dissipation(self.mesh, self.ph, gw, self.precision, self.ws.reduce, eps_dev)
+        return eps_dev
 
     def capture(self, U):
         """Records one SSP-RK3 step of U (this tensor, in place) as a HIP
