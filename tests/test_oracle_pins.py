@@ -64,7 +64,7 @@ def max_face_error(om, fs, f, skip_boundary=True):
     return err
 
 
-# ------------------------------------------------------------------ Pi 1
+# ------------------------------------------------------------------ benchmark-table counts
 
 
 def test_benchmark_table_counts():
@@ -109,7 +109,7 @@ def test_benchmark_table_counts():
             assert row["face_qps"] / row["faces"] == 6 and nq == 3
 
 
-# ------------------------------------------------------------------ Pi 2
+# ------------------------------------------------------------------ quadrature against closed forms
 
 
 def _single_tet_mesh(P):
@@ -197,7 +197,7 @@ def test_face_quadrature_exactness():
                     assert got == pytest.approx(1.0 / ((a + 1) * (b + 1)), rel=1e-13)
 
 
-# ------------------------------------------------------------------ Pi 3
+# ------------------------------------------------------------------ least-squares pseudo-inverses
 
 
 def test_pseudo_inverse_matches_library_pinv():
@@ -226,7 +226,7 @@ def test_pseudo_inverse_matches_library_pinv():
             assert np.abs(B @ np.diag(1.0 / vol[ids]) @ A - np.eye(K)).max() < 1e-12 * cond
 
 
-# ------------------------------------------------------------------ Pi 4
+# ------------------------------------------------------------------ polynomial reproduction and weights
 
 
 @pytest.mark.parametrize("ctype,order", [("hex", 2), ("tet", 2), ("tet", 3), ("hex", 3), ("hex", 4)])
@@ -284,7 +284,7 @@ def test_cwenoz_shifts_weight_at_discontinuity():
     assert label[near].min() > label2.max()
 
 
-# ------------------------------------------------------------------ Pi 5, Pi 6
+# ------------------------------------------------------------------ free stream and conservation
 
 
 @pytest.mark.parametrize("kind", ["hex", "tet", "mixed"])
@@ -320,7 +320,7 @@ def test_discrete_conservation_periodic():
     assert np.all(np.abs(tot - tot0) <= 1e-13 * (np.abs(U0) @ vol))
 
 
-# ------------------------------------------------------------------ Pi 7, Pi 8
+# ------------------------------------------------------------------ numerical fluxes and contacts
 
 
 def _rand_state(rng, gamma=1.4):
@@ -385,7 +385,7 @@ def test_steady_contact_hllc_vs_rusanov():
     assert np.abs(Ur[0] - U0[0]).max() > 1e-2
 
 
-# ------------------------------------------------------------------ Pi 10
+# ------------------------------------------------------------------ Riemann problem (Sod)
 
 
 def exact_riemann(WL, WR, xi, gamma=1.4):
@@ -511,7 +511,7 @@ def test_sod_tube_reduces_to_1d_and_converges():
     assert errs[2] < 0.01
 
 
-# ------------------------------------------------------------------ Pi 9
+# ------------------------------------------------------------------ design order (isentropic vortex)
 
 
 def _vortex_error(kind, n, order=2, t_end=0.5):
@@ -548,7 +548,7 @@ def test_isentropic_vortex_design_order(kind, ns, slope):
     assert rates[-1] >= slope, (errs, rates)
 
 
-# ------------------------------------------------------------------ Pi 11, Pi 12
+# ------------------------------------------------------------------ gradients, viscous fluxes, boundary planes
 
 
 def test_green_gauss_and_viscous_flux_linear_shear():
@@ -773,7 +773,7 @@ def test_tgv_initial_diagnostics_converge():
     assert errs_ke[0] / errs_ke[-1] > 12 and errs_es[0] / errs_es[-1] > 12
 
 
-# ------------------------------------------------------------------ Pi 13, Pi 14
+# ------------------------------------------------------------------ TGV diagnostics and time integrators
 
 
 def test_ssp_rk3_stability_polynomial():
@@ -836,7 +836,7 @@ def test_normal_shock_rankine_hugoniot():
     assert rho2 == pytest.approx(27.0 / 7.0, rel=1e-15) and p2 == pytest.approx(31.0 / 3.0, rel=1e-15)
 
 
-# ------------------------------------------------------------------ O6 (smoothness indicator)
+# ------------------------------------------------------------------ smoothness indicator (oscillation matrix O)
 
 
 def _monomial_exponents(order):
@@ -865,7 +865,7 @@ def _si_closed_form_cube(L):
 
 @pytest.mark.parametrize("order", [2, 3, 4])
 def test_smoothness_indicator_closed_form_on_a_cube(order):
-    """O6 (Sec. 2.2, eq. cwenoz_weights; indicator reading): for a polynomial
+    """The oscillation matrix O (Sec. 2.2, eq. cwenoz_weights; indicator reading): for a polynomial
     q = sum_k a_k phi_k, a^T O a = sum over multi-indices 1 <= |beta| <= r,
     each once, of |V|^(2|beta|/3 - 1) int_V (D^beta q)^2 in physical
     derivatives.  On a cube of side L != 1 the closed forms fix the
@@ -921,7 +921,7 @@ def _si_by_quadrature(x, w, vol, cen, h, a, order):
 
 @pytest.mark.parametrize("order", [2, 3])
 def test_smoothness_indicator_on_a_jittered_tetrahedron(order):
-    """O6 on a jittered tetrahedron with a random polynomial: a^T O a against
+    """O on a jittered tetrahedron with a random polynomial: a^T O a against
     the same sum built here from analytic derivatives and the oracle's volume
     quadrature (exact for these degrees; pinned by the closed forms above)."""
     m = inputs.kuhn_tet_mesh((3, 3, 3), (2 * math.pi,) * 3, (True,) * 3, 0.15, seed=4)
@@ -939,7 +939,7 @@ def test_smoothness_indicator_on_a_jittered_tetrahedron(order):
         assert np.linalg.eigvalsh(O).min() > -1e-12 * np.abs(O).max()
 
 
-# ------------------------------------------------------------------ viscous energy flux, Pi 11
+# ------------------------------------------------------------------ viscous energy flux
 
 
 def _interior_face_fluxes(om, U, ph, bcs):
@@ -1031,7 +1031,7 @@ def test_viscous_work_term_couette():
     assert ny > 0 and nx > 0
 
 
-# ------------------------------------------------------------------ time step (S19 reading)
+# ------------------------------------------------------------------ time step
 
 
 def test_time_step_closed_form_cube_and_kuhn_tets():
