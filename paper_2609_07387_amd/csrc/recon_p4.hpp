@@ -31,7 +31,6 @@ constexpr int kP4NO = kP4K * (kP4K + 1) / 2;  // rows of the upper triangle of O
 constexpr int kP4Waves64 = 2, kP4Waves32 = 3;
 constexpr int kP4OpAhead64 = 1, kP4OpAhead32 = 1;
 
-
 // The 34 monomials of degree 1..4 in graded-lex order (x exponent
 // descending, then y) at a face point's scaled offset.
 template <class T>
