@@ -46,14 +46,17 @@ def recon_bytes_per_cell(lm, precision, linear=False, gate=False):
     (neighbour states are re-reads of resident data).  linear: the cell
     takes the central polynomial only (no directional operators or
     indices).  gate: the in-kernel network's per-cell inputs (face-neighbour
-    ids and offsets, basis scale, stencil size) and its mask output."""
+    ids and offsets, basis scale, stencil size) and its mask output.  At
+    order 4 the call also stages the state cell-interleaved (40 bytes read,
+    64 written per cell)."""
     t = 8 if precision == 0 else 4
     K, MC, MD, ND, NF, Q = lm.K, lm.mc_pad, max(1, lm.md_pad), max(1, lm.nd_max), lm.nfmax, lm.qmax
     KD = getattr(lm, "kd", 3)  # terms of a directional polynomial (3 linear, 9 quadratic at P4)
     ops = K * MC + NF * Q * 3 + K + (0 if linear else K * (K + 1) // 2 + ND * KD * MD)
     idx = MC + (0 if linear else ND * MD)
     extra = (4 * NF + 3 * NF * t + t + 1 + 1) if gate else 0
-    return t * ops + 4 * idx + NF + 1 + 40 + t * 5 * NF * Q + 1 + extra
+    stage = 40 + 64 if K == 34 else 0
+    return t * ops + 4 * idx + NF + 1 + 40 + t * 5 * NF * Q + 1 + extra + stage
 
 
 def step_bytes_per_cell(lm, precision, viscous=True, recon=None):

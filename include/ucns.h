@@ -243,7 +243,10 @@ int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, doubl
  * (device [n_cell], required) records bit0 linear taken, bit1 CWENOZ
  * fallback, bit2 first-order fallback.  label (device float [n_cell],
  * may be NULL; only without a gate) receives max over variables and stencils
- * of |omega - lambda|. */
+ * of |omega - lambda|.  At order 4 the call first copies U, cell-interleaved,
+ * into a scratch region of the mesh's arena (64 bytes per cell, part of
+ * ucns_mesh_arena_bytes): two order-4 calls with one mesh and precision
+ * must not overlap (e.g. on two streams). */
 int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
                      const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream);
 

@@ -1121,6 +1121,7 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.hb = take(ts * nc);
     a.ncen = take(nc);
     a.glsq = take(ts * NF * 3 * nc);
+    a.ustage = take(m.order == 4 ? 64 * nc : 0);  // scratch, written per reconstruction call
     a.bytes = off;
     if (image) {
         image->assign(a.bytes, 0);

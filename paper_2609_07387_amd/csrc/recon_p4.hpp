@@ -118,7 +118,7 @@ __device__ __forceinline__ void p4_jumps(double uh, double u4, const double* ui,
 // same loads.
 template <class T, int NTL, int DB, class Body>
 __device__ __forceinline__ void p4_stream(const int32_t* sten, const T* op, int KR, int n, int64_t nc, uint32_t c4,
-                                          const uint32_t* off, __amdgpu_buffer_rsrc_t rU, uint32_t hrow, uint32_t rowU,
+                                          const uint32_t* off, __amdgpu_buffer_rsrc_t rS, uint32_t hofs,
                                           const double* ui, int h, Body&& body) {
     constexpr int RB = DB + 1;
     static_assert(8 % RB == 0, "operator slots must divide the trip");
@@ -133,9 +133,9 @@ __device__ __forceinline__ void p4_stream(const int32_t* sten, const T* op, int 
 #pragma unroll
         for (int i = 0; i < NTL; ++i) b[i] = bld<T>(rB, off[i], 0u);
     };
-    auto load_u = [&](int32_t j, double& uh, double& u4) {
-        uh = bld<double>(rU, uint32_t(j) * 8u + hrow, 0u);
-        u4 = bld<double>(rU, uint32_t(j) * 8u, 4u * rowU);
+    auto load_u = [&](int32_t j, double& uh, double& u4) {  // from the staged [cell][8] state
+        uh = bld<double>(rS, uint32_t(j) * 64u + hofs, 0u);
+        u4 = bld<double>(rS, uint32_t(j) * 64u + 32u, 0u);
     };
     int32_t gA = group(0), gB = group(1);  // members 0..3 and 4..7
     double uh[4], u4[4];
@@ -240,6 +240,22 @@ __device__ __forceinline__ void p4_forms(const T* __restrict__ O, int64_t nc, in
     for (int v = 0; v < 5; ++v) out[v] = fmax(quad_sum(s[v]), T(0));
 }
 
+// The state staged cell-interleaved, [cell][8] doubles (5 used): a stencil
+// member's five values then share one 64-byte segment, one cache line for
+// the quad where the [5][cell] rows of U would take five.
+__global__ __launch_bounds__(kBlock) void p4_stage_state_kernel(const double* __restrict__ U, int64_t nc,
+                                                               double* __restrict__ S) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double v[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = U[k * nc + c];
+    double2* o = reinterpret_cast<double2*>(S + c * 8);
+    o[0] = double2{v[0], v[1]};
+    o[1] = double2{v[2], v[3]};
+    S[c * 8 + 4] = v[4];
+}
+
 // Steps per quad (cell c; lane h owns the terms g = 4 i + h of all variables):
 //  (i)   jumps b_m = U_m - U_c in FP64, rounded to T
 //  (ii)  a = B_c b (34 terms)
@@ -270,9 +286,9 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
     // descriptor, the lane's byte offset in a 32-bit register (the launcher
     // bounds every such span below 4 GiB).
     const uint32_t cT = uint32_t(c) * uint32_t(sizeof(T)), c4 = uint32_t(c) * 4u;
-    const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T)), rowU = uint32_t(nc) * 8u;
-    const auto rU = rsrc(A.U, uint64_t(5) * rowU);
-    const uint32_t hrow = uint32_t(h) * rowU;  // the lane's variable row of U
+    const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T));
+    const auto rS = rsrc(A.ustage, uint64_t(nc) * 64u);  // the staged [cell][8] state
+    const uint32_t hofs = uint32_t(h) * 8u;              // the lane's variable in a cell's record
     // operator rows of the lane's terms (padding terms read the last row),
     // as byte offsets, and their diagonal rows of O
     int trow[NT], tbase[NT];
@@ -292,7 +308,7 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
     for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int i = 0; i < NT; ++i) a[v][i] = T(0);
-    p4_stream<T, NT, sizeof(T) == 4 ? kP4OpAhead32 : kP4OpAhead64>(A.sten_c, A.Bc, K, A.MC, nc, c4, toff, rU, hrow, rowU, ui, h,
+    p4_stream<T, NT, sizeof(T) == 4 ? kP4OpAhead32 : kP4OpAhead64>(A.sten_c, A.Bc, K, A.MC, nc, c4, toff, rS, hofs, ui, h,
                                              [&](int, const T* bv, const T* b) {
 #pragma unroll
                                                  for (int v = 0; v < 5; ++v)
@@ -346,7 +362,7 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
 #pragma unroll
                 for (int i = 0; i < NTD; ++i) as[v][i] = T(0);
             p4_stream<T, NTD, sizeof(T) == 4 ? kP4OpAhead32 : kP4OpAhead64>(A.sten_d + int64_t(s) * MD * nc, A.Bd + int64_t(s) * MD * KD * nc,
-                                                      KD, MD, nc, c4, doff, rU, hrow, rowU, ui, h,
+                                                      KD, MD, nc, c4, doff, rS, hofs, ui, h,
                                                       [&](int, const T* bv, const T* b) {
 #pragma unroll
                                                           for (int v = 0; v < 5; ++v)

@@ -49,6 +49,7 @@ struct Arena {
     size_t vol = 0, hdt = 0, fcell = 0, flf = 0, fnrm = 0, farea = 0, fw = 0, fdc = 0, fnq = 0;
     size_t nbr = 0, ndc = 0, hb = 0, ncen = 0;  // gate features: face neighbours, offsets, basis scale, stencil size
     size_t glsq = 0;  // [nfmax][3][nc] least-squares gradient weights per face slot
+    size_t ustage = 0;  // P4 only: [nc][8] FP64, the state staged cell-interleaved by each reconstruction call
     void* dev = nullptr;  // caller-owned device pointer after upload
 };
 

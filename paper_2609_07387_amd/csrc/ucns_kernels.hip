@@ -112,6 +112,7 @@ struct ReconArgs {
     const T* ndc;
     const T* hb;
     const uint8_t* ncen;
+    double* ustage;  // P4: the state staged [cell][8] (scratch in the arena)
 };
 
 __device__ __forceinline__ int tri_index(int K, int k, int l) { return k * K - (k * (k - 1)) / 2 + (l - k); }
@@ -877,6 +878,8 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.ndc = arena_ptr<T>(ar, ar.ndc);
     A.hb = arena_ptr<T>(ar, ar.hb);
     A.ncen = arena_ptr<uint8_t>(ar, ar.ncen);
+    // the arena's one scratch region (written by the P4 reconstruction call)
+    A.ustage = ar.ustage ? reinterpret_cast<double*>(static_cast<unsigned char*>(ar.dev) + ar.ustage) : nullptr;
     A.fs = static_cast<T*>(fs);
     A.flags = flags;
     A.label = label;
@@ -907,8 +910,9 @@ int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
 // (the gate's network is trained on P2 features).
 template <class T>
 int launch_recon_p4(const ReconArgs<T>& A, hipStream_t st) {
-    if (A.Q > kP4Q || A.NF > kMaxFaces || A.mlp || A.gate) return UCNS_EINVAL;
+    if (A.Q > kP4Q || A.NF > kMaxFaces || A.mlp || A.gate || !A.ustage) return UCNS_EINVAL;
     if (recon_span_bytes(A.nc, int(sizeof(T)), kP4K, A.NF) > kMaxDescriptorBytes) return UCNS_EINVAL;
+    hipLaunchKernelGGL(p4_stage_state_kernel, dim3(grid_for(A.nc)), dim3(kBlock), 0, st, A.U, A.nc, A.ustage);
     const int64_t per_block = int64_t(kBlock / 64) * kP4Cells;
     const dim3 grid(unsigned((A.nc + per_block - 1) / per_block)), block(kBlock);
     if (A.label)
