@@ -172,7 +172,9 @@ void ucns_mesh_free(ucns_mesh* mesh);
  * KD (unknowns of a directional polynomial: 3 linear, 9 quadratic), 0, 0. */
 int ucns_mesh_info(const ucns_mesh* mesh, int64_t* info);
 
-/* Bytes of the device arena holding all mesh arrays for one precision. */
+/* Bytes of the device arena holding all mesh arrays for one precision (at
+ * order 4 also a scratch region of 64 bytes per cell that ucns_reconstruct
+ * writes). */
 int ucns_mesh_arena_bytes(const ucns_mesh* mesh, int precision, size_t* bytes);
 
 /* Largest byte span that one buffer descriptor of the reconstruction
