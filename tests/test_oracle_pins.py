@@ -1167,3 +1167,44 @@ def test_p4_free_stream_and_conservation():
     U[4] = np.where(cx < math.pi, 2.5 / 0.4, 1.0 / 0.4) + 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2)
     _, _, label = om.reconstruct(U, ph, with_flags=True)
     assert label.max() > 0.3
+
+
+# ------------------------------------------------------------------ gate features
+
+
+def test_gate_features_on_linear_data():
+    """The twelve gate features (the reading of section 6 of the design notes:
+    max and mean stencil jumps, the central gradient's size, and the face
+    neighbours' deviation from it) on exactly linear data of a non-periodic
+    jittered tetrahedral box, for rho and rho E, against the same quantities
+    built here from the oracle's stencil lists and centroids: the central
+    polynomial reproduces linear data, so its gradient is the field's b (the
+    feature h |b| / |v_i|) and every face neighbour lies on the plane (the
+    deviation features sit at log(1e-12))."""
+    m = inputs.kuhn_tet_mesh((5, 5, 5), (1.0, 1.0, 1.0), (False, False, False), 0.15, seed=9)
+    om = oracle.OracleMesh(m, order=2)
+    vol, cen, hb = om.cell_data()
+    b_rho, b_e = np.array([0.3, -0.2, 0.1]), np.array([-0.5, 0.25, 0.4])
+    U = np.zeros((5, om.n_cell))
+    U[0] = 2.0 + cen @ b_rho   # cell averages of a linear field: values at the centroids
+    U[4] = 5.0 + cen @ b_e
+    U[1] = 0.1
+    F = om.gate_features(U, oracle.phys())
+    c2f, side = om.cell_faces()
+    fd = om.face_data()
+    checked = 0
+    for c in range(om.n_cell):
+        nbrs = [int(fd["cells"][c2f[c, lf], 1 - side[c, lf]]) for lf in range(4)]
+        if min(nbrs) < 0:
+            continue  # boundary cells: the deviation features skip boundary faces
+        members, _, _ = om.stencil(c)
+        for t, (v, b) in enumerate(((0, b_rho), (4, b_e))):
+            ui = U[v, c]
+            d = np.abs(U[v, members] - ui) / abs(ui)
+            f = F[c, 6 * t:6 * t + 6]
+            assert abs(f[0] - np.log(1e-12 + d.max())) < 1e-9
+            assert abs(f[1] - np.log(1e-12 + d.mean())) < 1e-9
+            assert abs(f[2] - np.log(1e-12 + hb[c] * np.linalg.norm(b) / abs(ui))) < 1e-9
+            assert f[3] < np.log(1e-9) and f[4] < np.log(1e-9) and f[5] < np.log(1e-9)
+        checked += 1
+    assert checked > 10
