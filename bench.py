@@ -29,15 +29,21 @@ HBM_PEAK_GBS = 8000.0
 # The dominant step is the reconstruction: one ucns_reconstruct call, timed
 # as a whole with HIP events; its kernels, and the record of their measured
 # HBM bytes per call (rocprofv3 counters, summed over the call's kernels)
-RECON_KERNELS = {
-    "fp32_gate": "reconstruct_kernel<float, 9, false, true>|reconstruct_fallback_kernel<float, 9>",
-    "fp64_plain": "reconstruct_kernel<double, 9, false, false>|reconstruct_fallback_kernel<double, 9>"}
+def recon_kernels(head, fused):
+    """Kernel names of one reconstruction call (main pass | positivity pass);
+    fused: the main pass also forms the Green-Gauss gradients."""
+    t, g = ("float", "true") if head == "fp32_gate" else ("double", "false")
+    return (f"reconstruct_kernel<{t}, 9, false, {g}, {'true' if fused else 'false'}>"
+            f"|reconstruct_fallback_kernel<{t}, 9>")
+
+
+
 TRAFFIC = {"fp32_gate": "traffic_reconstruct_fp32_gate_tgv64.md",
            "fp64_plain": "traffic_reconstruct_fp64_tgv64.md"}
 METRIC = "cell-stage updates/s, P2 CWENO+HLLC: FP64 plain vs FP32+MLP gate; % HBM peak"
 
 
-def recon_bytes_per_cell(lm, precision, linear=False, gate=False):
+def recon_bytes_per_cell(lm, precision, linear=False, gate=False, grad=False):
     """Algorithmic HBM bytes of one reconstruction of one cell: every operator
     value and index read once (the basis at a face point is recomputed from
     the point's 3 scaled coordinates and the cell's K basis means; one byte
@@ -46,9 +52,11 @@ def recon_bytes_per_cell(lm, precision, linear=False, gate=False):
     (neighbour states are re-reads of resident data).  linear: the cell
     takes the central polynomial only (no directional operators or
     indices).  gate: the in-kernel network's per-cell inputs (face-neighbour
-    ids and offsets, basis scale, stencil size) and its mask output.  At
-    order 4 the call also stages the state cell-interleaved (40 bytes read,
-    64 written per cell)."""
+    ids and offsets, basis scale, stencil size) and its mask output.  grad:
+    the call also forms the Green-Gauss gradients (the face-neighbour ids,
+    unless the gate has read them, each face slot's three weights, the twelve
+    gradient values written).  At order 4 the call also stages the state
+    cell-interleaved (40 bytes read, 64 written per cell)."""
     t = 8 if precision == 0 else 4
     K, MC, MD, ND, NF, Q = lm.K, lm.mc_pad, max(1, lm.md_pad), max(1, lm.nd_max), lm.nfmax, lm.qmax
     KD = getattr(lm, "kd", 3)  # terms of a directional polynomial (3 linear, 9 quadratic at P4)
@@ -56,18 +64,20 @@ def recon_bytes_per_cell(lm, precision, linear=False, gate=False):
     idx = MC + (0 if linear else ND * MD)
     extra = (4 * NF + 3 * NF * t + t + 1 + 1) if gate else 0
     stage = 40 + 64 if K == 34 else 0
-    return t * ops + 4 * idx + NF + 1 + 40 + t * 5 * NF * Q + 1 + extra + stage
+    ggrad = ((0 if gate else 4 * NF) + 3 * NF * t + 12 * t) if grad else 0
+    return t * ops + 4 * idx + NF + 1 + 40 + t * 5 * NF * Q + 1 + extra + stage + ggrad
 
 
-def step_bytes_per_cell(lm, precision, viscous=True, recon=None):
+def step_bytes_per_cell(lm, precision, viscous=True, recon=None, fused=False):
     """Algorithmic HBM bytes of one stage of the whole path per cell (recon:
-    the reconstruction's share, default the full CWENOZ one)."""
+    the reconstruction's share, default the full CWENOZ one; fused: the
+    gradients are part of it)."""
     t = 8 if precision == 0 else 4
     faces_per_cell = lm.n_face / lm.n_cell
     Q, NF = lm.qmax, lm.nfmax
     recon = recon_bytes_per_cell(lm, precision) if recon is None else recon
     flux = faces_per_cell * (2 * Q * 5 * t + t * (7 + Q) + 9 + 5 * t + (24 * t if viscous else 0))
-    grad = (40 + 4 * NF + 12 * t + faces_per_cell * (8 + 4 * t)) if viscous else 0
+    grad = (40 + 4 * NF + 12 * t + faces_per_cell * (8 + 4 * t)) if viscous and not fused else 0
     resid = 4 * NF + 5 * t * NF + 8 + 40 * 3
     return recon + flux + grad + resid
 
@@ -299,14 +309,16 @@ def main():
         # reconstruction kernels are this replay's timed calls
         rms, frac = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         gate = net is not None
-        rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate)
-               + frac * recon_bytes_per_cell(lm, prec, linear=True, gate=gate))
+        fused = solver.fused
+        rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate, grad=fused)
+               + frac * recon_bytes_per_cell(lm, prec, linear=True, gate=gate, grad=fused))
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
                           ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps,
                           "ms_per_step_runs": [r[0] / args.steps for r in per_run],
                           "recon_ms": rms, "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
-                          "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, recon=rbc),
-                          "path_GBs": step_bytes_per_cell(lm, prec, recon=rbc) * rate / 1e9}
+                          "fused_gradients": fused,
+                          "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, recon=rbc, fused=fused),
+                          "path_GBs": step_bytes_per_cell(lm, prec, recon=rbc, fused=fused) * rate / 1e9}
         if net is not None:
             variants[name]["fraction_gated"] = frac
         if long_rate is not None:
@@ -318,7 +330,7 @@ def main():
     copy_calibration(torch)
     head = "fp32_gate" if "fp32_gate" in variants else "fp64_plain"
     hv = variants[head]
-    kname = RECON_KERNELS[head]
+    kname = recon_kernels(head, hv["fused_gradients"])
     achieved = hv["recon_GBs"]
     from paper_2609_07387_amd import prof
 
@@ -339,7 +351,8 @@ def main():
         "speedup_vs_fp64_plain": hv["value"] / variants["fp64_plain"]["value"],
         "speedup_vs_fp64_plain_200_steps": (hv["value_200_steps"] / variants["fp64_plain"]["value_200_steps"]
                                             if "value_200_steps" in hv else None),
-        "roofline": {"kernel": "ucns_reconstruct call: " + " + ".join(kname.split("|")), "bound": "hbm",
+        "roofline": {"kernel": ("ucns_reconstruct_gradients" if hv["fused_gradients"] else "ucns_reconstruct")
+                               + " call: " + " + ".join(kname.split("|")), "bound": "hbm",
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": hv["recon_bytes_per_cell"] * nc,

@@ -1011,6 +1011,7 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
     auto* hb = reinterpret_cast<T*>(base + a.hb);
     auto* ncen = reinterpret_cast<uint8_t*>(base + a.ncen);
     auto* glsq = reinterpret_cast<T*>(base + a.glsq);
+    auto* ggw = reinterpret_cast<T*>(base + a.ggw);
     for (int64_t c = 0; c < nc; ++c) {
         hb[c] = T(m.hb[c]);
         for (int lf = 0; lf < NF; ++lf)
@@ -1019,17 +1020,21 @@ void fill_arena(const Mesh& m, const Arena& a, unsigned char* base) {
         for (int lf = 0; lf < NF; ++lf) {
             const int32_t fs = m.c2f[c * kMaxFaces + lf];
             int32_t j = -1;
-            double d[3] = {0, 0, 0};
+            double d[3] = {0, 0, 0}, w[3] = {0, 0, 0};
             if (fs >= 0) {
                 const int64_t f = fs >> 1, side = fs & 1;
                 const int64_t other = m.fcell[2 * f + (1 - side)];
-                if (other >= 0) {
-                    j = int32_t(other);
+                j = int32_t(other);  // a boundary face keeps its negative tag
+                if (other >= 0)
                     for (int k = 0; k < 3; ++k) d[k] = (side ? -1.0 : 1.0) * m.fdc[3 * f + k];
-                }
+                const double s = (side ? -0.5 : 0.5) * m.farea[f] / m.vol[c];
+                for (int k = 0; k < 3; ++k) w[k] = s * m.fnrm[3 * f + k];
             }
             nbr[size_t(lf) * nc + c] = j;
-            for (int k = 0; k < 3; ++k) ndc[(size_t(lf) * 3 + k) * nc + c] = T(d[k]);
+            for (int k = 0; k < 3; ++k) {
+                ndc[(size_t(lf) * 3 + k) * nc + c] = T(d[k]);
+                ggw[(size_t(lf) * 3 + k) * nc + c] = T(w[k]);
+            }
         }
     }
     std::vector<int> perm(kMaxCentral);
@@ -1121,6 +1126,7 @@ int pack_arena(const Mesh& m, int precision, Arena& a, std::vector<unsigned char
     a.hb = take(ts * nc);
     a.ncen = take(nc);
     a.glsq = take(ts * NF * 3 * nc);
+    a.ggw = take(ts * NF * 3 * nc);
     a.ustage = take(m.order == 4 ? 64 * nc : 0);  // scratch, written per reconstruction call
     a.bytes = off;
     if (image) {

@@ -973,8 +973,10 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 // imposes.
 //
 // A cell whose point states violate positivity is marked with bit 7 of its
-// flag for the fallback pass.
-template <class T, int K, bool LABEL, bool GATE>
+// flag for the fallback pass.  GRAD: the cell then forms its Green-Gauss
+// gradient of W as well (the positivity fallback changes point states only,
+// never the cell averages the gradient is taken from).
+template <class T, int K, bool LABEL, bool GATE, bool GRAD = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GATE && sizeof(T) == 4 && K == 9 ? 3 : 1)))
 void reconstruct_kernel(ReconArgs<T> A) {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
@@ -1037,6 +1039,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
         if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
         const bool ok = face_values<T, K>(A, c, ui, 0, a);
         A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
+        if constexpr (GRAD) cell_gradient_gg<T>(A, c, ui);
     } else {
         if (!valid) return;
 #pragma unroll
@@ -1046,6 +1049,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
         const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
         A.flags[c] = uint8_t(ok ? 0 : 0x80);
         if constexpr (LABEL) A.label[c] = lab;
+        if constexpr (GRAD) cell_gradient_gg<T>(A, c, ui);
     }
 }
 

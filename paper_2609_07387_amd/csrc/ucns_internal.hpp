@@ -47,8 +47,11 @@ struct Arena {
     size_t sten_c = 0, Bc = 0, ndir = 0, sten_d = 0, Bd = 0, O = 0, xi = 0, pmean = 0, c2f = 0;
     size_t cnq = 0;  // [nfmax][nc] Gauss points of each of a cell's face slots (0: no face)
     size_t vol = 0, hdt = 0, fcell = 0, flf = 0, fnrm = 0, farea = 0, fw = 0, fdc = 0, fnq = 0;
-    size_t nbr = 0, ndc = 0, hb = 0, ncen = 0;  // gate features: face neighbours, offsets, basis scale, stencil size
+    // face neighbours ([nfmax][nc]; a boundary slot holds its face's negative tag, an absent one -1),
+    // their centroid offsets, basis scale, stencil size (gate features; fused gradients)
+    size_t nbr = 0, ndc = 0, hb = 0, ncen = 0;
     size_t glsq = 0;  // [nfmax][3][nc] least-squares gradient weights per face slot
+    size_t ggw = 0;   // [nfmax][3][nc] Green-Gauss weights per face slot: outward n |S| / (2 |V|)
     size_t ustage = 0;  // P4 only: [nc][8] FP64, the state staged cell-interleaved by each reconstruction call
     void* dev = nullptr;  // caller-owned device pointer after upload
 };

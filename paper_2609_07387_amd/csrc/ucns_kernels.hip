@@ -113,7 +113,16 @@ struct ReconArgs {
     const T* hb;
     const uint8_t* ncen;
     double* ustage;  // P4: the state staged [cell][8] (scratch in the arena)
+    // Green-Gauss gradients of the same state in the same pass (null: none);
+    // the boundary table in device memory (null: every boundary transmissive)
+    T* gradW;
+    const T* ggw;
+    const ucns_bc* bcd;
+    T gM2;
 };
+
+template <class T>
+__device__ void cell_gradient_gg(const ReconArgs<T>& A, int64_t c, const double* ui);
 
 __device__ __forceinline__ int tri_index(int K, int k, int l) { return k * K - (k * (k - 1)) / 2 + (l - k); }
 
@@ -376,6 +385,98 @@ __global__ __launch_bounds__(kBlock) void gradients_kernel(GradArgs<T> A, PhysT<
     const T iv = LSQ ? T(1) : T(1.0 / A.vol[c]);
 #pragma unroll
     for (int k = 0; k < 12; ++k) A.gradW[k * nc + c] = g[k] * iv;
+}
+
+// The ghost state of ghost() for the cell-average interior state, the
+// boundary table read from device memory with the lane's own tag (a table
+// passed by value, selected with compile-time indices, would hold 48 scalar
+// registers through the long reconstruction kernels and spill them).
+template <class T>
+__device__ __forceinline__ void ghost_dev(const ucns_bc* bc, int tag, const T* in, const T* n, T* out) {
+    const int t = tag > 0 && tag < 8 ? tag : 0;
+    int kind = UCNS_BC_TRANSMISSIVE;
+    T st[5] = {T(0), T(0), T(0), T(0), T(0)};
+    if (bc && t > 0) {
+        kind = bc->kind[t];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) st[v] = T(bc->state[t][v]);
+    }
+    // selects, not branches (a branch per kind lets the compiler merge the
+    // table loads with the copies of the interior state and move that state
+    // to memory); a transmissive slot subtracts an exact zero
+    const bool dir = kind == UCNS_BC_DIRICHLET, wall = kind == UCNS_BC_WALL;
+    const T mn2 = kind == UCNS_BC_SYMMETRY ? T(2) * (in[1] * n[0] + in[2] * n[1] + in[3] * n[2]) : T(0);
+    out[0] = dir ? st[0] : in[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[1 + a] = dir ? st[1 + a] : (wall ? -in[1 + a] : in[1 + a] - mn2 * n[a]);
+    out[4] = dir ? st[4] : in[4];
+}
+
+// Green-Gauss gradient of one cell at the end of its reconstruction (the
+// sum of gradients_kernel<T, false>, each slot's outward n |S| / (2 |V|)
+// stored with the mesh; a boundary slot's neighbour entry is its face's
+// negative tag, an absent slot's weights are zero).  The neighbours' states
+// were gathered by the cell's central stencil a moment earlier.
+template <class T>
+__device__ void cell_gradient_gg(const ReconArgs<T>& A, int64_t c, const double* ui) {
+    const int64_t nc = A.nc;
+    // W of a state, as prim_W forms it
+    auto primw = [&](const T* q, T* W) {
+        const T ir = T(1) / q[0];
+        W[0] = q[1] * ir;
+        W[1] = q[2] * ir;
+        W[2] = q[3] * ir;
+        W[3] = A.gM2 * (A.gm1 * (q[4] - T(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0])) * ir;
+    };
+    T u[5], Wi[4], g[12];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = T(ui[v]);
+    primw(u, Wi);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) g[k] = T(0);
+    // every load unconditional (a slot beyond the mesh's NF reads slot 0 and
+    // is then taken as absent: transmissive ghost, zero weights)
+    int32_t jn[kMaxFaces];
+    T w[kMaxFaces][3];
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf) {
+        const bool have = lf < A.NF;
+        const int64_t r = have ? lf : 0;
+        const int32_t j = A.nbr[r * nc + c];
+        jn[lf] = have ? j : -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T x = A.ggw[(3 * r + a) * nc + c];
+            w[lf][a] = have ? x : T(0);
+        }
+    }
+    T uo[kMaxFaces][5];
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf) {
+        const int64_t j = jn[lf] >= 0 ? jn[lf] : c;  // boundary slots replaced below
+#pragma unroll
+        for (int v = 0; v < 5; ++v) uo[lf][v] = T(A.U[v * nc + j]);
+    }
+#pragma unroll
+    for (int lf = 0; lf < kMaxFaces; ++lf) {
+        if (jn[lf] < 0) {
+            // the symmetry ghost needs the unit normal: either orientation
+            const T wn = sqrt(w[lf][0] * w[lf][0] + w[lf][1] * w[lf][1] + w[lf][2] * w[lf][2]);
+            const T iw = wn > T(0) ? T(1) / wn : T(0);
+            const T nb[3] = {w[lf][0] * iw, w[lf][1] * iw, w[lf][2] * iw};
+            ghost_dev(A.bcd, -1 - jn[lf], u, nb, uo[lf]);
+        }
+        T Wo[4];
+        primw(uo[lf], Wo);
+#pragma unroll
+        for (int var = 0; var < 4; ++var) {
+            const T s2 = Wi[var] + Wo[var];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g[3 * var + a] += s2 * w[lf][a];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) A.gradW[k * nc + c] = g[k];
 }
 
 // ---------------------------------------------------------------- face flux
@@ -852,7 +953,8 @@ const T* arena_ptr(const Arena& a, size_t off) {
 
 template <class T>
 ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const double* U, const ucns_gate* gate,
-                             void* fs, uint8_t* flags, float* label) {
+                             void* fs, uint8_t* flags, float* label, void* gradW = nullptr,
+                             const ucns_phys* phys = nullptr, const ucns_bc* bc_device = nullptr) {
     ReconArgs<T> A;
     A.U = U;
     A.nc = m.nc;
@@ -886,7 +988,26 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.lam_c = T(m.lambda_c);
     A.eps = T(m.eps);
     A.gm1 = T(gm1);
+    A.gradW = static_cast<T*>(gradW);
+    A.ggw = arena_ptr<T>(ar, ar.ggw);
+    A.bcd = bc_device;
+    A.gM2 = phys ? T(phys->gamma * phys->mach * phys->mach) : T(0);
     return A;
+}
+
+// Cell gradients of W = (u, v, w, T) in a pass of their own.
+template <class T>
+void launch_gradients(const Mesh& m, const Arena& ar, const ucns_phys* phys, const ucns_bc* bc, const double* U,
+                      void* gradW, hipStream_t st) {
+    GradArgs<T> A{U, m.nc, arena_ptr<int32_t>(ar, ar.c2f), m.nfmax, arena_ptr<int32_t>(ar, ar.fcell),
+                  arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<double>(ar, ar.vol),
+                  arena_ptr<T>(ar, ar.glsq), static_cast<T*>(gradW)};
+    if (phys->grad == UCNS_GRAD_LSQ)
+        hipLaunchKernelGGL((gradients_kernel<T, true>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A,
+                           make_phys<T>(phys), make_bc<T>(bc));
+    else
+        hipLaunchKernelGGL((gradients_kernel<T, false>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A,
+                           make_phys<T>(phys), make_bc<T>(bc));
 }
 
 template <class T, int K>
@@ -894,7 +1015,19 @@ int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
     if (A.Q > face_qmax<K>()) return UCNS_EINVAL;
     if (recon_span_bytes(A.nc, int(sizeof(T)), K, A.NF) > kMaxDescriptorBytes) return UCNS_EINVAL;
     const dim3 grid(grid_for(A.nc)), block(kBlock);
-    if (A.mlp || A.gate) {
+    if (A.gradW) {
+        // the fused Green-Gauss gradients: P2 only (the P3 kernels have no
+        // scalar registers to spare for the extra arguments)
+        if constexpr (K == 9) {
+            if (A.label) return UCNS_EINVAL;
+            if (A.mlp || A.gate)
+                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true, true>), grid, block, 0, st, A);
+            else
+                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, false, true>), grid, block, 0, st, A);
+        } else {
+            return UCNS_EINVAL;
+        }
+    } else if (A.mlp || A.gate) {
         hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true>), grid, block, 0, st, A);
     } else {
         if (A.label)
@@ -923,13 +1056,16 @@ int launch_recon_p4(const ReconArgs<T>& A, hipStream_t st) {
     return UCNS_OK;
 }
 
+// gradW (optional, P2): the Green-Gauss gradients of U as well, formed by
+// the reconstruction kernel at the end of each cell.
 template <class T>
 int launch_recon(const Mesh& m, const Arena& ar, double gm1, const double* U, const ucns_gate* gate, void* fs,
-                 uint8_t* flags, float* label, hipStream_t st) {
-    const ReconArgs<T> A = make_recon_args<T>(m, ar, gm1, U, gate, fs, flags, label);
+                 uint8_t* flags, float* label, hipStream_t st, void* gradW = nullptr, const ucns_phys* phys = nullptr,
+                 const ucns_bc* bc_device = nullptr) {
+    const ReconArgs<T> A = make_recon_args<T>(m, ar, gm1, U, gate, fs, flags, label, gradW, phys, bc_device);
     if (m.K == 9) return launch_recon_k<T, 9>(A, st);
     if (m.K == 19) return launch_recon_k<T, 19>(A, st);
-    if (m.K == kP4K) return launch_recon_p4<T>(A, st);
+    if (m.K == kP4K && !gradW) return launch_recon_p4<T>(A, st);
     return UCNS_EINVAL;
 }
 
@@ -1166,8 +1302,11 @@ int ucns_dt(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, doubl
     return hip_check("ucns_dt");
 }
 
-int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
-                     const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream) {
+namespace {
+int reconstruct_impl(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc_device, const double* U,
+                     int precision,
+                     const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, void* gradW,
+                     ucns_stream stream, const char* name) {
     UCNS_REQUIRE(mesh && phys && U && face_state && flags, UCNS_EINVAL, "null argument");
     UCNS_REQUIRE(precision == UCNS_F64 || precision == UCNS_F32, UCNS_EINVAL, "bad precision");
     UCNS_REQUIRE(aligned(U) && aligned(face_state), UCNS_EINVAL, "device buffers must be 256-byte aligned");
@@ -1182,14 +1321,34 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
                  "labels are produced by the ungated reconstruction only");
 
     const double gm1 = phys->gamma - 1.0;
-    const int rc = precision == UCNS_F64 ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st)
-                                         : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st);
+    const int rc = precision == UCNS_F64
+                       ? launch_recon<double>(m, ar, gm1, U, gate, face_state, flags, label, st, gradW, phys, bc_device)
+                       : launch_recon<float>(m, ar, gm1, U, gate, face_state, flags, label, st, gradW, phys, bc_device);
     if (rc != UCNS_OK) {
         set_error("unsupported reconstruction order or face-point count, a gate at P4 (its network is trained "
                   "at P2), or a mesh beyond the 4 GiB span of one buffer descriptor (ucns_recon_span_bytes)");
         return rc;
     }
-    return hip_check("ucns_reconstruct");
+    return hip_check(name);
+}
+}  // namespace
+
+int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double* U, int precision,
+                     const ucns_gate* gate, void* face_state, uint8_t* flags, float* label, ucns_stream stream) {
+    return reconstruct_impl(mesh, phys, nullptr, U, precision, gate, face_state, flags, label, nullptr, stream,
+                            "ucns_reconstruct");
+}
+
+int ucns_reconstruct_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc_device,
+                               const double* U, int precision, const ucns_gate* gate, void* face_state,
+                               uint8_t* flags, void* gradW, ucns_stream stream) {
+    UCNS_REQUIRE(mesh && phys && gradW, UCNS_EINVAL, "null argument");
+    UCNS_REQUIRE(phys->grad == UCNS_GRAD_GREEN_GAUSS, UCNS_EINVAL,
+                 "the fused pass forms Green-Gauss gradients; least squares: ucns_gradients");
+    UCNS_REQUIRE(mesh->m->order == 2, UCNS_EINVAL, "the fused pass covers order 2; orders 3 and 4: ucns_gradients");
+    UCNS_REQUIRE(aligned(gradW), UCNS_EINVAL, "device buffers must be 256-byte aligned");
+    return reconstruct_impl(mesh, phys, bc_device, U, precision, gate, face_state, flags, nullptr, gradW, stream,
+                            "ucns_reconstruct_gradients");
 }
 
 int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const double* U, int precision,
@@ -1203,22 +1362,10 @@ int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* 
     const Arena& ar = m.arena[precision];
     UCNS_REQUIRE(ar.dev, UCNS_ESTATE, "mesh not uploaded for this precision");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    auto go = [&](auto zero) {
-        using T = decltype(zero);
-        GradArgs<T> A{U, m.nc, arena_ptr<int32_t>(ar, ar.c2f), m.nfmax, arena_ptr<int32_t>(ar, ar.fcell),
-                      arena_ptr<T>(ar, ar.fnrm), arena_ptr<T>(ar, ar.farea), arena_ptr<double>(ar, ar.vol),
-                      arena_ptr<T>(ar, ar.glsq), static_cast<T*>(gradW)};
-        if (phys->grad == UCNS_GRAD_LSQ)
-            hipLaunchKernelGGL((gradients_kernel<T, true>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A,
-                               make_phys<T>(phys), make_bc<T>(bc));
-        else
-            hipLaunchKernelGGL((gradients_kernel<T, false>), dim3(grid_for(m.nc)), dim3(kBlock), 0, st, A,
-                               make_phys<T>(phys), make_bc<T>(bc));
-    };
     if (precision == UCNS_F64)
-        go(double(0));
+        launch_gradients<double>(m, ar, phys, bc, U, gradW, st);
     else
-        go(float(0));
+        launch_gradients<float>(m, ar, phys, bc, U, gradW, st);
     return hip_check("ucns_gradients");
 }
 

@@ -31,6 +31,7 @@ EXPORTS = [
     "ucns_gate_mask", "ucns_mlp_train_step", "ucns_mlp_pack", "ucns_residual_rk_final",
     "ucns_residual_ssp54_stage", "ucns_mesh_gradient_weights", "ucns_recon_span_bytes",
     "ucns_check", "ucns_residual_rk_final_noalloc", "ucns_mesh_release", "ucns_diag_dissipation",
+    "ucns_reconstruct_gradients",
 ]
 
 
@@ -97,6 +98,7 @@ def lib():
         L.ucns_dt.argtypes = [vp, C.POINTER(Phys), vp, dbl, vp, vp, vp]
         L.ucns_reconstruct.argtypes = [vp, C.POINTER(Phys), vp, i32, vp, vp, vp, vp, vp]
         L.ucns_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, i32, vp, vp]
+        L.ucns_reconstruct_gradients.argtypes = [vp, C.POINTER(Phys), vp, vp, i32, vp, vp, vp, vp, vp]
         L.ucns_face_flux.argtypes = [vp, C.POINTER(Phys), vp, vp, vp, vp, i32, vp, vp]
         L.ucns_residual.argtypes = [vp, vp, i32, vp, vp]
         L.ucns_rk_stage.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -316,6 +318,30 @@ def reconstruct(mesh, ph, U, precision, face_state, gate_mask=None, flags=None, 
                                  _dp(face_state), _dp(flags), _dp(label), _stream(stream)))
 
 
+def bc_device(bcs, device="cuda"):
+    """A boundary table (BC, or None for all transmissive) copied to device
+    memory, for reconstruct_gradients."""
+    import torch
+
+    b = bc() if bcs is None else bcs
+    raw = torch.frombuffer(bytearray(bytes(b)), dtype=torch.uint8)
+    return raw.to(device)
+
+
+def reconstruct_gradients(mesh, ph, bc_dev, U, precision, face_state, flags, gradW, gate_mask=None, mlp_image=None,
+                          mask_out=None, stream=None):
+    """reconstruct() and the Green-Gauss gradients() of the same U in one
+    pass (order 2); bc_dev from bc_device()."""
+    g = None
+    if gate_mask is not None or mlp_image is not None:
+        g = Gate(None if gate_mask is None else C.c_void_p(gate_mask.data_ptr()),
+                 None if mlp_image is None else C.c_void_p(mlp_image.data_ptr()),
+                 None if mask_out is None else C.c_void_p(mask_out.data_ptr()))
+    check(lib().ucns_reconstruct_gradients(mesh.h, C.byref(ph), _dp(bc_dev), _dp(U), precision,
+                                           None if g is None else C.byref(g), _dp(face_state), _dp(flags),
+                                           _dp(gradW), _stream(stream)))
+
+
 def gate_features(mesh, U, precision, out, stream=None):
     check(lib().ucns_gate_features(mesh.h, _dp(U), precision, _dp(out), _stream(stream)))
 
@@ -420,6 +446,11 @@ class Solver:
         self.integrator = integrator
         self.W = (torch.empty((4, 5, mesh.n_cell), dtype=torch.float64, device=device)
                   if integrator == "ssp54" else None)
+        # viscous P2 with Green-Gauss gradients: one pass forms the point
+        # states and the gradients (the boundary table then lives on the device)
+        self.fused = (bool(ph.viscous) and ph.grad == GRADIENTS["green_gauss"] and mesh.order == 2
+                      and not label)
+        self.bc_dev = bc_device(bcs, device) if self.fused else None
         # a list here collects, for every reconstruction call, a (start, end)
         # HIP-event pair recorded on the launch stream and, with the network,
         # the call's count of cells taken as smooth (a device scalar); timing only
@@ -434,13 +465,17 @@ class Solver:
             s = torch.cuda.current_stream()
             ev.append([torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), None])
             ev[-1][0].record(s)
-        reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags, ws.label,
-                    mlp_image=self.mlp_image, mask_out=ws.mask_out)
+        if self.fused:
+            reconstruct_gradients(self.mesh, self.ph, self.bc_dev, U, self.precision, ws.face_state, ws.flags,
+                                  ws.gradW, self.gate_mask, mlp_image=self.mlp_image, mask_out=ws.mask_out)
+        else:
+            reconstruct(self.mesh, self.ph, U, self.precision, ws.face_state, self.gate_mask, ws.flags, ws.label,
+                        mlp_image=self.mlp_image, mask_out=ws.mask_out)
         if ev is not None:
             ev[-1][1].record(s)
             if ws.mask_out is not None:
                 ev[-1][2] = ws.mask_out.sum()
-        if self.ph.viscous:
+        if self.ph.viscous and not self.fused:
             gradients(self.mesh, self.ph, self.bcs, U, self.precision, ws.gradW)
         face_flux(self.mesh, self.ph, self.bcs, U, ws.face_state, ws.gradW, self.precision, ws.face_flux)
 

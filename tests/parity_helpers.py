@@ -53,9 +53,10 @@ def face_major(lm, fs_cells):
     return out
 
 
-def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
+def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda", fused=False):
     """One residual evaluation on the GPU; returns host copies of
-    (face_state [nf,2,Q,5], gradW [12,nc] or None, face_flux [nf,5], R [5,nc], flags)."""
+    (face_state [nf,2,Q,5], gradW [12,nc] or None, face_flux [nf,5], R [5,nc], flags).
+    fused: the point states and the gradients from the one-pass call."""
     import torch
 
     if precision not in lm.arenas:
@@ -64,9 +65,12 @@ def gpu_stage(lm, ph, U_np, precision, bcs=None, gate_mask=None, device="cuda"):
     fs, ff, gw, R = lib_arrays(lm, precision, device)
     flags = torch.zeros(lm.n_cell, dtype=torch.uint8, device=device)
     gm = None if gate_mask is None else torch.tensor(gate_mask, dtype=torch.uint8, device=device)
-    ucns.reconstruct(lm, ph, U, precision, fs, gm, flags)
-    if ph.viscous:
-        ucns.gradients(lm, ph, bcs, U, precision, gw)
+    if fused:
+        ucns.reconstruct_gradients(lm, ph, ucns.bc_device(bcs, device), U, precision, fs, flags, gw, gm)
+    else:
+        ucns.reconstruct(lm, ph, U, precision, fs, gm, flags)
+        if ph.viscous:
+            ucns.gradients(lm, ph, bcs, U, precision, gw)
     ucns.face_flux(lm, ph, bcs, U, fs, gw if ph.viscous else None, precision, ff)
     ucns.residual(lm, ff, precision, R)
     torch.cuda.synchronize()

@@ -32,6 +32,14 @@ def test_reconstruction_bytes_per_cell_hex_p2(hex_mesh):
     # indicator matrix; the network adds its inputs and the mask
     lin = bench.recon_bytes_per_cell(lm, ucns.F32, linear=True, gate=True)
     assert lin == 4 * 315 + 4 * 26 + 6 + 1 + 40 + 4 * 120 + 1 + (4 * 6 + 3 * 6 * 4 + 4 + 2) == 1994
+    # the fused Green-Gauss gradients: 6 x 3 slot weights and 12 values
+    # written, plus the 6 neighbour ids when the gate has not read them
+    assert bench.recon_bytes_per_cell(lm, ucns.F32, linear=True, gate=True, grad=True) == 1994 + 4 * 18 + 4 * 12
+    assert bench.recon_bytes_per_cell(lm, ucns.F64, grad=True) == 5504 + 4 * 6 + 8 * 18 + 8 * 12
+    # and the separate gradient pass drops out of the stage's bytes
+    full = bench.step_bytes_per_cell(lm, ucns.F64, recon=5504)
+    fused = bench.step_bytes_per_cell(lm, ucns.F64, recon=5504 + 4 * 6 + 8 * 18 + 8 * 12, fused=True)
+    assert full - fused == (40 + 4 * 6 + 8 * 12 + 3 * (8 + 4 * 8)) - (4 * 6 + 8 * 18 + 8 * 12)
 
 
 def test_traffic_records_name_the_timed_kernels():
@@ -42,5 +50,5 @@ def test_traffic_records_name_the_timed_kernels():
             text = f.read()
         i = text.index("```json")
         rec = json.loads(text[i + 7:text.index("```", i + 7)])
-        for k in bench.RECON_KERNELS[head].split("|"):
+        for k in bench.recon_kernels(head, fused=True).split("|"):
             assert k in rec["kernel"], (head, k)

@@ -154,6 +154,48 @@ def test_stage_intermediates_fp64(torch_cuda, name):
     assert err_R < (tol / 10 if name in TOL_CASE else 1e-13), err_R
 
 
+@pytest.mark.parametrize("name", ["hex7_p2_hllc_ns", "mixed_bl_ns", "tet_slab_sym_ns"])
+def test_fused_gradients_fp64(torch_cuda, name):
+    """The one-pass reconstruction + Green-Gauss gradients: point states and
+    flags bitwise those of the two separate calls, gradients within rounding
+    of theirs (each slot's weight n|S|/(2|V|) is stored, not formed) and
+    within the stage tolerance of the oracle; no-slip wall, Dirichlet,
+    transmissive and symmetry ghosts among the cases."""
+    print(f"[gpu] fused gradients {name}", flush=True)
+    m, order, ph, U, bcs = _setup(name)
+    lm = ucns.Mesh(m, order=order)
+    fs, gw, _, _, flags = gpu_stage(lm, ph, U, ucns.F64, bcs)
+    fs2, gw2, ff2, R2, flags2 = gpu_stage(lm, ph, U, ucns.F64, bcs, fused=True)
+    assert np.array_equal(fs, fs2, equal_nan=True)
+    assert np.array_equal(flags, flags2)
+    err_sep = np.abs(gw2 - gw).max() / np.abs(gw).max()
+    om = oracle.OracleMesh(m, order=order)
+    og = om.gradients(U, as_oracle_phys(ph), as_oracle_bc(bcs))
+    err_o = np.abs(gw2 - og).max() / np.abs(og).max()
+    print(f"[gpu]   gradW vs separate {err_sep:.2e}, vs oracle {err_o:.2e}", flush=True)
+    assert err_sep < 1e-13, err_sep
+    assert err_o < TOL_CASE.get(name, TOL_STAGE), err_o
+
+
+def test_fused_gradients_fp32_gate(torch_cuda):
+    """FP32 with a gate mask (every third cell troubled): the one-pass call's
+    point states and flags equal the separate calls' bit for bit, its
+    gradients agree to FP32 rounding."""
+    print("[gpu] fused gradients fp32 gate", flush=True)
+    m = inputs.periodic_hex_mesh(12)
+    U = inputs.tgv_initial(m)
+    ph = ucns.phys(flux="hllc", viscous=True)
+    lm = ucns.Mesh(m, order=2)
+    mask = (np.arange(lm.n_cell) % 3 != 0).astype(np.uint8)
+    fs, gw, _, _, flags = gpu_stage(lm, ph, U, ucns.F32, None, gate_mask=mask)
+    fs2, gw2, _, _, flags2 = gpu_stage(lm, ph, U, ucns.F32, None, gate_mask=mask, fused=True)
+    assert np.array_equal(fs, fs2, equal_nan=True)
+    assert np.array_equal(flags, flags2)
+    err = np.abs(gw2 - gw).max() / np.abs(gw).max()
+    print(f"[gpu]   gradW vs separate {err:.2e}", flush=True)
+    assert err < 1e-5, err
+
+
 @pytest.mark.parametrize("name,steps", [("hex16_p2_rusanov", 10), ("hex7_p2_hllc_ns", 10), ("tet4_p2_hllc", 5),
                                         ("tet3_p3_hllc", 3), ("hex98_p4_hllc", 10), ("tet_shock_box", 5),
                                         ("mixed_bl_ns", 5),
