@@ -501,32 +501,50 @@ struct FluxArgs {
 // Viscous flux F_v . n with the penalised interface gradient
 // grad W_f = (grad W_L + grad W_R)/2 + (4/3)/L_int (W_R - W_L) (x) n on
 // W = (u, v, w, T); G0 is the face's mean cell gradient, pen = (4/3)/L_int.
+// The stress and heat flux are linear in grad W_f, so they split into the
+// face's constant part from G0 (formed once per face) and the penalty part,
+// which for the rank-one dW (x) n with |n| = 1 reduces to
+//   tau_pen n = mu pen (dW_u + (1/3)(dW_u . n) n),   q_pen = kappa pen dW_T.
 template <class T>
-__device__ void viscous_flux(const PhysT<T>& P, const Prim<T>& L, const Prim<T>& R, const T* G0, const T* n, T pen,
-                             T* Fv) {
-    T dW[4];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) dW[a] = R.u[a] - L.u[a];
-    dW[3] = P.gM2 * (R.p * R.ir - L.p * L.ir);
-    T G[4][3];
-#pragma unroll
-    for (int var = 0; var < 4; ++var)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) G[var][a] = G0[3 * var + a] + pen * dW[var] * n[a];
-    const T div = G[0][0] + G[1][1] + G[2][2];
-    T e = T(0);
-    Fv[0] = T(0);
+struct ViscFace {
+    T t0[3], q0;  // mu (G0 + G0^T - (2/3) div G0 I) n and kappa G0_T . n
+    T mp, kp;     // mu pen, kappa pen
+};
+
+template <class T>
+__device__ __forceinline__ ViscFace<T> viscous_face(const PhysT<T>& P, const T* G0, const T* n, T pen) {
+    ViscFace<T> V;
+    const T div = G0[0] + G0[4] + G0[8];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         T t = T(0);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) t += (G[i][j] + G[j][i] - (i == j ? T(2.0 / 3.0) * div : T(0))) * n[j];
-        t *= P.mu;
+        for (int j = 0; j < 3; ++j) t += (G0[3 * i + j] + G0[3 * j + i]) * n[j];
+        V.t0[i] = P.mu * (t - T(2.0 / 3.0) * div * n[i]);
+    }
+    V.q0 = P.kappa * (G0[9] * n[0] + G0[10] * n[1] + G0[11] * n[2]);
+    V.mp = P.mu * pen;
+    V.kp = P.kappa * pen;
+    return V;
+}
+
+// F_v . n at one Gauss point (the work term with the mean velocity).
+template <class T>
+__device__ __forceinline__ void viscous_flux(const PhysT<T>& P, const ViscFace<T>& V, const Prim<T>& L,
+                                             const Prim<T>& R, const T* n, T* Fv) {
+    T dW[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dW[a] = R.u[a] - L.u[a];
+    const T dT = P.gM2 * (R.p * R.ir - L.p * L.ir);
+    const T dn3 = T(1.0 / 3.0) * (dW[0] * n[0] + dW[1] * n[1] + dW[2] * n[2]);
+    T e = V.q0 + V.kp * dT;
+    Fv[0] = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T t = V.t0[i] + V.mp * (dW[i] + dn3 * n[i]);
         Fv[1 + i] = t;
         e += T(0.5) * (L.u[i] + R.u[i]) * t;
     }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) e += P.kappa * G[3][j] * n[j];
     Fv[4] = e;
 }
 
@@ -581,6 +599,7 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         for (int v = 0; v < 5; ++v) avg[v] = T(A.U[v * nc + cL]);
     }
     T G0[12], pen = T(0);
+    ViscFace<T> VF{};
     if (P.viscous) {
         // a boundary face takes its own cell's gradient on both sides; both
         // loads are unconditional (a load under a lane condition would wait)
@@ -590,6 +609,7 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
         const T dx = A.fdc[3 * f], dy = A.fdc[3 * f + 1], dz = A.fdc[3 * f + 2];
         pen = T(4.0 / 3.0) / sqrt(dx * dx + dy * dy + dz * dz);
         if (cR < 0 && bc_kind(B, -1 - cR) == UCNS_BC_SYMMETRY) symmetry_gradient(G0, n);
+        VF = viscous_face(P, G0, n, pen);
     }
     T F[5] = {T(0), T(0), T(0), T(0), T(0)};
     // FP32 loads the next point's two states while it evaluates this one's
@@ -626,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
             rusanov_flux(qL, qR, uL, uR, n, Fq);
         if (P.viscous) {
             T Fv[5];
-            viscous_flux(P, qL, qR, G0, n, pen, Fv);
+            viscous_flux(P, VF, qL, qR, n, Fv);
 #pragma unroll
             for (int v = 0; v < 5; ++v) Fq[v] -= Fv[v];
         }
