@@ -28,7 +28,9 @@
  *    reconstruction, gradients and fluxes in FP32 with FP32 accumulation;
  *    state, residual and RK update stay FP64).
  *  - Face states: each cell's point values at its own face quadrature
- *    points, [NFMAX][QMAX][5][n_cell] (cell fastest) in the precision's type;
+ *    points in the precision's type, one row per point slot (lf, q):
+ *    [NFMAX][QMAX][n_pad][5], n_pad = n_cell rounded up to a multiple of 64
+ *    (ucns_workspace_elems counts the padding);
  *    slot (lf, q) holds the value at point q of local face lf, the points
  *    numbered in the owner's order on both sides of a face (owner = lower
  *    cell id); face fluxes [n_face][5];

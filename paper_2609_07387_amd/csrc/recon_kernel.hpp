@@ -365,18 +365,36 @@ __device__ __forceinline__ void basis_at(T x, T y, T z, const T* pm, T* ph) {
 // quadrilateral, 3 on a triangle); the launcher rejects meshes beyond it.
 template <int K>
 constexpr int face_qmax() { return K <= 9 ? 4 : 9; }
+// Points of one face staged together in LDS before their stores (P2: a whole
+// face, so one LDS round trip per face; P3, up to 9 points: one at a time).
+template <int K>
+constexpr int stage_points() { return face_qmax<K>() <= 4 ? face_qmax<K>() : 1; }
 
-// Point values at the cell's face quadrature points (step vii) from the
-// coefficients a (first order when mode == 2), stored in the cell-fastest
-// slots [lf][q][v][cell] so that a wave's stores are contiguous; returns
-// whether density and pressure are positive at all of them.
-template <class T, int K>
+// Point values U_i + Phi(x_q) . a at the cell's face points (step vii) from
+// the coefficients a (first order when mode == 2); returns whether density and
+// pressure are positive at all of them.  Point states are stored per point
+// slot (lf, q) as rows of [cell][5] (cells padded to whole 64-cell tiles), so
+// that the flux kernel reads a cell's five values from one run.
+// STAGE, in a wave whose 64 cells all exist (all its lanes here): each
+// point's 64 x 5 values pass through the wave's LDS (320 values per point,
+// stage_points<K>() points at a time) and leave as five contiguous 64-value
+// stores; a lane without the point stores a value into its unused slot.
+// Otherwise (the positivity fallback, the mesh's last, partial wave) each
+// lane stores its own points' five values.
+template <class T, int K, bool STAGE>
 __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, const double* ui, int mode,
-                                            const T a[K][5]) {
+                                            const T a[K][5], T* stage = nullptr) {
     const int64_t nc = A.nc;
     const int NF = A.NF, Q = A.Q;
     const uint32_t rowT = uint32_t(nc) * uint32_t(sizeof(T));
     const uint32_t cT = uint32_t(c) * uint32_t(sizeof(T));
+    const int64_t ncp = fs_cells_padded(nc);
+    const int lane = int(threadIdx.x & 63u);
+    // element offsets (bytes) in a slot row: this lane's own cell, and this
+    // lane's share of its wave's staged run
+    const uint32_t cF = 5u * cT;
+    const uint32_t wF = (uint32_t(c - lane) * 5u + uint32_t(lane)) * uint32_t(sizeof(T));
+    const bool staged = STAGE && c - lane + 64 <= nc;  // wave-uniform
     T pm[K];
     {
         const auto rM = row_rsrc(A.pmean, 0, nc, K);
@@ -385,9 +403,9 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
     }
     bool ok = true;
     // The loops are wave-uniform (every lane walks all NF x Q slots); a lane
-    // skips the points its cell does not have (nq of the slot).  The offset
-    // of point (lf, q) in rows ((lf Q + q) 3 + d), its state in rows
-    // ((lf Q + q) 5 + v).  The next face's offsets and point count load while
+    // without the point (nq of the slot) skips it, or, staged, forms a value
+    // that lands in its unused slot.  The offset of point (lf, q) in rows
+    // ((lf Q + q) 3 + d).  The next face's offsets and point count load while
     // this face's points are formed, so only the first face waits on memory.
     constexpr int QM = face_qmax<K>();
     auto load_face = [&](int lf, T (&x)[QM][3]) {
@@ -406,7 +424,8 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
         const int nqn = lf + 1 < NF ? load_face(lf + 1, xn) : 0;
 #pragma unroll
         for (int q = 0; q < QM; ++q) {
-            if (q >= nq) continue;
+            if (q >= Q) continue;  // wave-uniform
+            if (!staged && q >= nq) continue;
             T d[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) d[v] = T(0);
@@ -422,10 +441,28 @@ __device__ __forceinline__ bool face_values(const ReconArgs<T>& A, int64_t c, co
 #pragma unroll
             for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(d[v]));
             const T p = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
-            ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
-            const auto rF = row_rsrc(A.fs, (int64_t(lf) * Q + q) * 5, nc, 5);
+            if (q < nq) ok = ok && (val[0] > T(1e-10)) && (p > T(1e-10));
+            if (staged) {
+                constexpr int QB = stage_points<K>();
+                const int sq = q % QB;  // a constant once the point loop is unrolled
 #pragma unroll
-            for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cT, uint32_t(v) * rowT);
+                for (int v = 0; v < 5; ++v) stage[sq * 320 + lane * 5 + v] = val[v];
+                if (sq == QB - 1 || q == Q - 1) {  // wave-uniform: flush the batch
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int b = 0; b <= sq; ++b) {
+                        const auto rF = row_rsrc(A.fs, (int64_t(lf) * Q + q - sq + b) * 5, ncp, 5);
+#pragma unroll
+                        for (int k = 0; k < 5; ++k)
+                            bst<T>(stage[b * 320 + k * 64 + lane], rF, wF, uint32_t(k) * 64u * uint32_t(sizeof(T)));
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            } else {
+                const auto rF = row_rsrc(A.fs, (int64_t(lf) * Q + q) * 5, ncp, 5);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) bst<T>(val[v], rF, cF, uint32_t(v) * uint32_t(sizeof(T)));
+            }
         }
 #pragma unroll
         for (int q = 0; q < QM; ++q)
@@ -945,15 +982,17 @@ __device__ __forceinline__ void dir_blend_stencils(const ReconArgs<float>& A, ui
     if (mine) blend_finish<T, K, false>(B, nd, lab, a);
 }
 
-// One lane per cell: steps (iii)-(vi) for mode 1, then (vii) for any mode.
-template <class T, int K, bool LABEL>
+// One lane per cell: steps (iii)-(vi) for mode 1, then (vii) for any mode
+// (STAGE: the main pass; the positivity fallback runs on scattered cells and
+// stores its own points).
+template <class T, int K, bool LABEL, bool STAGE = false>
 __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, const double* ui, int mode, float& lab,
-                                           T a[K][5]) {
+                                           T a[K][5], T* stage = nullptr) {
     if (mode == 1) {
         const int nd = A.ndir[c];
         if (nd > 0) dir_blend_lane<T, K, LABEL>(A, c, ui, nd, lab, a);
     }
-    return face_values<T, K>(A, c, ui, mode, a);
+    return face_values<T, K, STAGE>(A, c, ui, mode, a, stage);
 }
 
 // Main pass without a gate (full CWENOZ everywhere), or with a gate (a mask,
@@ -977,7 +1016,8 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 // gradient of W as well (the positivity fallback changes point states only,
 // never the cell averages the gradient is taken from).
 template <class T, int K, bool LABEL, bool GATE, bool GRAD = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GATE && sizeof(T) == 4 && K == 9 ? 3 : 1)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    K == 9 && (sizeof(T) == 4 ? GATE : !GATE && !LABEL) ? (sizeof(T) == 4 ? 3 : 2) : 1)))
 void reconstruct_kernel(ReconArgs<T> A) {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     const bool valid = c < A.nc;
@@ -991,7 +1031,9 @@ void reconstruct_kernel(ReconArgs<T> A) {
         // per wave: the network's scratch, then (FP32 P2) the stash of
         // dir_blend_stencils
         constexpr int kStash = sizeof(T) == 4 && K == 9 ? K * 5 * 64 * 4 : 0;
-        constexpr int kWaveLds = sizeof(MlpWaveLds) > kStash ? int(sizeof(MlpWaveLds)) : kStash;
+        constexpr int kStage = stage_points<K>() * 320 * int(sizeof(T));  // then the point-state staging
+        constexpr int kWaveLds0 = sizeof(MlpWaveLds) > kStash ? int(sizeof(MlpWaveLds)) : kStash;
+        constexpr int kWaveLds = kWaveLds0 > kStage ? kWaveLds0 : kStage;
         __shared__ __attribute__((aligned(16))) unsigned char lds[kBlock / 64][kWaveLds];
         unsigned char* wl = lds[threadIdx.x >> 6];
         if (A.mlp) {
@@ -1037,16 +1079,18 @@ void reconstruct_kernel(ReconArgs<T> A) {
         }
         if (!valid) return;
         if (A.mask_out) A.mask_out[c] = mode == 0 ? 1 : 0;
-        const bool ok = face_values<T, K>(A, c, ui, 0, a);
+        // the network's LDS row is free again: it stages the point states
+        const bool ok = face_values<T, K, true>(A, c, ui, 0, a, reinterpret_cast<T*>(wl));
         A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
         if constexpr (GRAD) cell_gradient_gg<T>(A, c, ui);
     } else {
+        __shared__ T stage[kBlock / 64][stage_points<K>() * 320];
         if (!valid) return;
 #pragma unroll
         for (int v = 0; v < 5; ++v) ui[v] = A.U[v * A.nc + c];
         central_coeffs<T, K>(A, c, ui, a, nullptr, MCw);
         float lab = 0.f;
-        const bool ok = recon_cell<T, K, LABEL>(A, c, ui, 1, lab, a);
+        const bool ok = recon_cell<T, K, LABEL, true>(A, c, ui, 1, lab, a, stage[threadIdx.x >> 6]);
         A.flags[c] = uint8_t(ok ? 0 : 0x80);
         if constexpr (LABEL) A.label[c] = lab;
         if constexpr (GRAD) cell_gradient_gg<T>(A, c, ui);

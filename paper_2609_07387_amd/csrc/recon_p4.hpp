@@ -458,10 +458,10 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
         T val[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) val[v] = T(ui[v] + double(quad_sum(d[v])));
-        T* out = A.fs + int64_t(p) * 5 * nc + c;
+        T* out = A.fs + (int64_t(p) * fs_cells_padded(nc) + c) * 5;
         if (valid) {
-            out[int64_t(h) * nc] = h == 0 ? val[0] : h == 1 ? val[1] : h == 2 ? val[2] : val[3];
-            if (h == 0) out[4 * nc] = val[4];
+            out[h] = h == 0 ? val[0] : h == 1 ? val[1] : h == 2 ? val[2] : val[3];
+            if (h == 0) out[4] = val[4];
         }
         const T pr = A.gm1 * (val[4] - T(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
         ok = ok && (val[0] > T(1e-10)) && (pr > T(1e-10));
@@ -501,7 +501,8 @@ __global__ __launch_bounds__(kBlock) void reconstruct_p4_fallback_kernel(ReconAr
     for (int lf = 0; lf < A.NF; ++lf) {
         const int nq = A.cnq[int64_t(lf) * nc + c];
         for (int q = 0; q < nq; ++q)
-            for (int v = 0; v < 5; ++v) A.fs[((int64_t(lf) * A.Q + q) * 5 + v) * nc + c] = T(A.U[v * nc + c]);
+            for (int v = 0; v < 5; ++v)
+                A.fs[((int64_t(lf) * A.Q + q) * fs_cells_padded(nc) + c) * 5 + v] = T(A.U[v * nc + c]);
     }
     A.flags[c] = uint8_t((fl & 0x7f) | 4);
 }

@@ -25,21 +25,29 @@ constexpr int kNumVar = 5;
 
 void set_error(const std::string& msg);
 
+// Point states are stored per point slot (lf, q) as a row of [cell][5]
+// values, the cell count padded to whole 64-cell tiles (a wave stages its 64
+// cells' values and writes the tile's 320 values as five contiguous runs).
+constexpr int64_t kFsTile = 64;
+constexpr int64_t fs_cells_padded(int64_t nc) { return (nc + kFsTile - 1) / kFsTile * kFsTile; }
+
 // Largest byte span one buffer descriptor of the reconstruction kernels
 // covers (offsets inside a descriptor are 32-bit, so it must stay below
 // 4 GiB): the state U (5 rows of FP64), a member's or the basis means' K
 // operator rows, or the NF rows of face-neighbour ids.  Every other stream
 // (stencil ids, face-point offsets, directional operators, point states)
 // takes its row index in the descriptor's 64-bit base and spans at most
-// 5 rows of the precision's type.
+// 5 rows of the precision's type (a point-state slot: 5 values per cell of
+// the padded count).
 inline uint64_t recon_span_bytes(int64_t nc, int elem_bytes, int K, int NF) {
     uint64_t per_cell = 40;
     per_cell = std::max<uint64_t>(per_cell, uint64_t(K) * uint64_t(elem_bytes));
     per_cell = std::max<uint64_t>(per_cell, uint64_t(NF) * 4u);
-    per_cell = std::max<uint64_t>(per_cell, uint64_t(5) * uint64_t(elem_bytes));
-    return per_cell * uint64_t(nc);
+    return std::max<uint64_t>(per_cell * uint64_t(nc),
+                              uint64_t(5) * uint64_t(elem_bytes) * uint64_t(fs_cells_padded(nc)));
 }
 constexpr uint64_t kMaxDescriptorBytes = 0xffffffffull;
+
 
 // Offsets (bytes) of every array inside one precision's device arena.
 struct Arena {

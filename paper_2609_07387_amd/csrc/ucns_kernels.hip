@@ -585,14 +585,15 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
     const int nq = A.fnq[f];
     const T n[3] = {A.fnrm[3 * f], A.fnrm[3 * f + 1], A.fnrm[3 * f + 2]};
     const int32_t cL = A.fcell[2 * f], cR = A.fcell[2 * f + 1];
-    // point states in the cell-fastest slots [lf][q][v][cell] of each side
+    // point states in the slot rows [lf][q][cell][v] of each side
     // both sides' local face indices in one 16-bit load (the right one is
     // needed only off the boundary, and a load under that lane condition
     // would wait)
     const uint32_t lf2 = *reinterpret_cast<const uint16_t*>(A.flf + 2 * f);
     const int lfL = int(lf2 & 0xffu), lfR = int(lf2 >> 8);
-    const T* pL = A.fs + int64_t(lfL) * Q * 5 * nc + cL;
-    const T* pR = cR >= 0 ? A.fs + int64_t(lfR) * Q * 5 * nc + cR : pL;
+    const int64_t slot = 5 * fs_cells_padded(nc);  // values per point slot
+    const T* pL = A.fs + int64_t(lfL) * Q * slot + int64_t(cL) * 5;
+    const T* pR = cR >= 0 ? A.fs + int64_t(lfR) * Q * slot + int64_t(cR) * 5 : pL;
     T avg[5];
     if (cR < 0) {
 #pragma unroll
@@ -619,8 +620,8 @@ __global__ __launch_bounds__(kBlock) void face_flux_kernel(FluxArgs<T> A, PhysT<
     auto load_point = [&](int q, T* uL, T* uR) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            uL[v] = pL[int64_t(q * 5 + v) * nc];
-            uR[v] = pR[int64_t(q * 5 + v) * nc];
+            uL[v] = pL[int64_t(q) * slot + v];
+            uR[v] = pR[int64_t(q) * slot + v];
         }
     };
     T uLn[5], uRn[5];
@@ -1300,7 +1301,7 @@ int ucns_workspace_elems(const ucns_mesh* mesh, int64_t* face_state, int64_t* fa
                          int64_t* reduce_scratch) {
     UCNS_REQUIRE(mesh, UCNS_EINVAL, "null argument");
     const Mesh& m = *mesh->m;
-    if (face_state) *face_state = int64_t(m.nfmax) * m.qmax * 5 * m.nc;
+    if (face_state) *face_state = int64_t(m.nfmax) * m.qmax * 5 * fs_cells_padded(m.nc);
     if (face_flux) *face_flux = m.nf * 5;
     if (gradW) *gradW = 12 * m.nc;
     if (reduce_scratch) *reduce_scratch = std::max<int64_t>(kRedBlocks, 2 * int64_t(grid_for(m.nc)));

@@ -39,12 +39,22 @@ def lib_arrays(lm, precision, device="cuda"):
     return fs, ff, gw, R
 
 
-def face_major(lm, fs_cells):
-    """Library face states [NFMAX][Q][5][n_cell] (cell fastest) as
-    [n_face][2][Q][5] (NaN where a face has no such side)."""
-    c2f, _, _, _ = lm.faces()
+def point_states(lm, fs):
+    """Library point states [NFMAX][Q][n_pad][5] (one row per point slot, the
+    cell count padded to whole 64-cell tiles) as [NFMAX][Q][5][n_cell]; numpy
+    or torch."""
     NF, Q, nc = lm.nfmax, lm.qmax, lm.n_cell
-    fsc = np.asarray(fs_cells).reshape(NF, Q, 5, nc)
+    npad = -(-nc // 64) * 64
+    g = fs.reshape(NF, Q, npad, 5)[:, :, :nc, :]
+    return g.transpose(2, 3) if hasattr(g, "contiguous") else g.transpose(0, 1, 3, 2)
+
+
+def face_major(lm, fs_cells):
+    """Library point states as [n_face][2][Q][5] (NaN where a face has no such
+    side)."""
+    c2f, _, _, _ = lm.faces()
+    NF, Q = lm.nfmax, lm.qmax
+    fsc = point_states(lm, np.asarray(fs_cells))
     out = np.full((lm.n_face, 2, Q, 5), np.nan)
     for lf in range(NF):
         f2 = c2f[:, lf].astype(np.int64)

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2609_07387_amd import inputs, ucns
-from parity_helpers import as_oracle_phys
+from parity_helpers import as_oracle_phys, point_states
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +50,7 @@ def test_large_hex_mesh_fp64_point_states_sampled():
     ucns.reconstruct(lm, ph, Ud, ucns.F64, fs, None, flags)
     torch.cuda.synchronize()
     NF, Q = lm.nfmax, lm.qmax
-    g = fs.view(NF, Q, 5, nc)[:, :, :, torch.as_tensor(sample, device="cuda")].cpu().numpy()  # [NF][Q][5][s]
+    g = point_states(lm, fs)[:, :, :, torch.as_tensor(sample, device="cuda")].cpu().numpy()  # [NF][Q][5][s]
     del fs, Ud
     lm.release()
     torch.cuda.empty_cache()

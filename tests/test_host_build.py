@@ -246,3 +246,27 @@ def test_host_build_matches_oracle_stencil_factor_3():
         # operator columns follow each code's own member order
         pl, po = np.argsort(lc), np.argsort(oc)
         assert np.abs(lo["Bc"][:, pl] - oo["Bc"][:, po]).max() < 1e-12 * np.abs(oo["Bc"]).max()
+
+
+def test_point_state_layout_helper():
+    """The test-side view of the point states ([slot][cell][5], the cell count
+    padded to whole 64-cell tiles, as the kernels index them) against the
+    element-by-element formula, on a cell count with a ragged last tile."""
+    from types import SimpleNamespace
+
+    from parity_helpers import point_states
+
+    _lib_or_skip()
+    # the workspace holds whole tiles: 125 cells take two tiles
+    assert ucns.Mesh(inputs.periodic_hex_mesh(5)).n_face_state == 6 * 4 * 5 * 128
+    lm = SimpleNamespace(nfmax=3, qmax=2, n_cell=150)
+    nt = 3
+    fs = np.full(lm.nfmax * lm.qmax * 5 * nt * 64, np.nan)
+    for s in range(lm.nfmax * lm.qmax):
+        for v in range(5):
+            for c in range(lm.n_cell):
+                fs[(s * nt * 64 + c) * 5 + v] = 1000 * s + 100 * v + c / 1000
+    g = point_states(lm, fs)
+    assert g.shape == (3, 2, 5, 150)
+    lf, q, v, c = np.meshgrid(range(3), range(2), range(5), range(150), indexing="ij")
+    assert np.array_equal(g, 1000 * (lf * 2 + q) + 100 * v + c / 1000)
