@@ -421,7 +421,7 @@ void reconstruct_p4_kernel(ReconArgs<T> A) {
         }
     }
 
-    // (vi) point values at the cell's face points, slots [lf][q][v][cell]:
+    // (vi) point values at the cell's face points, slot rows [lf][q][cell][v]:
     // lane h writes variable h, lane 0 also variable 4
     T pm[NT];
 #pragma unroll
