@@ -366,9 +366,10 @@ __device__ __forceinline__ void basis_at(T x, T y, T z, const T* pm, T* ph) {
 template <int K>
 constexpr int face_qmax() { return K <= 9 ? 4 : 9; }
 // Points of one face staged together in LDS before their stores (P2: a whole
-// face, so one LDS round trip per face; P3, up to 9 points: one at a time).
+// face, so one LDS round trip per face; P3: three at a time, a whole
+// triangle).
 template <int K>
-constexpr int stage_points() { return face_qmax<K>() <= 4 ? face_qmax<K>() : 1; }
+constexpr int stage_points() { return face_qmax<K>() <= 4 ? face_qmax<K>() : 3; }
 
 // Point values U_i + Phi(x_q) . a at the cell's face points (step vii) from
 // the coefficients a (first order when mode == 2); returns whether density and
