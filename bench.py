@@ -29,12 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # The dominant step is the reconstruction: one ucns_reconstruct call, timed
 # as a whole with HIP events; its kernels, and the record of their measured
 # HBM bytes per call (rocprofv3 counters, summed over the call's kernels)
-def recon_kernels(head, fused):
+def recon_kernels(head, grad):
     """Kernel names of one reconstruction call (main pass | positivity pass);
-    fused: the main pass also forms the Green-Gauss gradients."""
+    grad: the gradients the main pass also forms (0 none, 1 Green-Gauss,
+    2 least squares)."""
     t, g = ("float", "true") if head == "fp32_gate" else ("double", "false")
-    return (f"reconstruct_kernel<{t}, 9, false, {g}, {'true' if fused else 'false'}>"
-            f"|reconstruct_fallback_kernel<{t}, 9>")
+    return f"reconstruct_kernel<{t}, 9, false, {g}, {grad}>|reconstruct_fallback_kernel<{t}, 9>"
 
 
 
@@ -310,13 +310,14 @@ def main():
         rms, frac = time_recon_replay(solver, U0, args.steps, args.warmup, torch)
         gate = net is not None
         fused = solver.fused
+        grad_mode = (2 if args.gradients == "least_squares" else 1) if fused else 0
         rbc = ((1 - frac) * recon_bytes_per_cell(lm, prec, gate=gate, grad=fused)
                + frac * recon_bytes_per_cell(lm, prec, linear=True, gate=gate, grad=fused))
         variants[name] = {"value": rate, "ms_per_step": ms / args.steps, "wall_s": wall,
                           ("ms_per_step_eager" if args.graph else "ms_per_step_graph"): other_ms / args.steps,
                           "ms_per_step_runs": [r[0] / args.steps for r in per_run],
                           "recon_ms": rms, "recon_bytes_per_cell": rbc, "recon_GBs": rbc * nc / (rms / 1e3) / 1e9,
-                          "fused_gradients": fused,
+                          "fused_gradients": fused, "grad_mode": grad_mode,
                           "step_bytes_per_cell_stage": step_bytes_per_cell(lm, prec, recon=rbc, fused=fused),
                           "path_GBs": step_bytes_per_cell(lm, prec, recon=rbc, fused=fused) * rate / 1e9}
         if net is not None:
@@ -330,7 +331,7 @@ def main():
     copy_calibration(torch)
     head = "fp32_gate" if "fp32_gate" in variants else "fp64_plain"
     hv = variants[head]
-    kname = recon_kernels(head, hv["fused_gradients"])
+    kname = recon_kernels(head, hv["grad_mode"])
     achieved = hv["recon_GBs"]
     from paper_2609_07387_amd import prof
 

@@ -270,17 +270,18 @@ int ucns_reconstruct(const ucns_mesh* mesh, const ucns_phys* phys, const double*
 int ucns_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc, const double* U,
                    int precision, void* gradW, ucns_stream stream);
 
-/* The reconstruction of ucns_reconstruct and the Green-Gauss gradients of
- * ucns_gradients (phys->grad = UCNS_GRAD_GREEN_GAUSS) of the same U in one
- * pass: each cell forms its gradient after its face-point values, from the
- * face neighbours its central stencil has just read (Sec. 2.2: the viscous
- * terms' cell gradients).  The arguments are those of the two calls, except
- * that the boundary table bc_device is a ucns_bc in DEVICE memory (read by
- * the boundary cells' lanes; NULL: every boundary transmissive) and that
- * there is no label output.  Order 2 only, no label: UCNS_EINVAL for order 3
- * or 4 or a least-squares phys->grad (use the two calls).  The gradients
- * differ from ucns_gradients' by rounding only (each face slot's weight
- * n |S| / (2 |V|) is stored with the mesh). */
+/* The reconstruction of ucns_reconstruct and the gradients of
+ * ucns_gradients (by phys->grad, Green-Gauss or least squares) of the same U
+ * in one pass: each cell forms its gradient after its face-point values,
+ * from the face neighbours its central stencil has just read (Sec. 2.2: the
+ * viscous terms' cell gradients).  The arguments are those of the two calls,
+ * except that the boundary table bc_device is a ucns_bc in DEVICE memory
+ * (read by the boundary cells' lanes; NULL: every boundary transmissive) and
+ * that there is no label output.  Order 2 only: UCNS_EINVAL for order 3 or 4
+ * (use the two calls) or an unknown phys->grad.  The gradients differ from
+ * ucns_gradients' by rounding only (the Green-Gauss weight n |S| / (2 |V|)
+ * of each face slot is stored with the mesh, and a symmetry plane's normal
+ * is taken from it). */
 int ucns_reconstruct_gradients(const ucns_mesh* mesh, const ucns_phys* phys, const ucns_bc* bc_device,
                                const double* U, int precision, const ucns_gate* gate, void* face_state,
                                uint8_t* flags, void* gradW, ucns_stream stream);

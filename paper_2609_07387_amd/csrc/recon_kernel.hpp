@@ -1013,10 +1013,10 @@ __device__ __forceinline__ bool recon_cell(const ReconArgs<T>& A, int64_t c, con
 // imposes.
 //
 // A cell whose point states violate positivity is marked with bit 7 of its
-// flag for the fallback pass.  GRAD: the cell then forms its Green-Gauss
-// gradient of W as well (the positivity fallback changes point states only,
-// never the cell averages the gradient is taken from).
-template <class T, int K, bool LABEL, bool GATE, bool GRAD = false>
+// flag for the fallback pass.  GRAD (1 Green-Gauss, 2 least squares): the
+// cell then forms its gradient of W as well (the positivity fallback changes
+// point states only, never the cell averages the gradient is taken from).
+template <class T, int K, bool LABEL, bool GATE, int GRAD = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     K == 9 && (sizeof(T) == 4 ? GATE : !GATE && !LABEL) ? (sizeof(T) == 4 ? 3 : 2) : 1)))
 void reconstruct_kernel(ReconArgs<T> A) {
@@ -1083,7 +1083,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
         // the network's LDS row is free again: it stages the point states
         const bool ok = face_values<T, K, true>(A, c, ui, 0, a, reinterpret_cast<T*>(wl));
         A.flags[c] = uint8_t((mode == 0 ? 1 : 0) | (ok ? 0 : 0x80));
-        if constexpr (GRAD) cell_gradient_gg<T>(A, c, ui);
+        if constexpr (GRAD != 0) cell_gradient<T, GRAD == 2>(A, c, ui);
     } else {
         __shared__ T stage[kBlock / 64][stage_points<K>() * 320];
         if (!valid) return;
@@ -1094,7 +1094,7 @@ void reconstruct_kernel(ReconArgs<T> A) {
         const bool ok = recon_cell<T, K, LABEL, true>(A, c, ui, 1, lab, a, stage[threadIdx.x >> 6]);
         A.flags[c] = uint8_t(ok ? 0 : 0x80);
         if constexpr (LABEL) A.label[c] = lab;
-        if constexpr (GRAD) cell_gradient_gg<T>(A, c, ui);
+        if constexpr (GRAD != 0) cell_gradient<T, GRAD == 2>(A, c, ui);
     }
 }
 

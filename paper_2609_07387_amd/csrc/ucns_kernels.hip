@@ -117,12 +117,13 @@ struct ReconArgs {
     // the boundary table in device memory (null: every boundary transmissive)
     T* gradW;
     const T* ggw;
+    const T* glsq;
     const ucns_bc* bcd;
     T gM2;
 };
 
-template <class T>
-__device__ void cell_gradient_gg(const ReconArgs<T>& A, int64_t c, const double* ui);
+template <class T, bool LSQ>
+__device__ void cell_gradient(const ReconArgs<T>& A, int64_t c, const double* ui);
 
 __device__ __forceinline__ int tri_index(int K, int k, int l) { return k * K - (k * (k - 1)) / 2 + (l - k); }
 
@@ -412,13 +413,15 @@ __device__ __forceinline__ void ghost_dev(const ucns_bc* bc, int tag, const T* i
     out[4] = dir ? st[4] : in[4];
 }
 
-// Green-Gauss gradient of one cell at the end of its reconstruction (the
-// sum of gradients_kernel<T, false>, each slot's outward n |S| / (2 |V|)
-// stored with the mesh; a boundary slot's neighbour entry is its face's
-// negative tag, an absent slot's weights are zero).  The neighbours' states
-// were gathered by the cell's central stencil a moment earlier.
-template <class T>
-__device__ void cell_gradient_gg(const ReconArgs<T>& A, int64_t c, const double* ui) {
+// Gradient of W of one cell at the end of its reconstruction, the sums of
+// gradients_kernel: Green-Gauss (LSQ false) sum_slots (W_i + W_j) w_slot with
+// each slot's outward n |S| / (2 |V|) stored with the mesh, or least squares
+// (LSQ true) sum_slots (W_j - W_i) G_slot with the fit's weights.  A
+// boundary slot's neighbour entry is its face's negative tag (the ghost state
+// enters), an absent slot's weights are zero.  The neighbours' states were
+// gathered by the cell's central stencil a moment earlier.
+template <class T, bool LSQ>
+__device__ void cell_gradient(const ReconArgs<T>& A, int64_t c, const double* ui) {
     const int64_t nc = A.nc;
     // W of a state, as prim_W forms it
     auto primw = [&](const T* q, T* W) {
@@ -446,7 +449,7 @@ __device__ void cell_gradient_gg(const ReconArgs<T>& A, int64_t c, const double*
         jn[lf] = have ? j : -1;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const T x = A.ggw[(3 * r + a) * nc + c];
+            const T x = (LSQ ? A.glsq : A.ggw)[(3 * r + a) * nc + c];
             w[lf][a] = have ? x : T(0);
         }
     }
@@ -460,17 +463,22 @@ __device__ void cell_gradient_gg(const ReconArgs<T>& A, int64_t c, const double*
 #pragma unroll
     for (int lf = 0; lf < kMaxFaces; ++lf) {
         if (jn[lf] < 0) {
-            // the symmetry ghost needs the unit normal: either orientation
-            const T wn = sqrt(w[lf][0] * w[lf][0] + w[lf][1] * w[lf][1] + w[lf][2] * w[lf][2]);
+            // the symmetry ghost needs the unit normal (either orientation):
+            // the direction of the slot's Green-Gauss weight (boundary lanes
+            // only read it for the least-squares sum)
+            T gw[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gw[a] = LSQ ? (lf < A.NF ? A.ggw[int64_t(3 * lf + a) * nc + c] : T(0)) : w[lf][a];
+            const T wn = sqrt(gw[0] * gw[0] + gw[1] * gw[1] + gw[2] * gw[2]);
             const T iw = wn > T(0) ? T(1) / wn : T(0);
-            const T nb[3] = {w[lf][0] * iw, w[lf][1] * iw, w[lf][2] * iw};
+            const T nb[3] = {gw[0] * iw, gw[1] * iw, gw[2] * iw};
             ghost_dev(A.bcd, -1 - jn[lf], u, nb, uo[lf]);
         }
         T Wo[4];
         primw(uo[lf], Wo);
 #pragma unroll
         for (int var = 0; var < 4; ++var) {
-            const T s2 = Wi[var] + Wo[var];
+            const T s2 = LSQ ? Wo[var] - Wi[var] : Wi[var] + Wo[var];
 #pragma unroll
             for (int a = 0; a < 3; ++a) g[3 * var + a] += s2 * w[lf][a];
         }
@@ -1011,6 +1019,7 @@ ReconArgs<T> make_recon_args(const Mesh& m, const Arena& ar, double gm1, const d
     A.gm1 = T(gm1);
     A.gradW = static_cast<T*>(gradW);
     A.ggw = arena_ptr<T>(ar, ar.ggw);
+    A.glsq = arena_ptr<T>(ar, ar.glsq);
     A.bcd = bc_device;
     A.gM2 = phys ? T(phys->gamma * phys->mach * phys->mach) : T(0);
     return A;
@@ -1032,19 +1041,25 @@ void launch_gradients(const Mesh& m, const Arena& ar, const ucns_phys* phys, con
 }
 
 template <class T, int K>
-int launch_recon_k(const ReconArgs<T>& A, hipStream_t st) {
+int launch_recon_k(const ReconArgs<T>& A, hipStream_t st, bool grad_lsq = false) {
     if (A.Q > face_qmax<K>()) return UCNS_EINVAL;
     if (recon_span_bytes(A.nc, int(sizeof(T)), K, A.NF) > kMaxDescriptorBytes) return UCNS_EINVAL;
     const dim3 grid(grid_for(A.nc)), block(kBlock);
     if (A.gradW) {
-        // the fused Green-Gauss gradients: P2 only (the P3 kernels have no
-        // scalar registers to spare for the extra arguments)
+        // the fused gradients (grad_lsq: least squares, else Green-Gauss): P2
+        // only (the P3 kernels have no scalar registers to spare for the
+        // extra arguments)
         if constexpr (K == 9) {
             if (A.label) return UCNS_EINVAL;
-            if (A.mlp || A.gate)
-                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true, true>), grid, block, 0, st, A);
+            const bool gate = A.mlp || A.gate;
+            if (grad_lsq && gate)
+                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true, 2>), grid, block, 0, st, A);
+            else if (grad_lsq)
+                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, false, 2>), grid, block, 0, st, A);
+            else if (gate)
+                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, true, 1>), grid, block, 0, st, A);
             else
-                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, false, true>), grid, block, 0, st, A);
+                hipLaunchKernelGGL((reconstruct_kernel<T, K, false, false, 1>), grid, block, 0, st, A);
         } else {
             return UCNS_EINVAL;
         }
@@ -1077,15 +1092,16 @@ int launch_recon_p4(const ReconArgs<T>& A, hipStream_t st) {
     return UCNS_OK;
 }
 
-// gradW (optional, P2): the Green-Gauss gradients of U as well, formed by
+// gradW (optional, P2): the gradients of U by phys->grad as well, formed by
 // the reconstruction kernel at the end of each cell.
 template <class T>
 int launch_recon(const Mesh& m, const Arena& ar, double gm1, const double* U, const ucns_gate* gate, void* fs,
                  uint8_t* flags, float* label, hipStream_t st, void* gradW = nullptr, const ucns_phys* phys = nullptr,
                  const ucns_bc* bc_device = nullptr) {
     const ReconArgs<T> A = make_recon_args<T>(m, ar, gm1, U, gate, fs, flags, label, gradW, phys, bc_device);
-    if (m.K == 9) return launch_recon_k<T, 9>(A, st);
-    if (m.K == 19) return launch_recon_k<T, 19>(A, st);
+    const bool lsq = phys && phys->grad == UCNS_GRAD_LSQ;
+    if (m.K == 9) return launch_recon_k<T, 9>(A, st, lsq);
+    if (m.K == 19) return launch_recon_k<T, 19>(A, st, lsq);
     if (m.K == kP4K && !gradW) return launch_recon_p4<T>(A, st);
     return UCNS_EINVAL;
 }
@@ -1364,8 +1380,8 @@ int ucns_reconstruct_gradients(const ucns_mesh* mesh, const ucns_phys* phys, con
                                const double* U, int precision, const ucns_gate* gate, void* face_state,
                                uint8_t* flags, void* gradW, ucns_stream stream) {
     UCNS_REQUIRE(mesh && phys && gradW, UCNS_EINVAL, "null argument");
-    UCNS_REQUIRE(phys->grad == UCNS_GRAD_GREEN_GAUSS, UCNS_EINVAL,
-                 "the fused pass forms Green-Gauss gradients; least squares: ucns_gradients");
+    UCNS_REQUIRE(phys->grad == UCNS_GRAD_GREEN_GAUSS || phys->grad == UCNS_GRAD_LSQ, UCNS_EINVAL,
+                 "bad gradient method");
     UCNS_REQUIRE(mesh->m->order == 2, UCNS_EINVAL, "the fused pass covers order 2; orders 3 and 4: ucns_gradients");
     UCNS_REQUIRE(aligned(gradW), UCNS_EINVAL, "device buffers must be 256-byte aligned");
     return reconstruct_impl(mesh, phys, bc_device, U, precision, gate, face_state, flags, nullptr, gradW, stream,

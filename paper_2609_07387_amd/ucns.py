@@ -330,8 +330,8 @@ def bc_device(bcs, device="cuda"):
 
 def reconstruct_gradients(mesh, ph, bc_dev, U, precision, face_state, flags, gradW, gate_mask=None, mlp_image=None,
                           mask_out=None, stream=None):
-    """reconstruct() and the Green-Gauss gradients() of the same U in one
-    pass (order 2); bc_dev from bc_device()."""
+    """reconstruct() and the gradients() of the same U in one pass (order 2,
+    either gradient method); bc_dev from bc_device()."""
     g = None
     if gate_mask is not None or mlp_image is not None:
         g = Gate(None if gate_mask is None else C.c_void_p(gate_mask.data_ptr()),
@@ -446,10 +446,9 @@ class Solver:
         self.integrator = integrator
         self.W = (torch.empty((4, 5, mesh.n_cell), dtype=torch.float64, device=device)
                   if integrator == "ssp54" else None)
-        # viscous P2 with Green-Gauss gradients: one pass forms the point
-        # states and the gradients (the boundary table then lives on the device)
-        self.fused = (bool(ph.viscous) and ph.grad == GRADIENTS["green_gauss"] and mesh.order == 2
-                      and not label)
+        # viscous P2: one pass forms the point states and the gradients (the
+        # boundary table then lives on the device)
+        self.fused = bool(ph.viscous) and mesh.order == 2 and not label
         self.bc_dev = bc_device(bcs, device) if self.fused else None
         # a list here collects, for every reconstruction call, a (start, end)
         # HIP-event pair recorded on the launch stream and, with the network,

@@ -154,11 +154,13 @@ def test_stage_intermediates_fp64(torch_cuda, name):
     assert err_R < (tol / 10 if name in TOL_CASE else 1e-13), err_R
 
 
-@pytest.mark.parametrize("name", ["hex7_p2_hllc_ns", "mixed_bl_ns", "tet_slab_sym_ns"])
+@pytest.mark.parametrize("name", ["hex7_p2_hllc_ns", "mixed_bl_ns", "tet_slab_sym_ns", "tet4_p2_hllc_ns_lsq",
+                                  "mixed_bl_ns_lsq", "tet_slab_sym_ns_lsq"])
 def test_fused_gradients_fp64(torch_cuda, name):
-    """The one-pass reconstruction + Green-Gauss gradients: point states and
-    flags bitwise those of the two separate calls, gradients within rounding
-    of theirs (each slot's weight n|S|/(2|V|) is stored, not formed) and
+    """The one-pass reconstruction + gradients (Green-Gauss or least squares):
+    point states and flags bitwise those of the two separate calls, gradients
+    within rounding of theirs (Green-Gauss: each slot's weight n|S|/(2|V|)
+    is stored, not formed; symmetry ghosts take the normal from it) and
     within the stage tolerance of the oracle; no-slip wall, Dirichlet,
     transmissive and symmetry ghosts among the cases."""
     print(f"[gpu] fused gradients {name}", flush=True)

@@ -191,13 +191,12 @@ def test_entry_points_reject_null_arguments():
     assert "gradient method" in L.ucns_last_error().decode()
     G = np.zeros((6, 3))
     assert L.ucns_mesh_gradient_weights(lm.h, lm.n_cell, G.ctypes.data_as(C.c_void_p)) == -1
-    # the fused reconstruction + gradients pass: Green-Gauss at order 2 only
+    # the fused reconstruction + gradients pass: order 2 only, a known method
     ns = ucns.phys(flux="hllc", viscous=True)
     assert L.ucns_reconstruct_gradients(lm.h, C.byref(ns), None, None, ucns.F64, None, None, None, None, None) == -1
-    lsq = ucns.phys(flux="hllc", viscous=True, gradients="least_squares")
-    assert L.ucns_reconstruct_gradients(lm.h, C.byref(lsq), None, aligned, ucns.F64, None, aligned, aligned, aligned,
+    assert L.ucns_reconstruct_gradients(lm.h, C.byref(bad), None, aligned, ucns.F64, None, aligned, aligned, aligned,
                                         None) == -1
-    assert "least squares" in L.ucns_last_error().decode()
+    assert "gradient method" in L.ucns_last_error().decode()
     lm3 = ucns.Mesh(inputs.periodic_hex_mesh(4), order=3)
     assert L.ucns_reconstruct_gradients(lm3.h, C.byref(ns), None, aligned, ucns.F64, None, aligned, aligned, aligned,
                                         None) == -1
