@@ -249,7 +249,7 @@ def main():
         return _cpu_baseline_child(sys.argv[2], int(sys.argv[3]))
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     if args.workload in ("tgv_tet_p3", "tgv_hex_p4"):

@@ -104,7 +104,7 @@ def test_benchmark_table_counts():
         if ctype == "hex":
             assert row["faces"] * nq == pytest.approx(row["face_qps"], rel=1e-12)
         else:
-            # The paper's triangle faces carry 6 points at P3; this build's
+            # The paper's triangle faces carry 6 points at P3; the library's
             # tetrahedral workloads use the 3-point rule instead.
             assert row["face_qps"] / row["faces"] == 6 and nq == 3
 
