@@ -179,18 +179,23 @@ def test_fused_gradients_fp64(torch_cuda, name):
     assert err_o < TOL_CASE.get(name, TOL_STAGE), err_o
 
 
-def test_fused_gradients_fp32_gate(torch_cuda):
+@pytest.mark.parametrize("name", ["hex12_tgv", "mixed_bl_ns", "mixed_bl_ns_lsq"])
+def test_fused_gradients_fp32_gate(torch_cuda, name):
     """FP32 with a gate mask (every third cell troubled): the one-pass call's
     point states and flags equal the separate calls' bit for bit, its
-    gradients agree to FP32 rounding."""
-    print("[gpu] fused gradients fp32 gate", flush=True)
-    m = inputs.periodic_hex_mesh(12)
-    U = inputs.tgv_initial(m)
-    ph = ucns.phys(flux="hllc", viscous=True)
+    gradients agree to FP32 rounding (on the mixed mesh with its wall,
+    inflow, outflow and far-field ghosts, both gradient methods)."""
+    print(f"[gpu] fused gradients fp32 gate {name}", flush=True)
+    if name == "hex12_tgv":
+        m = inputs.periodic_hex_mesh(12)
+        U = inputs.tgv_initial(m)
+        ph, bcs = ucns.phys(flux="hllc", viscous=True), None
+    else:
+        m, _, ph, U, bcs = _setup(name)
     lm = ucns.Mesh(m, order=2)
     mask = (np.arange(lm.n_cell) % 3 != 0).astype(np.uint8)
-    fs, gw, _, _, flags = gpu_stage(lm, ph, U, ucns.F32, None, gate_mask=mask)
-    fs2, gw2, _, _, flags2 = gpu_stage(lm, ph, U, ucns.F32, None, gate_mask=mask, fused=True)
+    fs, gw, _, _, flags = gpu_stage(lm, ph, U, ucns.F32, bcs, gate_mask=mask)
+    fs2, gw2, _, _, flags2 = gpu_stage(lm, ph, U, ucns.F32, bcs, gate_mask=mask, fused=True)
     assert np.array_equal(fs, fs2, equal_nan=True)
     assert np.array_equal(flags, flags2)
     err = np.abs(gw2 - gw).max() / np.abs(gw).max()
